@@ -1,0 +1,218 @@
+/*
+ * tpf_oracle.c -- plain FP64 CPU oracle of the batched fixed-point power flow.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes or
+ * calls this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark load it.  It shares no code, header, table or helper with the
+ * GPU path.
+ *
+ * Paper: J. S. Giraldo / E. Salazar Duque et al., "Tensor Power Flow Formulations
+ * for Multidimensional Analyses in Distribution Systems" (arXiv 2403.04578).
+ *
+ * What it computes, each step written out plainly in double complex arithmetic
+ * (compiled with -ffp-contract=off, no BLAS, no blocking, no fusion):
+ *   oracle_build     Sec. II Eq. (1): nodal admittance Y from the branch list,
+ *                    partition into slack (s) and demand (d) blocks; Eq. (2) with
+ *                    constant-power loads (alpha_P = 1, alpha_Z = alpha_I = 0):
+ *                    B = Y_dd, F = -B^-1 diag(s*), w = -B^-1 Y_ds v_s.  We keep
+ *                    Z = -Y_dd^-1 (Algorithm 1's Z_B with the sign Eq. (2) needs).
+ *   oracle_fpi       Algorithm 1 (dense tensor power flow) applied column by
+ *                    column: flat start 1 + j0, update V <- Z conj(S ./ V) + w,
+ *                    stop when max_i |V'_i - V_i| < tol or after max_iter sweeps.
+ *   oracle_mismatch  Power balance of Eq. (1): m = S + V .* conj(Y_ds v_s + Y_dd V),
+ *                    reported as max_i |m_i| per column.
+ *
+ * Readings where the paper is silent or garbled (listed in the design notes):
+ *   - the stopping measure is the complex modulus of the voltage step,
+ *     per column, not squared, with a strict test d < tol;
+ *   - a column whose iterate becomes non-finite stops with status NONFINITE;
+ *   - max_iter = 0 returns the start voltages with status MAX_ITER.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_ERR_INVALID -1
+#define OR_ERR_SINGULAR -2
+#define OR_ERR_OOM -4
+
+#define ST_CONVERGED 0
+#define ST_MAX_ITER 1
+#define ST_NONFINITE 2
+
+/* Sec. II Eq. (1) and Eq. (2).  Outputs (caller-allocated, interleaved re/im):
+ *   Ydd [n*n], Yds [n], Z [n*n] = -Y_dd^-1, w [n] = -Y_dd^-1 Y_ds v_s,
+ * with n = n_bus - 1 and PQ bus order = ascending bus index, slack removed. */
+int oracle_build(int n_bus, int n_branch, const int32_t *frm, const int32_t *to,
+                 const double *r, const double *x, int slack, double vs_re,
+                 double vs_im, double complex *Ydd, double complex *Yds,
+                 double complex *Z, double complex *w)
+{
+    if (n_bus < 2 || n_branch < 1 || slack < 0 || slack >= n_bus)
+        return OR_ERR_INVALID;
+    const int n = n_bus - 1;
+    double complex *Y = calloc((size_t)n_bus * n_bus, sizeof(double complex));
+    double complex *M = calloc((size_t)n * 2 * n, sizeof(double complex));
+    int *pq = malloc(sizeof(int) * n);
+    if (!Y || !M || !pq) {
+        free(Y); free(M); free(pq);
+        return OR_ERR_OOM;
+    }
+    int rc = OR_OK;
+    /* Eq. (1): series branch admittance y = 1/(r + jx) stamped into Y. */
+    for (int k = 0; k < n_branch; ++k) {
+        int f = frm[k], t = to[k];
+        if (f < 0 || f >= n_bus || t < 0 || t >= n_bus || f == t ||
+            !isfinite(r[k]) || !isfinite(x[k]) || (r[k] == 0.0 && x[k] == 0.0)) {
+            rc = OR_ERR_INVALID;
+            goto done;
+        }
+        double complex y = 1.0 / (r[k] + I * x[k]);
+        Y[(size_t)f * n_bus + f] += y;
+        Y[(size_t)t * n_bus + t] += y;
+        Y[(size_t)f * n_bus + t] -= y;
+        Y[(size_t)t * n_bus + f] -= y;
+    }
+    /* Partition: demand nodes are every bus but the slack, ascending. */
+    for (int b = 0, i = 0; b < n_bus; ++b)
+        if (b != slack) pq[i++] = b;
+    for (int i = 0; i < n; ++i) {
+        Yds[i] = Y[(size_t)pq[i] * n_bus + slack];
+        for (int j = 0; j < n; ++j)
+            Ydd[(size_t)i * n + j] = Y[(size_t)pq[i] * n_bus + pq[j]];
+    }
+    /* Y_dd^-1 by Gauss-Jordan elimination with partial pivoting on [Y_dd | 1]. */
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) M[(size_t)i * 2 * n + j] = Ydd[(size_t)i * n + j];
+        M[(size_t)i * 2 * n + n + i] = 1.0;
+    }
+    double scale = 0.0;
+    for (size_t e = 0; e < (size_t)n * n; ++e) scale = fmax(scale, cabs(Ydd[e]));
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        double best = cabs(M[(size_t)c * 2 * n + c]);
+        for (int i = c + 1; i < n; ++i) {
+            double v = cabs(M[(size_t)i * 2 * n + c]);
+            if (v > best) { best = v; p = i; }
+        }
+        if (!(best > 1e-13 * scale)) { rc = OR_ERR_SINGULAR; goto done; }
+        if (p != c)
+            for (int j = 0; j < 2 * n; ++j) {
+                double complex tmp = M[(size_t)c * 2 * n + j];
+                M[(size_t)c * 2 * n + j] = M[(size_t)p * 2 * n + j];
+                M[(size_t)p * 2 * n + j] = tmp;
+            }
+        double complex piv = M[(size_t)c * 2 * n + c];
+        for (int j = 0; j < 2 * n; ++j) M[(size_t)c * 2 * n + j] /= piv;
+        for (int i = 0; i < n; ++i) {
+            if (i == c) continue;
+            double complex f = M[(size_t)i * 2 * n + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 2 * n; ++j)
+                M[(size_t)i * 2 * n + j] -= f * M[(size_t)c * 2 * n + j];
+        }
+    }
+    /* Z = -Y_dd^-1 ; w = -Y_dd^-1 Y_ds v_s = Z (Y_ds v_s). */
+    double complex vs = vs_re + I * vs_im;
+    for (int i = 0; i < n; ++i) {
+        double complex acc = 0.0;
+        for (int j = 0; j < n; ++j) {
+            Z[(size_t)i * n + j] = -M[(size_t)i * 2 * n + n + j];
+            acc += Z[(size_t)i * n + j] * (Yds[j] * vs);
+        }
+        w[i] = acc;
+    }
+done:
+    free(Y); free(M); free(pq);
+    return rc;
+}
+
+/* Algorithm 1, one column at a time (the reshape to tau columns changes no
+ * iterate, Sec. IV-A).  S, V0, V: [tau][n] interleaved complex; V0 may be NULL
+ * (flat start 1 + j0).  Per column: iters (sweeps done), status, and the last
+ * step size d (INFINITY when no sweep ran). */
+void oracle_fpi(int n, const double complex *Z, const double complex *w, int64_t tau,
+                const double complex *S, double tol, int max_iter,
+                const double complex *V0, double complex *V, int32_t *iters,
+                int8_t *status, double *dlast)
+{
+#pragma omp parallel
+    {
+        double complex *cur = malloc(sizeof(double complex) * n);
+        double complex *nxt = malloc(sizeof(double complex) * n);
+        double complex *cinj = malloc(sizeof(double complex) * n);
+#pragma omp for schedule(static)
+        for (int64_t col = 0; col < tau; ++col) {
+            const double complex *s = S + col * n;
+            for (int i = 0; i < n; ++i) cur[i] = V0 ? V0[col * n + i] : 1.0;
+            double d = INFINITY;
+            int k = 0, bad = 0;
+            while (d >= tol && k < max_iter) {
+                /* current injection conj(S ./ V) */
+                for (int i = 0; i < n; ++i) cinj[i] = conj(s[i] / cur[i]);
+                /* V' = Z I + w */
+                for (int i = 0; i < n; ++i) {
+                    double complex acc = 0.0;
+                    for (int j = 0; j < n; ++j) acc += Z[(size_t)i * n + j] * cinj[j];
+                    nxt[i] = acc + w[i];
+                }
+                d = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    if (!isfinite(creal(nxt[i])) || !isfinite(cimag(nxt[i]))) bad = 1;
+                    double e = cabs(nxt[i] - cur[i]);
+                    if (e > d) d = e;
+                }
+                memcpy(cur, nxt, sizeof(double complex) * n);
+                ++k;
+                if (bad) break;
+            }
+            memcpy(V + col * n, cur, sizeof(double complex) * n);
+            iters[col] = k;
+            status[col] = bad ? ST_NONFINITE : (d < tol ? ST_CONVERGED : ST_MAX_ITER);
+            if (dlast) dlast[col] = bad ? NAN : d;
+        }
+        free(cur); free(nxt); free(cinj);
+    }
+}
+
+/* Power-balance mismatch from Eq. (1): with -i_d = Y_ds v_s + Y_dd v, the power a
+ * load draws is v .* conj(i_d), so m = S + V .* conj(Y_ds v_s + Y_dd V).  Writes
+ * max_i |m_i| per column. */
+void oracle_mismatch(int n, const double complex *Ydd, const double complex *Yds,
+                     double vs_re, double vs_im, int64_t tau, const double complex *S,
+                     const double complex *V, double *mmax)
+{
+    double complex vs = vs_re + I * vs_im;
+#pragma omp parallel for schedule(static)
+    for (int64_t col = 0; col < tau; ++col) {
+        const double complex *v = V + col * n;
+        double worst = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double complex acc = Yds[i] * vs;
+            for (int j = 0; j < n; ++j) acc += Ydd[(size_t)i * n + j] * v[j];
+            double complex m = S[col * n + i] + v[i] * conj(acc);
+            double a = cabs(m);
+            if (!(a <= worst)) worst = a; /* NaN propagates */
+        }
+        mmax[col] = worst;
+    }
+}
+
+int oracle_num_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        {
+#ifdef _OPENMP
+            extern int omp_get_num_threads(void);
+            t = omp_get_num_threads();
+#endif
+        }
+    }
+    return t;
+}
