@@ -1,0 +1,144 @@
+/*
+ * tpf.h -- C ABI of the MI355X batched fixed-point power-flow library (libtpf.so).
+ *
+ * Method: the tensor ("dense") fixed-point power flow of Giraldo, Salazar Duque
+ * et al., "Tensor Power Flow Formulations for Multidimensional Analyses in
+ * Distribution Systems" (arXiv 2403.04578):
+ *   Sec. II Eq. (1)   nodal admittance Y of a network with one slack (substation)
+ *                     node and b demand nodes, partitioned into Y_ss, Y_sd, Y_ds, Y_dd;
+ *   Sec. II Eq. (2)   with constant-power loads the iteration
+ *                     v <- F conj(v)^(-1) + w,  F = -Y_dd^-1 diag(s*),  w = -Y_dd^-1 Y_ds v_s,
+ *                     i.e. V <- Z conj(S ./ V) + w with Z = -Y_dd^-1;
+ *   Sec. IV-A Eq.(12) all power flows (time steps, scenarios, ...) reshaped into the
+ *                     columns of one matrix and iterated together;
+ *   Algorithm 1       flat start 1 + j0, iterate until the voltage step falls
+ *                     below a tolerance or an iteration cap is reached.
+ *
+ * Conventions shared by every call
+ *   - Per unit throughout.  S > 0 is consumption (Eq. (1) writes -i_d), so a PV
+ *     injection is a negative S.
+ *   - PQ order: column/bus index q of S and V is the q-th non-slack bus in
+ *     ascending bus number.
+ *   - Complex arrays are interleaved (re, im): dtype TPF_C128 = 2 x double,
+ *     TPF_C64 = 2 x float.  S and V have the same dtype.
+ *   - Arrays named "device" are device pointers on the current HIP device
+ *     (16-byte aligned, contiguous, row-major: [tau][n] or [P][T][n]); arrays
+ *     named "host" are host pointers.  The caller owns every array it passes.
+ *   - Calls that take a stream are stream-ordered and asynchronous: the return
+ *     code reports argument and launch errors only.  Non-convergence is data
+ *     (status_out), never an error code.
+ *   - On error a call returns a negative TPF_ERR_* code and tpf_last_error()
+ *     (thread-local) describes it; outputs are then unspecified.
+ */
+#ifndef TPF_H_
+#define TPF_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tpf_network_s *tpf_network; /* opaque; immutable after build */
+
+enum {
+    TPF_OK = 0,
+    TPF_ERR_INVALID_ARG = -1, /* bad sizes, indices, pointers, tolerances */
+    TPF_ERR_SINGULAR = -2,    /* Y_dd not invertible (e.g. a bus not connected to the slack) */
+    TPF_ERR_DEVICE = -3,      /* HIP runtime error */
+    TPF_ERR_OOM = -4,         /* host or device allocation failed */
+    TPF_ERR_UNSUPPORTED = -5  /* valid request this build does not implement */
+};
+
+enum { TPF_C64 = 0, TPF_C128 = 1 };
+
+/* Arithmetic of the sweeps.
+ *   FP64        every sweep in FP64 (MFMA FP64), state in FP64;
+ *   FP32        every sweep in FP32 (MFMA FP32), state kept as FP32 drop V - w;
+ *   MIXED_BF16  low-precision sweeps on BF16 MFMA (FP32 accumulation) refined by
+ *   MIXED_FP16  FP32 sweeps; convergence is only declared on a refined iterate.
+ *   In FP32 and mixed modes tol must be >= 5e-7 pu (the FP32 state floor). */
+enum { TPF_MODE_FP64 = 0, TPF_MODE_FP32 = 1, TPF_MODE_MIXED_BF16 = 2, TPF_MODE_MIXED_FP16 = 3 };
+
+/* Per-column outcome written to status_out. */
+enum { TPF_ST_CONVERGED = 0, TPF_ST_MAX_ITER = 1, TPF_ST_NONFINITE = 2 };
+
+typedef struct {
+    int32_t mode;          /* TPF_MODE_*; default TPF_MODE_FP64 */
+    int32_t reserved0;
+    const void *V0;        /* device [tau][n] start voltages (same dtype as S), or NULL for the
+                              flat start 1 + j0 of Algorithm 1.  A column whose V0 holds a
+                              non-finite value or a modulus outside [0.5, 1.5] pu starts flat. */
+    double *mismatch_out;  /* device [tau] float64, or NULL: per-column max |S + V.*conj(Y_ds v_s +
+                              Y_dd V)| of the returned V, computed in FP64 (Eq. (1) balance). */
+    double reserved1[4];
+} tpf_options;
+
+/* Sec. II Eq. (1)-(2): build the network from its branch list.
+ *   n_bus            number of buses including the slack (>= 2)
+ *   n_branch         number of series branches (>= 1)
+ *   from, to         host int32 [n_branch], bus numbers in [0, n_bus), from != to
+ *   r, x             host float64 [n_branch], branch impedance r + jx pu, finite, not both 0
+ *   slack_bus        the slack bus number
+ *   vs_re, vs_im     slack voltage v_s
+ *   out              receives the handle (library-owned; free with tpf_free_network)
+ * Assembles Y (parallel branches add up; meshed networks allowed), partitions it,
+ * factorises Y_dd in FP64 (LU, partial pivoting) and forms Z = -Y_dd^-1 and
+ * w = -Y_dd^-1 Y_ds v_s.  Host work only; device copies are made on first use on
+ * each device.  Errors: TPF_ERR_INVALID_ARG, TPF_ERR_SINGULAR (a bus unreachable
+ * from the slack, or a numerically singular Y_dd), TPF_ERR_OOM. */
+int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                      const double *r, const double *x, int32_t slack_bus, double vs_re,
+                      double vs_im, tpf_network *out);
+
+void tpf_free_network(tpf_network net);
+
+/* Number of PQ (demand) buses n = n_bus - 1. */
+int tpf_network_n_pq(tpf_network net);
+
+/* Copies Z = -Y_dd^-1 (host float64 [n][n][2]) and w (host float64 [n][2]) out of the
+ * handle.  Either pointer may be NULL. */
+int tpf_network_get_zw(tpf_network net, double *Z_out, double *w_out);
+
+/* Bytes of device workspace that tpf_solve_* needs for tau columns with these
+ * options (opts may be NULL).  The solve calls allocate nothing themselves. */
+size_t tpf_workspace_bytes(tpf_network net, int64_t tau, const tpf_options *opts);
+
+/* Algorithm 1 over a [T][n] load matrix (Sec. IV-A: each time step is a column).
+ *   S            device [T][n] complex loads, dtype TPF_C64 or TPF_C128
+ *   T            number of power flows (>= 0)
+ *   tol          stop a column once max_i |V'_i - V_i| < tol (pu); tol >= 0
+ *   max_iter     sweep cap per column (>= 0); 0 returns the start voltages
+ *   opts         may be NULL (FP64, flat start, no mismatch)
+ *   V_out        device [T][n] complex, same dtype as S
+ *   iters_out    device int32 [T]: sweeps done per column
+ *   status_out   device int8  [T]: TPF_ST_*
+ *   workspace    device, >= tpf_workspace_bytes(net, T, opts) bytes, 256-byte aligned
+ *   stream       hipStream_t (NULL = default stream) */
+int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtype, int64_t T, double tol,
+                         int32_t max_iter, const tpf_options *opts, void *V_out,
+                         int32_t *iters_out, int8_t *status_out, void *workspace,
+                         size_t workspace_bytes, void *stream);
+
+/* Same over a [P][T][n] tensor (Sec. IV-A Eq. (12): any leading dimensions collapse into
+ * tau = P*T columns without changing any iterate).  Arrays are [P][T][n], [P][T]. */
+int tpf_solve_tensor(tpf_network net, const void *S, int32_t dtype, int64_t n_scen, int64_t T,
+                     double tol, int32_t max_iter, const tpf_options *opts, void *V_out,
+                     int32_t *iters_out, int8_t *status_out, void *workspace,
+                     size_t workspace_bytes, void *stream);
+
+/* FP64 power-balance mismatch of given voltages (Eq. (1)):
+ * out[c] = max_i |S_ci + V_ci conj((Y_ds v_s)_i + (Y_dd V_c)_i)|.
+ *   S, V   device [tau][n], dtype TPF_C64 or TPF_C128;  out  device float64 [tau]. */
+int tpf_mismatch(tpf_network net, const void *S, const void *V, int32_t dtype, int64_t tau,
+                 double *out, void *stream);
+
+/* Description of the last error on this thread ("" if none). */
+const char *tpf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TPF_H_ */

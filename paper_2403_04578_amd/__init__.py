@@ -1,0 +1,240 @@
+"""MI355X batched fixed-point power flow (tensor power flow, arXiv 2403.04578).
+
+Thin Python binding over ``libtpf.so``: it only marshals arguments.  Every step
+of the solve runs in the library's HIP kernels; PyTorch supplies device memory
+and the current stream.  There is no CPU fallback: if the library is missing the
+import of a solve fails with an error that says how to build it.
+
+    net = Network.from_feeder(workloads.make_feeder(100))
+    V, iters, status = solve_timeseries(net, S_cuda, tol=1e-6, max_iter=100)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtpf.so")
+
+TPF_OK = 0
+TPF_ERR_INVALID_ARG = -1
+TPF_ERR_SINGULAR = -2
+TPF_ERR_DEVICE = -3
+TPF_ERR_OOM = -4
+TPF_ERR_UNSUPPORTED = -5
+
+TPF_C64, TPF_C128 = 0, 1
+MODE_FP64, MODE_FP32, MODE_MIXED_BF16, MODE_MIXED_FP16 = 0, 1, 2, 3
+ST_CONVERGED, ST_MAX_ITER, ST_NONFINITE = 0, 1, 2
+
+_MODES = {"fp64": MODE_FP64, "fp32": MODE_FP32, "mixed_bf16": MODE_MIXED_BF16, "mixed_fp16": MODE_MIXED_FP16}
+
+
+class TpfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"tpf error {code}: {msg}")
+        self.code = code
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("V0", ctypes.c_void_p),
+                ("mismatch_out", ctypes.c_void_p), ("reserved1", ctypes.c_double * 4)]
+
+
+_lib = None
+
+
+def load_library() -> ctypes.CDLL:
+    """Loads libtpf.so (built in-tree by ``python -m paper_2403_04578_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing; build it with `python -m paper_2403_04578_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    sig = {
+        "tpf_build_network": (ctypes.c_int, [I32, I32, P, P, P, P, I32, D, D, ctypes.POINTER(P)]),
+        "tpf_free_network": (None, [P]),
+        "tpf_network_n_pq": (ctypes.c_int, [P]),
+        "tpf_network_get_zw": (ctypes.c_int, [P, P, P]),
+        "tpf_workspace_bytes": (ctypes.c_size_t, [P, I64, P]),
+        "tpf_solve_timeseries": (ctypes.c_int, [P, P, I32, I64, D, I32, P, P, P, P, P, ctypes.c_size_t, P]),
+        "tpf_solve_tensor": (ctypes.c_int, [P, P, I32, I64, I64, D, I32, P, P, P, P, P, ctypes.c_size_t, P]),
+        "tpf_mismatch": (ctypes.c_int, [P, P, P, I32, I64, P, P]),
+        "tpf_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != TPF_OK:
+        raise TpfError(rc, load_library().tpf_last_error().decode())
+
+
+class Network:
+    """A feeder prepared for the sweeps: Z = -Y_dd^-1 and w (Sec. II Eqs. (1)-(2))."""
+
+    def __init__(self, n_bus: int, frm, to, r, x, slack: int = 0, vs: complex = 1.0 + 0.0j):
+        lib = load_library()
+        self._keep = [np.ascontiguousarray(frm, np.int32), np.ascontiguousarray(to, np.int32),
+                      np.ascontiguousarray(r, np.float64), np.ascontiguousarray(x, np.float64)]
+        h = ctypes.c_void_p()
+        f, t, rr, xx = self._keep
+        if not (len(f) == len(t) == len(rr) == len(xx)):
+            raise ValueError("branch arrays must have equal lengths")
+        rc = lib.tpf_build_network(int(n_bus), len(f), f.ctypes.data, t.ctypes.data, rr.ctypes.data,
+                                   xx.ctypes.data, int(slack), float(np.real(vs)), float(np.imag(vs)),
+                                   ctypes.byref(h))
+        _check(rc)
+        self._h = h
+        self.n_bus = int(n_bus)
+        self.n = lib.tpf_network_n_pq(h)
+
+    @classmethod
+    def from_feeder(cls, feeder) -> "Network":
+        return cls(feeder.n_bus, feeder.frm, feeder.to, feeder.r, feeder.x, 0, feeder.vs)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def zw(self):
+        """(Z, w) as complex128 numpy arrays, copied out of the handle."""
+        Z = np.empty((self.n, self.n), np.complex128)
+        w = np.empty(self.n, np.complex128)
+        _check(load_library().tpf_network_get_zw(self._h, Z.ctypes.data, w.ctypes.data))
+        return Z, w
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tpf_free_network(h)
+            self._h = None
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return TPF_C128
+    if t.dtype == torch.complex64:
+        return TPF_C64
+    raise TypeError("S must be complex64 or complex128")
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def workspace_bytes(net: Network, tau: int, mode: int = MODE_FP64) -> int:
+    o = _Options(mode=mode)
+    return int(load_library().tpf_workspace_bytes(net.handle, int(tau), ctypes.byref(o)))
+
+
+def solve_timeseries(net: Network, S, tol: float, max_iter: int, mode="fp64", V0=None,
+                     mismatch: bool = False, out=None):
+    """Algorithm 1 over S [T, n] (CUDA complex tensor).  Returns (V, iters, status[, mismatch]).
+
+    ``mode``: "fp64" | "fp32" | "mixed_bf16" | "mixed_fp16" (or the MODE_* ints).
+    ``V0``: optional start voltages [T, n] (same dtype); guarded columns fall back to flat.
+    """
+    return _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor=False)
+
+
+def solve_tensor(net: Network, S, tol: float, max_iter: int, mode="fp64", V0=None,
+                 mismatch: bool = False, out=None):
+    """Algorithm 1 over S [P, T, n]; outputs shaped [P, T, n], [P, T]."""
+    return _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor=True)
+
+
+def _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor):
+    torch = _torch()
+    lib = load_library()
+    if not S.is_cuda:
+        raise ValueError("S must be a device tensor")
+    if not S.is_contiguous():
+        raise ValueError("S must be contiguous")
+    mode_i = _MODES[mode] if isinstance(mode, str) else int(mode)
+    dt = _dtype_code(S)
+    if tensor:
+        if S.dim() != 3 or S.shape[2] != net.n:
+            raise ValueError(f"S must be [P, T, {net.n}]")
+        lead = tuple(S.shape[:2])
+    else:
+        if S.dim() != 2 or S.shape[1] != net.n:
+            raise ValueError(f"S must be [T, {net.n}]")
+        lead = (S.shape[0],)
+    tau = int(np.prod(lead)) if lead else 0
+    dev = S.device
+    if out is None:
+        V = torch.empty_like(S)
+        iters = torch.empty(lead, dtype=torch.int32, device=dev)
+        status = torch.empty(lead, dtype=torch.int8, device=dev)
+        mm = torch.empty(lead, dtype=torch.float64, device=dev) if mismatch else None
+        ws = torch.empty(max(workspace_bytes(net, tau, mode_i), 256), dtype=torch.uint8, device=dev)
+    else:
+        V, iters, status, mm, ws = out
+    opts = _Options(mode=mode_i)
+    if V0 is not None:
+        if V0.shape != S.shape or V0.dtype != S.dtype or not V0.is_contiguous() or V0.device != dev:
+            raise ValueError("V0 must match S in shape, dtype and device and be contiguous")
+        opts.V0 = V0.data_ptr()
+    if mismatch:
+        opts.mismatch_out = mm.data_ptr()
+    with torch.cuda.device(dev):
+        stream = _stream_ptr(dev)
+        if tensor:
+            rc = lib.tpf_solve_tensor(net.handle, S.data_ptr(), dt, lead[0], lead[1], float(tol), int(max_iter),
+                                      ctypes.byref(opts), V.data_ptr(), iters.data_ptr(), status.data_ptr(),
+                                      ws.data_ptr(), ws.numel(), stream)
+        else:
+            rc = lib.tpf_solve_timeseries(net.handle, S.data_ptr(), dt, tau, float(tol), int(max_iter),
+                                          ctypes.byref(opts), V.data_ptr(), iters.data_ptr(), status.data_ptr(),
+                                          ws.data_ptr(), ws.numel(), stream)
+    _check(rc)
+    if mismatch:
+        return V, iters, status, mm
+    return V, iters, status
+
+
+def alloc_outputs(net: Network, S, mode="fp64", mismatch: bool = False, tensor: bool = False):
+    """Pre-allocates (V, iters, status, mismatch, workspace) for repeated solves of S's shape."""
+    torch = _torch()
+    lead = tuple(S.shape[:2]) if tensor else (S.shape[0],)
+    tau = int(np.prod(lead))
+    mode_i = _MODES[mode] if isinstance(mode, str) else int(mode)
+    dev = S.device
+    return (torch.empty_like(S), torch.empty(lead, dtype=torch.int32, device=dev),
+            torch.empty(lead, dtype=torch.int8, device=dev),
+            torch.empty(lead, dtype=torch.float64, device=dev) if mismatch else None,
+            torch.empty(max(workspace_bytes(net, tau, mode_i), 256), dtype=torch.uint8, device=dev))
+
+
+def mismatch(net: Network, S, V):
+    """FP64 power-balance mismatch per column: max_i |S + V .* conj(Y_ds v_s + Y_dd V)|."""
+    torch = _torch()
+    lib = load_library()
+    if S.shape != V.shape or S.dtype != V.dtype:
+        raise ValueError("S and V must match")
+    lead = tuple(S.shape[:-1])
+    tau = int(np.prod(lead))
+    out = torch.empty(lead, dtype=torch.float64, device=S.device)
+    with torch.cuda.device(S.device):
+        rc = lib.tpf_mismatch(net.handle, S.data_ptr(), V.data_ptr(), _dtype_code(S), tau, out.data_ptr(),
+                              _stream_ptr(S.device))
+    _check(rc)
+    return out

@@ -1,0 +1,102 @@
+// C ABI entry points: argument checks, workspace carving and kernel dispatch.
+#include <cmath>
+
+#include "tpf_internal.h"
+
+using namespace tpf;
+
+namespace {
+
+constexpr size_t kQueueBytes = 256;  // atomic column queue (+ padding to 256 B)
+
+bool valid_dtype(int32_t d) { return d == TPF_C64 || d == TPF_C128; }
+
+int check_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TPF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return TPF_OK;
+}
+
+}  // namespace
+
+extern "C" size_t tpf_workspace_bytes(tpf_network net, int64_t tau, const tpf_options *opts) {
+    (void)net;
+    (void)tau;
+    (void)opts;
+    return kQueueBytes;
+}
+
+extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtype, int64_t T, double tol,
+                                    int32_t max_iter, const tpf_options *opts, void *V_out, int32_t *iters_out,
+                                    int8_t *status_out, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!net) return fail(TPF_ERR_INVALID_ARG, "net is NULL");
+    if (!valid_dtype(dtype)) return fail(TPF_ERR_INVALID_ARG, "dtype must be TPF_C64 or TPF_C128");
+    if (T < 0) return fail(TPF_ERR_INVALID_ARG, "T must be >= 0");
+    if (!(tol >= 0.0)) return fail(TPF_ERR_INVALID_ARG, "tol must be >= 0 (and not NaN)");
+    if (max_iter < 0) return fail(TPF_ERR_INVALID_ARG, "max_iter must be >= 0");
+    const int mode = opts ? opts->mode : TPF_MODE_FP64;
+    if (mode < TPF_MODE_FP64 || mode > TPF_MODE_MIXED_FP16) return fail(TPF_ERR_INVALID_ARG, "unknown mode");
+    if (mode != TPF_MODE_FP64 && tol < 5e-7)
+        return fail(TPF_ERR_INVALID_ARG, "tol below the FP32 state floor (5e-7 pu) in a reduced-precision mode");
+    if (T == 0) return TPF_OK;
+    if (!S || !V_out || !iters_out || !status_out) return fail(TPF_ERR_INVALID_ARG, "array pointer is NULL");
+    const int n = net->n;
+    if (T > (int64_t)1 << 40 || (int64_t)n * T > ((int64_t)1 << 50)) return fail(TPF_ERR_INVALID_ARG, "T too large");
+    if (!workspace || workspace_bytes < tpf_workspace_bytes(net, T, opts))
+        return fail(TPF_ERR_INVALID_ARG, "workspace missing or smaller than tpf_workspace_bytes()");
+    if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(TPF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+    if (mode != TPF_MODE_FP64) return fail(TPF_ERR_UNSUPPORTED, "only TPF_MODE_FP64 is implemented");
+    const void *V0 = opts ? opts->V0 : nullptr;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    DeviceNet *dn = nullptr;
+    int rc = device_net(net, &dn);
+    if (rc != TPF_OK) return rc;
+    if (max_iter == 0) {
+        rc = launch_start_only(n, V0, dtype, T, V_out, iters_out, status_out, st);
+    } else if (n <= 8 * kMaxSmallTiles) {
+        auto *queue = reinterpret_cast<unsigned long long *>(workspace);
+        rc = launch_zero_u64(queue, 1, st);
+        if (rc == TPF_OK) rc = check_launch("queue reset");
+        if (rc == TPF_OK)
+            rc = launch_fpi_small_f64(*net, *dn, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out,
+                                      queue, st);
+    } else {
+        return fail(TPF_ERR_UNSUPPORTED, "networks with more than 128 PQ buses are not implemented yet");
+    }
+    if (rc != TPF_OK) return rc;
+    rc = check_launch("sweep kernel launch");
+    if (rc != TPF_OK) return rc;
+    if (opts && opts->mismatch_out) {
+        rc = launch_mismatch_f64(*net, *dn, S, V_out, dtype, T, opts->mismatch_out, st);
+        if (rc == TPF_OK) rc = check_launch("mismatch kernel launch");
+    }
+    return rc;
+}
+
+extern "C" int tpf_solve_tensor(tpf_network net, const void *S, int32_t dtype, int64_t n_scen, int64_t T, double tol,
+                                int32_t max_iter, const tpf_options *opts, void *V_out, int32_t *iters_out,
+                                int8_t *status_out, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (n_scen < 0 || T < 0) return fail(TPF_ERR_INVALID_ARG, "n_scen and T must be >= 0");
+    if (T > 0 && n_scen > (((int64_t)1 << 40) / T)) return fail(TPF_ERR_INVALID_ARG, "n_scen * T too large");
+    // Sec. IV-A: [P][T][n] is contiguous-reshaped to [P*T][n]; no iterate changes.
+    return tpf_solve_timeseries(net, S, dtype, n_scen * T, tol, max_iter, opts, V_out, iters_out, status_out,
+                                workspace, workspace_bytes, stream);
+}
+
+extern "C" int tpf_mismatch(tpf_network net, const void *S, const void *V, int32_t dtype, int64_t tau, double *out,
+                            void *stream) {
+    clear_error();
+    if (!net) return fail(TPF_ERR_INVALID_ARG, "net is NULL");
+    if (!valid_dtype(dtype)) return fail(TPF_ERR_INVALID_ARG, "dtype must be TPF_C64 or TPF_C128");
+    if (tau < 0) return fail(TPF_ERR_INVALID_ARG, "tau must be >= 0");
+    if (tau == 0) return TPF_OK;
+    if (!S || !V || !out) return fail(TPF_ERR_INVALID_ARG, "array pointer is NULL");
+    DeviceNet *dn = nullptr;
+    int rc = device_net(net, &dn);
+    if (rc != TPF_OK) return rc;
+    rc = launch_mismatch_f64(*net, *dn, S, V, dtype, tau, out, reinterpret_cast<hipStream_t>(stream));
+    if (rc != TPF_OK) return rc;
+    return check_launch("mismatch kernel launch");
+}

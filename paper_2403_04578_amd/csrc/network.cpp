@@ -1,0 +1,285 @@
+// Network build (host, FP64) and per-device staging of the sweep operator.
+//
+// Sec. II Eq. (1): nodal admittance Y from the series branches, partitioned into
+// the slack block and the demand block; Eq. (2) with constant-power loads:
+// Z = -Y_dd^-1 and w = -Y_dd^-1 Y_ds v_s, computed once per network (the paper
+// notes F and w stay constant through the iteration).  Y_dd is factorised here
+// by LU with partial pivoting; the solve kernels never see Y_dd except through
+// the FP64 mismatch check.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <queue>
+
+#include "tpf_internal.h"
+
+namespace tpf {
+
+namespace {
+thread_local std::string g_err;
+}
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+void clear_error() { g_err.clear(); }
+
+// In-place LU with partial pivoting of a dense n x n complex matrix (row-major);
+// returns false when a pivot is negligible against the matrix scale.
+static bool lu_factor(std::vector<cd> &a, std::vector<int> &piv, int n) {
+    double scale = 0.0;
+    for (const cd &v : a) scale = std::max(scale, std::abs(v));
+    piv.resize(n);
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        double best = std::abs(a[(size_t)k * n + k]);
+        for (int i = k + 1; i < n; ++i) {
+            double v = std::abs(a[(size_t)i * n + k]);
+            if (v > best) best = v, p = i;
+        }
+        if (!(best > 1e-13 * scale)) return false;
+        piv[k] = p;
+        if (p != k)
+            for (int j = 0; j < n; ++j) std::swap(a[(size_t)k * n + j], a[(size_t)p * n + j]);
+        const cd inv = 1.0 / a[(size_t)k * n + k];
+        for (int i = k + 1; i < n; ++i) {
+            cd f = a[(size_t)i * n + k] * inv;
+            a[(size_t)i * n + k] = f;
+            if (f == 0.0) continue;
+            for (int j = k + 1; j < n; ++j) a[(size_t)i * n + j] -= f * a[(size_t)k * n + j];
+        }
+    }
+    return true;
+}
+
+// Solves LU x = b in place (b length n).
+static void lu_solve(const std::vector<cd> &lu, const std::vector<int> &piv, int n, cd *b) {
+    for (int k = 0; k < n; ++k)
+        if (piv[k] != k) std::swap(b[k], b[piv[k]]);
+    for (int i = 1; i < n; ++i) {
+        cd s = b[i];
+        for (int j = 0; j < i; ++j) s -= lu[(size_t)i * n + j] * b[j];
+        b[i] = s;
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        cd s = b[i];
+        for (int j = i + 1; j < n; ++j) s -= lu[(size_t)i * n + j] * b[j];
+        b[i] = s / lu[(size_t)i * n + i];
+    }
+}
+
+// Row/column position of (PQ bus q, part) inside the real-block operator used by
+// the small-network kernels: each 16-row tile holds 8 buses, real parts in rows
+// 0-7 and imaginary parts in rows 8-15, so that the FP64 MFMA output layout
+// (lane group g holds tile rows g, g+4, g+8, g+12) keeps Re and Im of a bus in
+// one lane.
+static inline int blk_pos(int q, int part) { return 16 * (q / 8) + 8 * part + (q % 8); }
+
+static int upload(tpf_network_s &net, DeviceNet &dn) {
+    const int n = net.n;
+    auto dalloc = [&](void **p, size_t bytes) -> bool {
+        if (hipMalloc(p, bytes) != hipSuccess) return false;
+        dn.owned.push_back(*p);
+        return true;
+    };
+    auto h2d = [&](void *dst, const void *src, size_t bytes) -> bool {
+        return hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    // ---- small-network FP64 fragments
+    if (n <= 8 * kMaxSmallTiles) {
+        const int MT = (n + 7) / 8, M = 16 * MT, KT = 4 * MT;
+        dn.MT = MT;
+        std::vector<double> Ab((size_t)M * M, 0.0);  // real-block operator, permuted rows/cols
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                const cd z = net.Z[(size_t)i * n + k];
+                Ab[(size_t)blk_pos(i, 0) * M + blk_pos(k, 0)] = z.real();
+                Ab[(size_t)blk_pos(i, 0) * M + blk_pos(k, 1)] = -z.imag();
+                Ab[(size_t)blk_pos(i, 1) * M + blk_pos(k, 0)] = z.imag();
+                Ab[(size_t)blk_pos(i, 1) * M + blk_pos(k, 1)] = z.real();
+            }
+        // 16x16x4 FP64 MFMA A operand: lane 16*kk + ii holds A[16*mt + ii][4*kt + kk].
+        std::vector<double> frag((size_t)KT * MT * 64);
+        for (int kt = 0; kt < KT; ++kt)
+            for (int mt = 0; mt < MT; ++mt)
+                for (int l = 0; l < 64; ++l)
+                    frag[((size_t)kt * MT + mt) * 64 + l] = Ab[(size_t)(16 * mt + (l % 16)) * M + 4 * kt + l / 16];
+        std::vector<double> wv(2 * 8 * MT);
+        for (int q = 0; q < 8 * MT; ++q) {
+            wv[q] = q < n ? net.w[q].real() : 1.0;
+            wv[8 * MT + q] = q < n ? net.w[q].imag() : 0.0;
+        }
+        if (!dalloc((void **)&dn.A64, frag.size() * 8) || !dalloc((void **)&dn.w64, wv.size() * 8))
+            return fail(TPF_ERR_OOM, "device allocation failed (network staging)");
+        if (!h2d(dn.A64, frag.data(), frag.size() * 8) || !h2d(dn.w64, wv.data(), wv.size() * 8))
+            return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
+    }
+    // ---- CSR Y_dd and c = Y_ds v_s (FP64 mismatch)
+    {
+        const size_t nnz = net.colidx.size();
+        std::vector<double> yv(2 * nnz), cv(2 * n);
+        for (size_t e = 0; e < nnz; ++e) yv[2 * e] = net.yval[e].real(), yv[2 * e + 1] = net.yval[e].imag();
+        for (int i = 0; i < n; ++i) cv[2 * i] = net.c[i].real(), cv[2 * i + 1] = net.c[i].imag();
+        if (!dalloc((void **)&dn.rowptr, (n + 1) * 4) || !dalloc((void **)&dn.colidx, nnz * 4) ||
+            !dalloc((void **)&dn.yval, nnz * 16) || !dalloc((void **)&dn.cval, n * 16))
+            return fail(TPF_ERR_OOM, "device allocation failed (network staging)");
+        if (!h2d(dn.rowptr, net.rowptr.data(), (n + 1) * 4) || !h2d(dn.colidx, net.colidx.data(), nnz * 4) ||
+            !h2d(dn.yval, yv.data(), nnz * 16) || !h2d(dn.cval, cv.data(), n * 16))
+            return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
+    }
+    return TPF_OK;
+}
+
+int device_net(tpf_network net, DeviceNet **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TPF_ERR_DEVICE, "hipGetDevice failed (no GPU?)");
+    std::lock_guard<std::mutex> lock(net->mu);
+    if ((int)net->dev.size() <= dev) net->dev.resize(dev + 1, nullptr);
+    if (!net->dev[dev]) {
+        auto *dn = new (std::nothrow) DeviceNet();
+        if (!dn) return fail(TPF_ERR_OOM, "host allocation failed");
+        dn->device = dev;
+        int rc = upload(*net, *dn);
+        if (rc != TPF_OK) {
+            for (void *p : dn->owned) (void)hipFree(p);
+            delete dn;
+            return rc;
+        }
+        net->dev[dev] = dn;
+    }
+    *out = net->dev[dev];
+    return TPF_OK;
+}
+
+}  // namespace tpf
+
+using namespace tpf;
+
+extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                                 const double *r, const double *x, int32_t slack_bus, double vs_re,
+                                 double vs_im, tpf_network *out) {
+    clear_error();
+    if (!out) return fail(TPF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_bus < 2) return fail(TPF_ERR_INVALID_ARG, "n_bus must be >= 2");
+    if (n_branch < 1) return fail(TPF_ERR_INVALID_ARG, "n_branch must be >= 1");
+    if (!from || !to || !r || !x) return fail(TPF_ERR_INVALID_ARG, "branch arrays must not be NULL");
+    if (slack_bus < 0 || slack_bus >= n_bus) return fail(TPF_ERR_INVALID_ARG, "slack_bus out of range");
+    if (!std::isfinite(vs_re) || !std::isfinite(vs_im)) return fail(TPF_ERR_INVALID_ARG, "slack voltage not finite");
+    for (int k = 0; k < n_branch; ++k) {
+        if (from[k] < 0 || from[k] >= n_bus || to[k] < 0 || to[k] >= n_bus)
+            return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": bus index out of range");
+        if (from[k] == to[k]) return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": from == to");
+        if (!std::isfinite(r[k]) || !std::isfinite(x[k]))
+            return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": impedance not finite");
+        if (r[k] == 0.0 && x[k] == 0.0)
+            return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": zero impedance");
+    }
+    const int N = n_bus, n = n_bus - 1;
+    // Connectivity: every bus must be reachable from the slack, else Y_dd is singular.
+    {
+        std::vector<std::vector<int>> adj(N);
+        for (int k = 0; k < n_branch; ++k) adj[from[k]].push_back(to[k]), adj[to[k]].push_back(from[k]);
+        std::vector<char> seen(N, 0);
+        std::queue<int> q;
+        q.push(slack_bus);
+        seen[slack_bus] = 1;
+        int cnt = 1;
+        while (!q.empty()) {
+            int u = q.front();
+            q.pop();
+            for (int v : adj[u])
+                if (!seen[v]) seen[v] = 1, ++cnt, q.push(v);
+        }
+        if (cnt != N) return fail(TPF_ERR_SINGULAR, "network is not connected: some bus cannot reach the slack");
+    }
+    auto *net = new (std::nothrow) tpf_network_s();
+    if (!net) return fail(TPF_ERR_OOM, "host allocation failed");
+    try {
+        net->n_bus = N;
+        net->n = n;
+        net->slack = slack_bus;
+        net->vs = cd(vs_re, vs_im);
+        // Eq. (1): branch admittances stamped into Y.
+        std::vector<cd> Y((size_t)N * N, 0.0);
+        for (int k = 0; k < n_branch; ++k) {
+            const cd y = 1.0 / cd(r[k], x[k]);
+            const int f = from[k], t = to[k];
+            Y[(size_t)f * N + f] += y;
+            Y[(size_t)t * N + t] += y;
+            Y[(size_t)f * N + t] -= y;
+            Y[(size_t)t * N + f] -= y;
+        }
+        std::vector<int> pq;
+        for (int b = 0; b < N; ++b)
+            if (b != slack_bus) pq.push_back(b);
+        std::vector<cd> Ydd((size_t)n * n);
+        std::vector<cd> Yds(n);
+        for (int i = 0; i < n; ++i) {
+            Yds[i] = Y[(size_t)pq[i] * N + slack_bus];
+            for (int j = 0; j < n; ++j) Ydd[(size_t)i * n + j] = Y[(size_t)pq[i] * N + pq[j]];
+        }
+        net->rowptr.assign(1, 0);
+        for (int i = 0; i < n; ++i) {
+            for (int j = 0; j < n; ++j)
+                if (Ydd[(size_t)i * n + j] != 0.0) net->colidx.push_back(j), net->yval.push_back(Ydd[(size_t)i * n + j]);
+            net->rowptr.push_back((int32_t)net->colidx.size());
+        }
+        net->c.resize(n);
+        for (int i = 0; i < n; ++i) net->c[i] = Yds[i] * net->vs;
+        // Eq. (2): Z = -Y_dd^-1 (column by column from the LU factors), w = Z (Y_ds v_s).
+        std::vector<int> piv;
+        std::vector<cd> lu = Ydd;
+        if (!lu_factor(lu, piv, n)) {
+            delete net;
+            return fail(TPF_ERR_SINGULAR, "Y_dd is numerically singular");
+        }
+        net->Z.assign((size_t)n * n, 0.0);
+        std::vector<cd> col(n);
+        for (int j = 0; j < n; ++j) {
+            std::fill(col.begin(), col.end(), cd(0.0));
+            col[j] = -1.0;
+            lu_solve(lu, piv, n, col.data());
+            for (int i = 0; i < n; ++i) net->Z[(size_t)i * n + j] = col[i];
+        }
+        net->w.assign(n, 0.0);
+        for (int i = 0; i < n; ++i) {
+            cd acc = 0.0;
+            for (int j = 0; j < n; ++j) acc += net->Z[(size_t)i * n + j] * net->c[j];
+            net->w[i] = acc;
+        }
+    } catch (const std::bad_alloc &) {
+        delete net;
+        return fail(TPF_ERR_OOM, "host allocation failed");
+    }
+    *out = net;
+    return TPF_OK;
+}
+
+extern "C" void tpf_free_network(tpf_network net) {
+    if (!net) return;
+    for (DeviceNet *dn : net->dev) {
+        if (!dn) continue;
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(dn->device);
+        for (void *p : dn->owned) (void)hipFree(p);
+        (void)hipSetDevice(cur);
+        delete dn;
+    }
+    delete net;
+}
+
+extern "C" int tpf_network_n_pq(tpf_network net) { return net ? net->n : fail(TPF_ERR_INVALID_ARG, "net is NULL"); }
+
+extern "C" int tpf_network_get_zw(tpf_network net, double *Z_out, double *w_out) {
+    clear_error();
+    if (!net) return fail(TPF_ERR_INVALID_ARG, "net is NULL");
+    if (Z_out) std::memcpy(Z_out, net->Z.data(), net->Z.size() * sizeof(cd));
+    if (w_out) std::memcpy(w_out, net->w.data(), net->w.size() * sizeof(cd));
+    return TPF_OK;
+}
+
+extern "C" const char *tpf_last_error(void) { return tpf::g_err.c_str(); }

@@ -1,0 +1,73 @@
+// Internal declarations shared by the host and device sources of libtpf.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/tpf.h"
+
+namespace tpf {
+
+using cd = std::complex<double>;
+
+// Small-network sweep kernels keep one 16-row MFMA tile per 8 PQ buses in
+// registers; MT = ceil(n / 8) tiles, n <= 8 * kMaxSmallTiles.
+constexpr int kMaxSmallTiles = 16;
+
+// Device copies of a network, made on first use on each device.
+struct DeviceNet {
+    int device = -1;
+    int MT = 0;                  // 16-row tiles of the real-block operator (small-n kernels)
+    double *A64 = nullptr;       // FP64 MFMA A fragments, [4*MT k-steps][MT tiles][64 lanes]
+    double *w64 = nullptr;       // [2][8*MT]: Re w then Im w per bus (padding buses: 1, 0)
+    // Sparse Y_dd (CSR) and c = Y_ds v_s for the FP64 mismatch.
+    int32_t *rowptr = nullptr;   // [n+1]
+    int32_t *colidx = nullptr;   // [nnz]
+    double *yval = nullptr;      // [nnz][2]
+    double *cval = nullptr;      // [n][2]
+    std::vector<void *> owned;   // every allocation above, freed with the network
+};
+
+}  // namespace tpf
+
+struct tpf_network_s {
+    int n_bus = 0;
+    int n = 0;  // PQ buses
+    int slack = 0;
+    tpf::cd vs;
+    std::vector<tpf::cd> Z;  // [n][n], Z = -Y_dd^-1
+    std::vector<tpf::cd> w;  // [n]
+    // CSR of Y_dd in PQ order and c = Y_ds v_s.
+    std::vector<int32_t> rowptr, colidx;
+    std::vector<tpf::cd> yval;
+    std::vector<tpf::cd> c;
+    std::mutex mu;
+    std::vector<tpf::DeviceNet *> dev;  // indexed by HIP device id
+};
+
+namespace tpf {
+
+// Thread-local error text + return code helper.
+int fail(int code, const std::string &msg);
+void clear_error();
+
+// Returns the device copies of `net` on the current device, uploading on first use.
+int device_net(tpf_network net, DeviceNet **out);
+
+// Launchers (device code in fpi_small.hip / mismatch.hip).  All asynchronous on `stream`.
+int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype,
+                         int64_t tau, double tol, int max_iter, const void *V0, void *V,
+                         int32_t *iters, int8_t *status, unsigned long long *queue,
+                         hipStream_t stream);
+int launch_start_only(int n, const void *V0, int dtype, int64_t tau, void *V, int32_t *iters,
+                      int8_t *status, hipStream_t stream);
+int launch_mismatch_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, const void *V,
+                        int dtype, int64_t tau, double *out, hipStream_t stream);
+int launch_zero_u64(unsigned long long *p, int count, hipStream_t stream);
+
+}  // namespace tpf

@@ -1,0 +1,109 @@
+"""Host-side checks of libtpf.so that need no GPU: exported symbols, network
+build (Y partition, Z = -Y_dd^-1, w) against the oracle, error codes, and the
+argument checks the solve calls make before touching a device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2403_04578_amd as tpf
+from paper_2403_04578_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    src = open(os.path.join(ROOT, "include", "tpf.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tpf_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = tpf.load_library()
+    names = _declared_symbols()
+    assert len(names) >= 9
+    for name in names:
+        assert hasattr(lib, name), f"{name} declared in include/tpf.h but not exported"
+
+
+@pytest.mark.parametrize("n_bus", [2, 10, 100, 300])
+def test_network_build_matches_oracle(n_bus):
+    f = W.make_feeder(n_bus, seed=3)
+    net = tpf.Network.from_feeder(f)
+    Z, w = net.zw()
+    on = oracle.build_feeder(f)
+    assert net.n == n_bus - 1
+    assert np.abs(Z - on.Z).max() <= 1e-12 * np.abs(on.Z).max()
+    assert np.abs(w - on.w).max() <= 1e-12
+
+
+def test_meshed_network_and_parallel_branches():
+    # Eq. (1) is general: a loop and a doubled branch are accepted
+    frm, to = [0, 1, 2, 0, 1], [1, 2, 3, 3, 2]
+    r, x = [0.01, 0.02, 0.015, 0.03, 0.02], [0.02, 0.01, 0.02, 0.02, 0.01]
+    net = tpf.Network(4, frm, to, r, x)
+    on = oracle.build_network(4, frm, to, r, x)
+    Z, w = net.zw()
+    assert np.abs(Z - on.Z).max() < 1e-13
+
+
+def test_slack_not_bus_zero():
+    f = W.make_feeder(12, seed=5)
+    # relabel: swap bus 0 and bus 5 so the slack is bus 5
+    perm = np.arange(12)
+    perm[0], perm[5] = 5, 0
+    net = tpf.Network(12, perm[f.frm], perm[f.to], f.r, f.x, slack=5)
+    on = oracle.build_network(12, perm[f.frm], perm[f.to], f.r, f.x, slack=5)
+    Z, _ = net.zw()
+    assert np.abs(Z - on.Z).max() < 1e-13
+
+
+@pytest.mark.parametrize("case,code", [
+    (dict(n_bus=3, frm=[0, 1], to=[1, 2], r=[0.01, 0.0], x=[0.01, 0.0]), tpf.TPF_ERR_INVALID_ARG),  # zero z
+    (dict(n_bus=4, frm=[0, 2], to=[1, 3], r=[0.01, 0.01], x=[0.01, 0.01]), tpf.TPF_ERR_SINGULAR),  # island
+    (dict(n_bus=3, frm=[0, 1], to=[1, 3], r=[0.01, 0.01], x=[0.01, 0.01]), tpf.TPF_ERR_INVALID_ARG),  # index
+    (dict(n_bus=3, frm=[0, 1], to=[1, 1], r=[0.01, 0.01], x=[0.01, 0.01]), tpf.TPF_ERR_INVALID_ARG),  # self loop
+    (dict(n_bus=1, frm=[0], to=[0], r=[0.01], x=[0.01]), tpf.TPF_ERR_INVALID_ARG),
+    (dict(n_bus=3, frm=[0, 1], to=[1, 2], r=[np.nan, 0.01], x=[0.01, 0.01]), tpf.TPF_ERR_INVALID_ARG),
+])
+def test_network_build_errors(case, code):
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.Network(case["n_bus"], case["frm"], case["to"], case["r"], case["x"])
+    assert e.value.code == code
+    assert tpf.load_library().tpf_last_error().decode()
+
+
+def test_slack_out_of_range():
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.Network(3, [0, 1], [1, 2], [0.01, 0.01], [0.01, 0.01], slack=3)
+    assert e.value.code == tpf.TPF_ERR_INVALID_ARG
+
+
+def test_solve_argument_checks_before_device_use():
+    lib = tpf.load_library()
+    net = tpf.Network.from_feeder(W.make_feeder(10))
+    fake = ctypes.c_void_p(4096)  # never dereferenced: every case fails validation first
+    ws = ctypes.c_void_p(256 * 64)
+
+    def call(dtype=tpf.TPF_C128, T=10, tol=1e-6, max_iter=10, mode=0, wsb=256, wsp=ws):
+        o = tpf._Options(mode=mode)
+        return lib.tpf_solve_timeseries(net.handle, fake, dtype, T, tol, max_iter, ctypes.byref(o), fake, fake,
+                                        fake, wsp, wsb, None)
+
+    assert call(dtype=7) == tpf.TPF_ERR_INVALID_ARG
+    assert call(T=-1) == tpf.TPF_ERR_INVALID_ARG
+    assert call(tol=-1.0) == tpf.TPF_ERR_INVALID_ARG
+    assert call(tol=float("nan")) == tpf.TPF_ERR_INVALID_ARG
+    assert call(max_iter=-3) == tpf.TPF_ERR_INVALID_ARG
+    assert call(mode=9) == tpf.TPF_ERR_INVALID_ARG
+    assert call(mode=tpf.MODE_FP32, tol=1e-8) == tpf.TPF_ERR_INVALID_ARG  # below the FP32 floor
+    assert call(wsb=8) == tpf.TPF_ERR_INVALID_ARG
+    assert call(wsp=ctypes.c_void_p(256 * 64 + 8)) == tpf.TPF_ERR_INVALID_ARG  # misaligned
+    assert call(T=0) == tpf.TPF_OK  # nothing to do, no device touched
+    o = tpf._Options()
+    assert lib.tpf_solve_tensor(net.handle, fake, 1, -2, 5, 1e-6, 10, ctypes.byref(o), fake, fake, fake, ws, 256,
+                                None) == tpf.TPF_ERR_INVALID_ARG
+    assert lib.tpf_workspace_bytes(net.handle, 1000, None) >= 8

@@ -1,0 +1,220 @@
+"""GPU parity of the FP64 sweep path against the CPU oracle (Algorithm 1).
+
+Contract (FP64 mode): |V_gpu - V_oracle| <= 1e-9 pu on every bus of every column.
+With the same sweep count the two differ only by rounding order (FMA, MFMA
+summation), observed around 1e-15.  When a column's last step size sits on the
+tolerance the two may stop one sweep apart; such columns are re-run on the
+oracle with the GPU's sweep count and tol = 0 (fixed iteration count).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_04578_amd as tpf
+from paper_2403_04578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-9
+
+
+def _to_dev(S, dev, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(S)).to(dev).to(dtype).contiguous()
+
+
+def _parity(onet, S_host, V_gpu, it_gpu, st_gpu, tol, max_iter, V0=None, bound=TOL_FP64):
+    ref = oracle.fpi(onet, S_host, tol, max_iter, V0)
+    Vg = V_gpu.detach().cpu().numpy().astype(np.complex128).reshape(ref.V.shape)
+    ig = it_gpu.detach().cpu().numpy().reshape(-1)
+    sg = st_gpu.detach().cpu().numpy().reshape(-1)
+    same = ig == ref.iters
+    assert np.sum(~same) <= max(2, 0.001 * len(same)), f"sweep counts differ on {np.sum(~same)} columns"
+    err = np.abs(Vg[same] - ref.V[same]).max(initial=0.0)
+    assert err <= bound, f"max |dV| = {err:.3e}"
+    assert np.array_equal(sg[same], ref.status[same])
+    if (~same).any():
+        idx = np.nonzero(~same)[0]
+        assert np.all(np.abs(ig[idx] - ref.iters[idx]) <= 1)
+        for c in idx:
+            r2 = oracle.fpi(onet, S_host[c:c + 1], 0.0, int(ig[c]), None if V0 is None else V0[c:c + 1])
+            assert np.abs(Vg[c] - r2.V[0]).max() <= bound
+    return err
+
+
+@pytest.fixture(scope="module")
+def feeder100():
+    f = W.make_feeder(100)
+    return f, tpf.Network.from_feeder(f), oracle.build_feeder(f)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8])
+def test_fixed_sweeps_match_oracle(gpu, feeder100, k):
+    f, net, onet = feeder100
+    S = W.profile_minute_year(f, steps=1999, t0=12345)
+    V, it, st = tpf.solve_timeseries(net, _to_dev(S, gpu), tol=0.0, max_iter=k)
+    assert int(it.min()) == k and int(it.max()) == k
+    err = _parity(onet, S, V, it, st, 0.0, k, bound=1e-12)
+    assert err <= 1e-12
+
+
+def test_daily96_10bus_tol_1e10(gpu):
+    f = W.make_feeder(10)
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    S = W.profile_daily96(f)
+    V, it, st = tpf.solve_timeseries(net, _to_dev(S, gpu), tol=1e-10, max_iter=100)
+    _parity(onet, S, V, it, st, 1e-10, 100)
+    assert int(st.max()) == tpf.ST_CONVERGED
+
+
+@pytest.mark.parametrize("T", [1, 15, 16, 17, 63, 64, 65, 4099])
+def test_ragged_column_counts(gpu, feeder100, T):
+    f, net, onet = feeder100
+    S = W.profile_minute_year(f, steps=T, t0=777)
+    V, it, st = tpf.solve_timeseries(net, _to_dev(S, gpu), tol=1e-6, max_iter=100)
+    _parity(onet, S, V, it, st, 1e-6, 100)
+
+
+def test_complex64_io(gpu, feeder100):
+    f, net, onet = feeder100
+    S = W.profile_minute_year(f, steps=3000, t0=5000, dtype=np.complex64)
+    Sd = _to_dev(S, gpu, torch.complex64)
+    V, it, st = tpf.solve_timeseries(net, Sd, tol=1e-6, max_iter=100)
+    assert V.dtype == torch.complex64
+    # FP64 arithmetic on exactly-widened inputs; only the output is rounded to complex64
+    _parity(onet, S.astype(np.complex128), V, it, st, 1e-6, 100, bound=2e-7)
+
+
+@pytest.mark.parametrize("n_bus", [2, 3, 9, 17, 33, 64, 65, 100, 120, 129])
+def test_feeder_sizes(gpu, n_bus):
+    f = W.make_feeder(n_bus, seed=40 + n_bus)
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=333, seed=n_bus)
+    V, it, st = tpf.solve_timeseries(net, _to_dev(S, gpu), tol=1e-9, max_iter=60)
+    _parity(onet, S, V, it, st, 1e-9, 60)
+
+
+def test_star_feeder_closed_form(gpu):
+    # every PQ bus on its own line to the slack: n independent two-bus problems
+    rng = np.random.default_rng(5)
+    z = rng.uniform(0.01, 0.05, 40) + 1j * rng.uniform(0.01, 0.05, 40)
+    f = W.make_star_feeder(z)
+    net = tpf.Network.from_feeder(f)
+    s = rng.uniform(0.5, 2.0, (50, 40)) + 1j * rng.uniform(0.1, 1.0, (50, 40))
+    V, it, st = tpf.solve_timeseries(net, _to_dev(s, gpu), tol=1e-13, max_iter=500)
+    a = 1.0 - 2.0 * (z.real * s.real + z.imag * s.imag)
+    m2 = (a + np.sqrt(a * a - 4.0 * np.abs(z) ** 2 * np.abs(s) ** 2)) / 2.0
+    Vx = m2 + np.conj(z) * s
+    assert np.abs(V.cpu().numpy() - Vx).max() < 1e-11
+    assert int(st.max()) == tpf.ST_CONVERGED
+
+
+def test_zero_iterations_returns_start(gpu, feeder100):
+    f, net, _ = feeder100
+    S = _to_dev(W.profile_minute_year(f, steps=40), gpu)
+    V, it, st = tpf.solve_timeseries(net, S, tol=1e-6, max_iter=0)
+    assert torch.all(V == 1.0)
+    assert int(it.max()) == 0 and torch.all(st == tpf.ST_MAX_ITER)
+    V0 = (0.99 + 0.01j) * torch.ones_like(S)
+    V, it, st = tpf.solve_timeseries(net, S, tol=1e-6, max_iter=0, V0=V0)
+    assert torch.equal(V, V0)
+
+
+def test_zero_columns(gpu, feeder100):
+    f, net, _ = feeder100
+    S = torch.zeros((0, net.n), dtype=torch.complex128, device=gpu)
+    V, it, st = tpf.solve_timeseries(net, S, tol=1e-6, max_iter=10)
+    assert V.shape == (0, net.n)
+
+
+def test_zero_load_is_slack_voltage(gpu, feeder100):
+    f, net, _ = feeder100
+    S = torch.zeros((20, net.n), dtype=torch.complex128, device=gpu)
+    V, it, st = tpf.solve_timeseries(net, S, tol=1e-12, max_iter=10)
+    assert torch.all(it == 1) and torch.all(st == tpf.ST_CONVERGED)
+    assert float((V - 1.0).abs().max()) < 1e-14
+
+
+def test_nonfinite_and_infeasible_columns(gpu):
+    # two-bus, z = 1 + j0.5 (the paper's Fig. 1 line); 0.25 + j0.15 violates Eq. (11)
+    f = W.make_star_feeder(np.array([1.0 + 0.5j]))
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    S = np.array([[0.18 + 0.11j], [0.25 + 0.15j], [np.nan + 0j], [0.18 + 0.11j], [np.inf + 0j]])
+    V, it, st = tpf.solve_timeseries(net, _to_dev(S, gpu), tol=1e-12, max_iter=100)
+    st = st.cpu().numpy()
+    it = it.cpu().numpy()
+    ref = oracle.fpi(onet, S, 1e-12, 100)
+    assert list(st) == [0, 1, 2, 0, 2]
+    assert list(st) == list(ref.status)
+    assert it[1] == 100 and it[2] == 1
+    assert np.abs(V.cpu().numpy()[[0, 3]] - ref.V[[0, 3]]).max() < 1e-12
+
+
+def test_warm_start_and_guard(gpu, feeder100):
+    f, net, onet = feeder100
+    S = W.profile_minute_year(f, steps=500, t0=99)
+    rng = np.random.default_rng(3)
+    V0 = oracle.fpi(onet, S, 1e-3, 100).V + 1e-4 * (rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape))
+    bad = [3, 77, 200]
+    V0[3, 5] = np.nan
+    V0[77, 0] = 2.0
+    V0[200, 10] = 0.1 + 0j
+    V, it, st = tpf.solve_timeseries(net, _to_dev(S, gpu), tol=1e-9, max_iter=100, V0=_to_dev(V0, gpu))
+    V0g = V0.copy()
+    V0g[bad] = 1.0
+    _parity(onet, S, V, it, st, 1e-9, 100, V0=V0g)
+    flat = oracle.fpi(onet, S[bad], 1e-9, 100)
+    assert np.array_equal(it.cpu().numpy()[bad], flat.iters)
+
+
+def test_tensor_equals_timeseries_bitwise(gpu, feeder100):
+    f, net, _ = feeder100
+    S = _to_dev(W.profile_minute_year(f, steps=6 * 250, t0=31), gpu)
+    V1, i1, s1 = tpf.solve_timeseries(net, S, tol=1e-7, max_iter=50)
+    V2, i2, s2 = tpf.solve_tensor(net, S.reshape(6, 250, net.n).contiguous(), tol=1e-7, max_iter=50)
+    assert torch.equal(V1.reshape(6, 250, net.n), V2)
+    assert torch.equal(i1.reshape(6, 250), i2) and torch.equal(s1.reshape(6, 250), s2)
+
+
+def test_column_order_and_batch_invariance(gpu, feeder100):
+    f, net, _ = feeder100
+    S = _to_dev(W.profile_minute_year(f, steps=3001, t0=4242), gpu)
+    V1, i1, _ = tpf.solve_timeseries(net, S, tol=1e-8, max_iter=50)
+    perm = torch.randperm(S.shape[0], generator=torch.Generator().manual_seed(0)).to(gpu)
+    V2, i2, _ = tpf.solve_timeseries(net, S[perm].contiguous(), tol=1e-8, max_iter=50)
+    assert torch.equal(V2, V1[perm]) and torch.equal(i2, i1[perm])
+    V3, _, _ = tpf.solve_timeseries(net, S[1000:1100].contiguous(), tol=1e-8, max_iter=50)
+    assert torch.equal(V3, V1[1000:1100])
+    V4, _, _ = tpf.solve_timeseries(net, S, tol=1e-8, max_iter=50)
+    assert torch.equal(V4, V1)  # run-twice determinism
+
+
+def test_mismatch_kernel_matches_oracle(gpu, feeder100):
+    f, net, onet = feeder100
+    S = W.profile_minute_year(f, steps=800, t0=3)
+    V, it, st, mm = tpf.solve_timeseries(net, _to_dev(S, gpu), tol=1e-6, max_iter=100, mismatch=True)
+    Vh = V.cpu().numpy()
+    ref = oracle.mismatch(onet, S, Vh)
+    g = mm.cpu().numpy()
+    assert np.all(np.abs(g - ref) <= 1e-12 + 1e-9 * ref)
+    # power balance at tol 1e-6: |m_i| <= |S_i| d / |V_i| (about 3e-8 on this feeder)
+    assert g.max() < 1e-7
+    m2 = tpf.mismatch(net, _to_dev(S, gpu), V)
+    assert torch.equal(m2, mm)
+
+
+def test_full_year_sampled(gpu, feeder100):
+    """The 100-bus, 525,600-step year in the benchmark's launch configuration;
+    4096 sampled columns are checked against the oracle."""
+    f, net, onet = feeder100
+    S = W.profile_minute_year(f)
+    Sd = _to_dev(S, gpu)
+    V, it, st, mm = tpf.solve_timeseries(net, Sd, tol=1e-6, max_iter=100, mismatch=True)
+    torch.cuda.synchronize()
+    assert int(st.max()) == tpf.ST_CONVERGED
+    rng = np.random.default_rng(11)
+    idx = np.sort(rng.choice(S.shape[0], 4096, replace=False))
+    idx[-1] = S.shape[0] - 1
+    _parity(onet, S[idx], V[torch.from_numpy(idx).to(gpu)], it[torch.from_numpy(idx).to(gpu)],
+            st[torch.from_numpy(idx).to(gpu)], 1e-6, 100)
+    assert float(mm.max()) < 1e-7
