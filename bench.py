@@ -1,0 +1,195 @@
+#!/usr/bin/env python3
+"""Benchmark: power flows per second on the 100-bus feeder, one year at one-minute
+resolution (525,600 power flows), solved to 1e-6 pu.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step is one pass of the whole solve path over the year: start voltages,
+all sweeps of every column until it converges, and the FP64 power-balance
+mismatch check, with S already resident in device memory.  The FP64 form
+(every sweep in FP64) is timed; `value` is its whole-job throughput.  Prints
+ONE JSON line.
+
+Inputs are synthetic and seeded (no dataset): a random radial feeder grown as
+a k-ary tree (1-5 children per node), line r ~ U(0.005, 0.02) pu, x = r U(0.5, 2),
+base loads P ~ U(0.005, 0.02) pu at pf ~ U(0.9, 1), and per-bus minute profiles
+made of daily and weekly sinusoids times lognormal noise (sigma 0.2).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "power flows/s to 1e-6 pu, 100-bus 1-yr 1-min: FP64 FPI vs mixed+warm-start"
+PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
+PEAK_HBM_GBS = 8000.0
+
+
+def _kernel_sources_digest() -> str:
+    h = hashlib.sha256()
+    for name in ("fpi_small.hip",):
+        with open(os.path.join(ROOT, "paper_2403_04578_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic_from_profiles(kernel_key: str):
+    """HBM bytes per launch measured with rocprofv3 PMC counters, if they were taken on
+    the current kernel source (profiles/hbm_traffic.json); otherwise None."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+        e = d[kernel_key]
+        if e.get("source_digest") != _kernel_sources_digest():
+            return None
+        return float(e["bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(net_args, S, tol, max_iter, budget_s=12.0):
+    """The CPU oracle (plain FP64 C, OpenMP over columns) on a bounded sample of the
+    same workload, extrapolated to power flows per second."""
+    import oracle
+    onet = oracle.build_network(*net_args)
+    probe = 4000
+    t0 = time.perf_counter()
+    oracle.fpi(onet, S[:probe], tol, max_iter)
+    dt = time.perf_counter() - t0
+    n = int(min(len(S), max(probe, probe * budget_s / max(dt, 1e-6))))
+    t0 = time.perf_counter()
+    oracle.fpi(onet, S[:n], tol, max_iter)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "power flows/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {n} of {len(S)} one-minute steps of the year, tol {tol:g} pu, FP64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one plain device copy of known size (HBM counter calibration)")
+    ap.add_argument("--kernel-only", action="store_true",
+                    help="time only the sweep kernel launches (for profiling runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import paper_2403_04578_amd as tpf
+    from paper_2403_04578_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    tol, max_iter = 1e-6, 100
+    f = W.make_feeder(100)
+    t0 = time.perf_counter()
+    S_host = W.profile_minute_year(f)  # [525600, 99] complex128
+    gen_s = time.perf_counter() - t0
+    T, n = S_host.shape
+    net = tpf.Network.from_feeder(f)
+    t0 = time.perf_counter()
+    S = torch.from_numpy(S_host).to(dev)
+    torch.cuda.synchronize()
+    h2d_s = time.perf_counter() - t0
+
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    out = tpf.alloc_outputs(net, S, "fp64", mismatch=True)
+    stream = torch.cuda.current_stream(dev)
+
+    def step():
+        return tpf.solve_timeseries(net, S, tol, max_iter, "fp64", mismatch=True, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1e3 * wall / args.steps
+    V, iters, status, mm, _ = out
+    it = iters.cpu().numpy()
+    n_conv = int((status == tpf.ST_CONVERGED).sum())
+    max_mm = float(mm.max())
+
+    # sweep-kernel duration alone, HIP events on the stream the kernel runs on
+    kout = tpf.alloc_outputs(net, S, "fp64", mismatch=False)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for a, b in ev:
+        a.record(stream)
+        tpf.solve_timeseries(net, S, tol, max_iter, "fp64", out=kout)
+        b.record(stream)
+    torch.cuda.synchronize()
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    # mismatch kernel alone
+    ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+    for a, b in ev2:
+        a.record(stream)
+        tpf.mismatch(net, S, V)
+        b.record(stream)
+    torch.cuda.synchronize()
+    mm_ms = float(np.mean([a.elapsed_time(b) for a, b in ev2]))
+
+    sweeps = int(it.sum())
+    flops = 8.0 * n * n * sweeps  # dense complex product Z I per column-sweep: 8 n^2 real flops
+    achieved_tflops = flops / (k_ms * 1e-3) / 1e12
+    traffic = _traffic_from_profiles("fpi_f64_kernel<2,8,double>/year100")
+    pf_s = T / (ms_per_step * 1e-3)
+    rec = {
+        "metric": METRIC,
+        "value": pf_s,
+        "unit": "power flows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded k-ary radial feeder, sinusoid x lognormal minute profiles)",
+        "config": {"workload": "100-bus radial feeder (99 PQ), 525,600 one-minute steps, complex128 S, "
+                               "flat start, tol 1e-6 pu max|dV|, max 100 sweeps, FP64 sweeps + FP64 mismatch",
+                   "form": "fp64", "n_pq": n, "power_flows": T},
+        "roofline": {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
+                     "kernel": "fpi_f64_kernel<2,8,double>", "kernel_ms": k_ms,
+                     "algorithmic_flops": flops},
+        "sweeps": {"mean": float(it.mean()), "min": int(it.min()), "max": int(it.max()),
+                   "hist": {int(k): int(v) for k, v in zip(*np.unique(it, return_counts=True))}},
+        "converged": n_conv,
+        "max_mismatch_pu": max_mm,
+        "mismatch_kernel_ms": mm_ms,
+        "host_to_device_s": h2d_s,
+        "input_generation_s": gen_s,
+    }
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline((f.n_bus, f.frm, f.to, f.r, f.x, 0, f.vs), S_host, tol, max_iter)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

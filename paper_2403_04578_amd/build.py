@@ -28,6 +28,8 @@ FLAGS = [
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
+    # MFMA accumulators stay in VGPRs (no AGPR copies around the k-loops)
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", os.path.join(REPO, "include"),
 ]
 

@@ -62,7 +62,7 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
             rc = launch_fpi_small_f64(*net, *dn, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out,
                                       queue, st);
     } else {
-        return fail(TPF_ERR_UNSUPPORTED, "networks with more than 128 PQ buses are not implemented yet");
+        return fail(TPF_ERR_UNSUPPORTED, "networks with more than 320 PQ buses are not implemented yet");
     }
     if (rc != TPF_OK) return rc;
     rc = check_launch("sweep kernel launch");

@@ -100,12 +100,24 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
                 Ab[(size_t)blk_pos(i, 1) * M + blk_pos(k, 0)] = z.imag();
                 Ab[(size_t)blk_pos(i, 1) * M + blk_pos(k, 1)] = z.real();
             }
-        // 16x16x4 FP64 MFMA A operand: lane 16*kk + ii holds A[16*mt + ii][4*kt + kk].
-        std::vector<double> frag((size_t)KT * MT * 64);
-        for (int kt = 0; kt < KT; ++kt)
-            for (int mt = 0; mt < MT; ++mt)
-                for (int l = 0; l < 64; ++l)
-                    frag[((size_t)kt * MT + mt) * 64 + l] = Ab[(size_t)(16 * mt + (l % 16)) * M + 4 * kt + l / 16];
+        // 16x16x4 FP64 MFMA A operand: lane 16*kk + ii holds A[16*mt + ii][4*kt + kk].  Grouped
+        // by the wave role that multiplies tile mt (mt % NW), so that one wave's fragments
+        // of a k-step are contiguous.
+        int NW = 0, TPW = 0;
+        rows_config(MT, NW, TPW);
+        dn.NW = NW;
+        dn.TPW = TPW;
+        const int KP = KT + kFragPadSteps;
+        std::vector<double> frag((size_t)NW * KP * TPW * 64, 0.0);
+        for (int tw = 0; tw < NW; ++tw)
+            for (int kt = 0; kt < KT; ++kt)
+                for (int q = 0; q < TPW; ++q) {
+                    const int mt = tw + NW * q;
+                    if (mt >= MT) continue;
+                    for (int l = 0; l < 64; ++l)
+                        frag[(((size_t)tw * KP + kt) * TPW + q) * 64 + l] =
+                            Ab[(size_t)(16 * mt + (l % 16)) * M + 4 * kt + l / 16];
+                }
         std::vector<double> wv(2 * 8 * MT);
         for (int q = 0; q < 8 * MT; ++q) {
             wv[q] = q < n ? net.w[q].real() : 1.0;

@@ -15,15 +15,26 @@ namespace tpf {
 
 using cd = std::complex<double>;
 
-// Small-network sweep kernels keep one 16-row MFMA tile per 8 PQ buses in
+// Register-resident sweep kernels keep one 16-row MFMA tile per 8 PQ buses in
 // registers; MT = ceil(n / 8) tiles, n <= 8 * kMaxSmallTiles.
-constexpr int kMaxSmallTiles = 16;
+constexpr int kMaxSmallTiles = 40;
+
+// Workgroup shape of the register-resident kernels for MT row tiles: NW waves,
+// each owning at most TPW tiles (tile t belongs to wave role t % NW).
+inline void rows_config(int MT, int &NW, int &TPW) {
+    NW = MT <= 4 ? 4 : 8;
+    TPW = (MT + NW - 1) / NW;
+}
+// The FP64 fragment array carries this many zero k-steps past the end so that the
+// k-loop's prefetch ring never needs a bounds branch.
+constexpr int kFragPadSteps = 4;
 
 // Device copies of a network, made on first use on each device.
 struct DeviceNet {
     int device = -1;
     int MT = 0;                  // 16-row tiles of the real-block operator (small-n kernels)
-    double *A64 = nullptr;       // FP64 MFMA A fragments, [4*MT k-steps][MT tiles][64 lanes]
+    int NW = 0, TPW = 0;         // workgroup shape (rows_config)
+    double *A64 = nullptr;       // FP64 MFMA A fragments, [NW roles][4*MT+pad k-steps][TPW tiles][64 lanes]
     double *w64 = nullptr;       // [2][8*MT]: Re w then Im w per bus (padding buses: 1, 0)
     // Sparse Y_dd (CSR) and c = Y_ds v_s for the FP64 mismatch.
     int32_t *rowptr = nullptr;   // [n+1]
