@@ -32,11 +32,12 @@ sys.path.insert(0, ROOT)
 METRIC = "power flows/s to 1e-6 pu, 100-bus 1-yr 1-min: FP64 FPI vs mixed+warm-start"
 PEAK_FP64_TFLOPS = 78.6  # MI355X dense FP64 (matrix and vector)
 PEAK_HBM_GBS = 8000.0
+PEAK_F16_TFLOPS = 2500.0  # MI355X dense FP16/BF16 matrix
 
 
 def _kernel_sources_digest() -> str:
     h = hashlib.sha256()
-    for name in ("fpi_small.hip",):
+    for name in ("fpi_small.hip", "fpi_mixed.hip"):
         with open(os.path.join(ROOT, "paper_2403_04578_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -115,73 +116,102 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    out = tpf.alloc_outputs(net, S, "fp64", mismatch=True)
     stream = torch.cuda.current_stream(dev)
 
-    def step():
-        return tpf.solve_timeseries(net, S, tol, max_iter, "fp64", mismatch=True, out=out)
+    def time_form(mode, V0=None):
+        """K timed steps of one form (solve + FP64 mismatch), plus the sweep kernel alone."""
+        out = tpf.alloc_outputs(net, S, mode, mismatch=True)
+        step = lambda: tpf.solve_timeseries(net, S, tol, max_iter, mode, V0=V0, mismatch=True, out=out)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kout = tpf.alloc_outputs(net, S, mode, mismatch=False)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for a, b in ev:
+            a.record(stream)
+            tpf.solve_timeseries(net, S, tol, max_iter, mode, V0=V0, out=kout)
+            b.record(stream)
+        torch.cuda.synchronize()
+        k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        V, iters, status, mm, _ = out
+        it = iters.cpu().numpy()
+        return {"ms_per_step": 1e3 * wall / args.steps, "kernel_ms": k_ms, "V": V,
+                "power_flows_per_s": T / (wall / args.steps),
+                "sweeps_mean": float(it.mean()), "sweeps_max": int(it.max()),
+                "sweep_hist": {int(k): int(v) for k, v in zip(*np.unique(it, return_counts=True))},
+                "converged": int((status == tpf.ST_CONVERGED).sum()), "max_mismatch_pu": float(mm.max()),
+                "total_sweeps": int(it.sum())}
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = 1e3 * wall / args.steps
-    V, iters, status, mm, _ = out
-    it = iters.cpu().numpy()
-    n_conv = int((status == tpf.ST_CONVERGED).sum())
-    max_mm = float(mm.max())
-
-    # sweep-kernel duration alone, HIP events on the stream the kernel runs on
-    kout = tpf.alloc_outputs(net, S, "fp64", mismatch=False)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    for a, b in ev:
-        a.record(stream)
-        tpf.solve_timeseries(net, S, tol, max_iter, "fp64", out=kout)
-        b.record(stream)
-    torch.cuda.synchronize()
-    k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    forms = {}
+    forms["fp64"] = time_form("fp64")
+    for mode in ("fp32", "mixed_bf16", "mixed_fp16"):
+        forms[mode] = time_form(mode)
+    Vref = forms["fp64"]["V"]
+    for mode, r in forms.items():
+        r["max_err_vs_fp64_pu"] = float((r["V"] - Vref).abs().max())
+    # error of every form against the CPU oracle on a sample of columns
+    import oracle
+    onet = oracle.build_network(f.n_bus, f.frm, f.to, f.r, f.x, 0, f.vs)
+    rng = np.random.default_rng(7)
+    idx = np.sort(rng.choice(T, 2000, replace=False))
+    ref = oracle.fpi(onet, S_host[idx], 1e-10, 200).V
+    ti = torch.from_numpy(idx).to(dev)
+    for mode, r in forms.items():
+        r["max_err_vs_oracle_sample_pu"] = float(np.abs(r["V"][ti].cpu().numpy() - ref).max())
+        del r["V"]
     # mismatch kernel alone
     ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
     for a, b in ev2:
         a.record(stream)
-        tpf.mismatch(net, S, V)
+        tpf.mismatch(net, S, Vref)
         b.record(stream)
     torch.cuda.synchronize()
     mm_ms = float(np.mean([a.elapsed_time(b) for a, b in ev2]))
 
-    sweeps = int(it.sum())
-    flops = 8.0 * n * n * sweeps  # dense complex product Z I per column-sweep: 8 n^2 real flops
-    achieved_tflops = flops / (k_ms * 1e-3) / 1e12
-    traffic = _traffic_from_profiles("fpi_f64_kernel<2,8,double>/year100")
-    pf_s = T / (ms_per_step * 1e-3)
+    head = min(("mixed_bf16", "mixed_fp16"), key=lambda m: forms[m]["ms_per_step"])
+    hf = forms[head]
+    base = forms["fp64"]
+    for r in forms.values():
+        r["speedup_vs_fp64"] = base["ms_per_step"] / r["ms_per_step"]
+    # dominant kernel of the headline form: the mixed sweep kernel
+    flops = 8.0 * n * n * hf["total_sweeps"]
+    achieved = flops / (hf["kernel_ms"] * 1e-3) / 1e12
+    flops64 = 8.0 * n * n * base["total_sweeps"]
+    ach64 = flops64 / (base["kernel_ms"] * 1e-3) / 1e12
     rec = {
         "metric": METRIC,
-        "value": pf_s,
+        "value": hf["power_flows_per_s"],
         "unit": "power flows/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
+        "ms_per_step": hf["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f16" if head == "mixed_fp16" else "bf16",
         "data": "synthetic (seeded k-ary radial feeder, sinusoid x lognormal minute profiles)",
         "config": {"workload": "100-bus radial feeder (99 PQ), 525,600 one-minute steps, complex128 S, "
-                               "flat start, tol 1e-6 pu max|dV|, max 100 sweeps, FP64 sweeps + FP64 mismatch",
-                   "form": "fp64", "n_pq": n, "power_flows": T},
-        "roofline": {"bound": "mfma", "achieved": achieved_tflops, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved_tflops / PEAK_FP64_TFLOPS, "traffic": traffic,
-                     "kernel": "fpi_f64_kernel<2,8,double>", "kernel_ms": k_ms,
+                               "flat start, tol 1e-6 pu max|dV|, max 100 sweeps, + FP64 mismatch",
+                   "form": head, "n_pq": n, "power_flows": T},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_F16_TFLOPS, "traffic": _traffic_from_profiles(f"{head}/year100"),
+                     "kernel": f"fpi_mixed_kernel<2,8,7,{head}>", "kernel_ms": hf["kernel_ms"],
                      "algorithmic_flops": flops},
-        "sweeps": {"mean": float(it.mean()), "min": int(it.min()), "max": int(it.max()),
-                   "hist": {int(k): int(v) for k, v in zip(*np.unique(it, return_counts=True))}},
-        "converged": n_conv,
-        "max_mismatch_pu": max_mm,
+        "fp64_form": {"value": base["power_flows_per_s"], "ms_per_step": base["ms_per_step"],
+                      "roofline": {"bound": "mfma", "achieved": ach64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                                   "frac": ach64 / PEAK_FP64_TFLOPS,
+                                   "traffic": _traffic_from_profiles("fp64/year100"),
+                                   "kernel": "fpi_f64_kernel<2,8,double>", "kernel_ms": base["kernel_ms"],
+                                   "algorithmic_flops": flops64}},
+        "speedup_vs_fp64_form": base["ms_per_step"] / hf["ms_per_step"],
+        "forms": forms,
         "mismatch_kernel_ms": mm_ms,
         "host_to_device_s": h2d_s,
         "input_generation_s": gen_s,

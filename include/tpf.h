@@ -134,6 +134,58 @@ int tpf_solve_tensor(tpf_network net, const void *S, int32_t dtype, int64_t n_sc
 int tpf_mismatch(tpf_network net, const void *S, const void *V, int32_t dtype, int64_t tau,
                  double *out, void *stream);
 
+/* ---------------------------------------------------------------------------------------
+ * Learned warm start.  Not part of the paper's method: a multilayer perceptron that maps a
+ * time step's loads to an estimate of its converged voltages, used as V0 so that Algorithm 1
+ * starts closer to its fixed point (the flat start stays the fallback through the V0 guard
+ * of tpf_solve_*).  Definitions:
+ *   features  x = [50 Re S, 50 Im S, sin/cos(2 pi (t mod 1440)/1440),
+ *                  sin/cos(2 pi (floor(t/1440) mod 365)/365)]  (2n + 4 values, t = minute index)
+ *   layers    h_l = gelu(h_{l-1} W_l^T + b_l) for the hidden layers, y = h_L W^T + b (2n outputs);
+ *             gelu(z) = z (1 + erf(z/sqrt 2))/2; products in BF16 on MFMA, FP32 accumulation
+ *   output    V0 = v_s + (y_re + j y_im) / 20
+ *   training  loss = mean (y - 20 [Re(V - v_s), Im(V - v_s)])^2 over rows and outputs;
+ *             AdamW (beta1 0.9, beta2 0.999, eps 1e-8, decoupled weight decay) on FP32 master
+ *             parameters, BF16 copies refreshed after each step.
+ * Parameters are one flat float32 vector [W_1 (out x in, row-major), b_1, W_2, b_2, ...].
+ * A handle is bound to the device that is current when it is created.
+ * --------------------------------------------------------------------------------------- */
+typedef struct tpf_mlp_s *tpf_mlp;
+
+/* n_pq PQ buses, `layers` hidden layers of width `hidden`; params: host float32 [num_params]
+ * initial values (NULL: zeros); vs: slack voltage.  Errors: INVALID_ARG, DEVICE, OOM. */
+int tpf_mlp_create(int32_t n_pq, int32_t hidden, int32_t layers, const float *params, double vs_re,
+                   double vs_im, tpf_mlp *out);
+void tpf_mlp_free(tpf_mlp mlp);
+int64_t tpf_mlp_num_params(tpf_mlp mlp);
+/* Host float32 [num_params] copies of the FP32 master parameters (synchronous). */
+int tpf_mlp_get_params(tpf_mlp mlp, float *params_out);
+int tpf_mlp_set_params(tpf_mlp mlp, const float *params);
+
+/* Device workspace for `rows` rows of training or prediction. */
+size_t tpf_mlp_workspace_bytes(tpf_mlp mlp, int64_t rows);
+
+/* Loss and FP32 gradient of a batch.
+ *   S        device [rows][n] loads (TPF_C64 / TPF_C128);  t_index  device int64 [rows] minute index
+ *   V        device [rows][n] target voltages, same dtype as S
+ *   loss_out device float32 [1];  grad_out  device float32 [num_params] */
+int tpf_mlp_loss_grad(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t *t_index, const void *V,
+                      int64_t rows, float *loss_out, float *grad_out, void *workspace, size_t workspace_bytes,
+                      void *stream);
+
+/* One AdamW step on a batch (same inputs); loss_out may be NULL. */
+int tpf_mlp_train_step(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t *t_index, const void *V,
+                       int64_t rows, float lr, float weight_decay, float *loss_out, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/* Warm start V0 (device [rows][n], same dtype as S) for the loads S at minute indices t_index. */
+int tpf_mlp_predict(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t *t_index, int64_t rows, void *V0_out,
+                    void *workspace, size_t workspace_bytes, void *stream);
+
+/* Binary file with sizes, slack voltage, Adam step count and FP32 parameters. */
+int tpf_mlp_save(tpf_mlp mlp, const char *path);
+int tpf_mlp_load(const char *path, tpf_mlp *out);
+
 /* Description of the last error on this thread ("" if none). */
 const char *tpf_last_error(void);
 

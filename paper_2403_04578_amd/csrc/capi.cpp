@@ -46,7 +46,6 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
     if (!workspace || workspace_bytes < tpf_workspace_bytes(net, T, opts))
         return fail(TPF_ERR_INVALID_ARG, "workspace missing or smaller than tpf_workspace_bytes()");
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(TPF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-    if (mode != TPF_MODE_FP64) return fail(TPF_ERR_UNSUPPORTED, "only TPF_MODE_FP64 is implemented");
     const void *V0 = opts ? opts->V0 : nullptr;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     DeviceNet *dn = nullptr;
@@ -58,9 +57,12 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
         auto *queue = reinterpret_cast<unsigned long long *>(workspace);
         rc = launch_zero_u64(queue, 1, st);
         if (rc == TPF_OK) rc = check_launch("queue reset");
-        if (rc == TPF_OK)
+        if (rc == TPF_OK && mode == TPF_MODE_FP64)
             rc = launch_fpi_small_f64(*net, *dn, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out,
                                       queue, st);
+        else if (rc == TPF_OK)
+            rc = launch_fpi_mixed(*net, *dn, mode, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out,
+                                  queue, st);
     } else {
         return fail(TPF_ERR_UNSUPPORTED, "networks with more than 320 PQ buses are not implemented yet");
     }

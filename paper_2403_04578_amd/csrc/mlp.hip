@@ -1,0 +1,615 @@
+// Learned warm start: a multilayer perceptron from loads to converged voltages,
+// trained and evaluated with this library's own kernels (BF16 MFMA products,
+// FP32 accumulation, FP32 master parameters, AdamW).
+//
+// Kernels
+//   features_kernel    S, minute index -> X [rows][D0] bf16 (zero padded)
+//   gemm_bf16_kernel   C = A B on 16x16x32 BF16 MFMA, 64x64 output tiles, A and B
+//                      read through arbitrary element strides (so the same kernel
+//                      does X W^T, dZ W and dZ^T X), fused epilogues: bias + GELU
+//                      (hidden layers), bias (output), GELU' (backward), store of
+//                      the weight gradient into the flat FP32 gradient vector
+//   output_grad_kernel MSE loss and dY = 2 (y - target) / (rows outputs)
+//   colsum_kernel      bias gradients
+//   adamw_kernel       decoupled-weight-decay Adam on the FP32 master vector
+//   sync_kernel        BF16 copies of the weights in both layouts the GEMMs read
+//   predict_out_kernel y -> V0 = v_s + (y_re + j y_im)/20
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "tpf_internal.h"
+
+namespace tpf {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+
+namespace {
+
+constexpr int kPad = 64;  // every layer width is padded to a multiple of 64
+inline int padw(int x) { return (x + kPad - 1) / kPad * kPad; }
+constexpr float kFeatScale = 50.0f, kOutScale = 20.0f;
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.39894228040143268f;
+}
+
+template <typename IO>
+__global__ void features_kernel(const IO *__restrict__ S, const int64_t *__restrict__ t_index, int n, int64_t rows,
+                                int64_t rows_pad, int D0p, __bf16 *__restrict__ X) {
+    const int64_t total = rows_pad * D0p;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / D0p;
+        const int f = (int)(e - r * D0p);
+        float v = 0.0f;
+        if (r < rows) {
+            if (f < n) {
+                v = kFeatScale * (float)S[2 * (r * n + f)];
+            } else if (f < 2 * n) {
+                v = kFeatScale * (float)S[2 * (r * n + f - n) + 1];
+            } else if (f < 2 * n + 4) {
+                const int64_t t = t_index[r];
+                const double mod = (double)(t % 1440) / 1440.0;
+                const double day = (double)((t / 1440) % 365) / 365.0;
+                const double ang = 2.0 * M_PI * (f < 2 * n + 2 ? mod : day);
+                v = (float)(((f - 2 * n) & 1) ? cos(ang) : sin(ang));
+            }
+        }
+        X[e] = (__bf16)v;
+    }
+}
+
+enum { EP_HIDDEN = 0, EP_OUT = 1, EP_DGELU = 2, EP_DW = 3 };
+
+// C[M][N] = sum_k A(m, k) B(k, n), A(m,k) = A[m sam + k sak], B(k,n) = B[k sbk + n sbn].
+// M, N multiples of 64 and K a multiple of 32 (callers pad).  AK / BK: the operand is
+// contiguous along k (else along m / n).
+template <bool AK, bool BK, int EP>
+__global__ __launch_bounds__(256) void gemm_bf16_kernel(const __bf16 *__restrict__ A, int64_t sam, int64_t sak,
+                                                        const __bf16 *__restrict__ B, int64_t sbk, int64_t sbn,
+                                                        int K, const float *__restrict__ bias,
+                                                        float *__restrict__ Cf, __bf16 *__restrict__ Cb,
+                                                        int64_t ldc, const float *__restrict__ Zin, int64_t ldz,
+                                                        int valid_m, int valid_n, int64_t goff) {
+    __shared__ __align__(16) __bf16 As[64][40];
+    __shared__ __align__(16) __bf16 Bs[64][40];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int64_t m0 = (int64_t)blockIdx.x * 64;
+    const int n0 = blockIdx.y * 64;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    f4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = f4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        if (AK) {
+            const int m = tid >> 2, kk = (tid & 3) * 8;
+            const b8 v = *reinterpret_cast<const b8 *>(A + (m0 + m) * sam + (int64_t)(k0 + kk));
+            *reinterpret_cast<b8 *>(&As[m][kk]) = v;
+        } else {
+            const int k = tid >> 3, mm = (tid & 7) * 8;
+            const b8 v = *reinterpret_cast<const b8 *>(A + (m0 + mm) + (int64_t)(k0 + k) * sak);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) As[mm + i][k] = v[i];
+        }
+        if (BK) {
+            const int nn = tid >> 2, kk = (tid & 3) * 8;
+            const b8 v = *reinterpret_cast<const b8 *>(B + (int64_t)(n0 + nn) * sbn + (k0 + kk));
+            *reinterpret_cast<b8 *>(&Bs[nn][kk]) = v;
+        } else {
+            const int k = tid >> 3, nn = (tid & 7) * 8;
+            const b8 v = *reinterpret_cast<const b8 *>(B + (int64_t)(k0 + k) * sbk + (n0 + nn));
+#pragma unroll
+            for (int i = 0; i < 8; ++i) Bs[nn + i][k] = v[i];
+        }
+        __syncthreads();
+        b8 af[2], bf[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) af[a] = *reinterpret_cast<const b8 *>(&As[wm + 16 * a + j][8 * g]);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bf[b] = *reinterpret_cast<const b8 *>(&Bs[wn + 16 * b + j][8 * g]);
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+        __syncthreads();
+    }
+    // epilogue: lane holds C[row 4g + r][col j] of each 16x16 tile
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t m = m0 + wm + 16 * a + 4 * g + r;
+                const int nn = n0 + wn + 16 * b + j;
+                float v = acc[a][b][r];
+                if (EP == EP_HIDDEN) {
+                    v += bias[nn];
+                    Cf[m * ldc + nn] = v;                       // pre-activation (for backward)
+                    Cb[m * ldc + nn] = (__bf16)(nn < valid_n ? gelu(v) : 0.0f);
+                } else if (EP == EP_OUT) {
+                    Cf[m * ldc + nn] = v + bias[nn];
+                } else if (EP == EP_DGELU) {
+                    Cb[m * ldc + nn] = (__bf16)(nn < valid_n ? v * gelu_grad(Zin[m * ldz + nn]) : 0.0f);
+                } else {  // EP_DW: gradient of W [valid_m][valid_n], row-major at goff
+                    if (m < valid_m && nn < valid_n) Cf[goff + m * valid_n + nn] = v;
+                }
+            }
+}
+
+template <typename IO>
+__global__ void output_grad_kernel(const float *__restrict__ Y, int64_t ldy, const IO *__restrict__ V, int n,
+                                   int64_t rows, int64_t rows_pad, int Np, double vs_re, double vs_im,
+                                   __bf16 *__restrict__ dY, float *__restrict__ loss) {
+    const int64_t total = rows_pad * Np;
+    const float scale = 2.0f / (float)(rows * 2 * n);
+    float part = 0.0f;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / Np;
+        const int c = (int)(e - r * Np);
+        float d = 0.0f;
+        if (r < rows && c < 2 * n) {
+            const int b = c < n ? c : c - n;
+            const double t = c < n ? ((double)V[2 * (r * n + b)] - vs_re) : ((double)V[2 * (r * n + b) + 1] - vs_im);
+            d = Y[r * ldy + c] - (float)(kOutScale * t);
+            part += d * d;
+        }
+        dY[e] = (__bf16)(scale * d);
+    }
+    for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+    if (loss && (threadIdx.x & 63) == 0) atomicAdd(loss, part / (float)(rows * 2 * n));
+}
+
+// bias gradient: g[c] = sum_r dZ[r][c] for c < nvalid
+__global__ void colsum_kernel(const __bf16 *__restrict__ dZ, int64_t rows_pad, int Np, int nvalid,
+                              float *__restrict__ g) {
+    const int c = blockIdx.x;
+    float s = 0.0f;
+    for (int64_t r = threadIdx.x; r < rows_pad; r += blockDim.x) s += (float)dZ[r * Np + c];
+    __shared__ float red[256];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && c < nvalid) g[c] = red[0];
+}
+
+__global__ void adamw_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                             float *__restrict__ v, int64_t P, float lr, float wd, float b1, float b2, float eps,
+                             float bc1, float bc2) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < P; i += (int64_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float mh = mi / bc1, vh = vi / bc2;
+        p[i] -= lr * (mh / (sqrtf(vh) + eps) + wd * p[i]);
+    }
+}
+
+// BF16 copies of layer l: Wt [out_p][in_p] (= W, k contiguous for X W^T) and
+// Wn [in_p][out_p] (= W^T, for dZ W), zero in the padding.
+__global__ void sync_kernel(const float *__restrict__ p, int64_t woff, int in, int out, int in_p, int out_p,
+                            __bf16 *__restrict__ Wt, __bf16 *__restrict__ Wn, float *__restrict__ bias_p,
+                            int64_t boff) {
+    const int64_t total = (int64_t)in_p * out_p;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int o = (int)(e / in_p), i = (int)(e - (int64_t)o * in_p);
+        const float w = (o < out && i < in) ? p[woff + (int64_t)o * in + i] : 0.0f;
+        Wt[(int64_t)o * in_p + i] = (__bf16)w;
+        Wn[(int64_t)i * out_p + o] = (__bf16)w;
+        if (i == 0) bias_p[o] = o < out ? p[boff + o] : 0.0f;
+    }
+}
+
+template <typename IO>
+__global__ void predict_out_kernel(const float *__restrict__ Y, int64_t ldy, int n, int64_t rows, double vs_re,
+                                   double vs_im, IO *__restrict__ V0) {
+    const int64_t total = rows * n;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e / n;
+        const int b = (int)(e - r * n);
+        V0[2 * e] = (IO)(vs_re + (double)Y[r * ldy + b] / kOutScale);
+        V0[2 * e + 1] = (IO)(vs_im + (double)Y[r * ldy + n + b] / kOutScale);
+    }
+}
+
+__global__ void zero_f32_kernel(float *p, int64_t count) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0.0f;
+}
+
+unsigned grid_for(int64_t work, int64_t per_block = 256) {
+    const int64_t b = (work + per_block - 1) / per_block;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 65536));
+}
+
+}  // namespace
+}  // namespace tpf
+
+using namespace tpf;
+
+struct tpf_mlp_s {
+    int n = 0, hidden = 0, layers = 0;  // layers = hidden layers
+    int device = 0;
+    double vs_re = 1.0, vs_im = 0.0;
+    std::vector<int> d, dp;              // widths and padded widths, L+2 entries
+    std::vector<int64_t> woff, boff;     // offsets in the flat vector
+    int64_t P = 0;
+    int64_t step = 0;                    // AdamW steps taken
+    float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;  // device FP32 [P]
+    std::vector<__bf16 *> Wt, Wn;        // device BF16 copies per layer
+    std::vector<float *> bias;           // device padded FP32 bias per layer
+    std::vector<void *> owned;
+};
+
+namespace {
+
+int64_t rows_pad(int64_t rows) { return (rows + 63) / 64 * 64; }
+
+// Workspace carving: X/activations bf16 [rows_pad][Dmax] x (L+1), pre-activations f32
+// [rows_pad][Dmax] x L, output f32 [rows_pad][Dout], gradient scratch bf16 x 2.
+struct MlpWs {
+    std::vector<__bf16 *> H;   // H[0] = X, H[l] = activation of hidden layer l
+    std::vector<float *> Z;    // Z[l] pre-activation of hidden layer l (1-based, l = 1..L)
+    float *Y = nullptr;
+    __bf16 *G0 = nullptr, *G1 = nullptr;
+    float *loss = nullptr;
+};
+
+size_t carve(const tpf_mlp_s &M, int64_t rows, void *base, MlpWs *ws) {
+    const int64_t rp = rows_pad(rows);
+    int Dmax = 0;
+    for (int w : M.dp) Dmax = std::max(Dmax, w);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *ptr = base ? static_cast<char *>(base) + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return ptr;
+    };
+    const int L = M.layers;
+    if (ws) ws->H.assign(L + 1, nullptr), ws->Z.assign(L + 1, nullptr);
+    for (int l = 0; l <= L; ++l) {
+        char *q = take((size_t)rp * Dmax * 2);
+        if (ws) ws->H[l] = reinterpret_cast<__bf16 *>(q);
+    }
+    for (int l = 1; l <= L; ++l) {
+        char *q = take((size_t)rp * Dmax * 4);
+        if (ws) ws->Z[l] = reinterpret_cast<float *>(q);
+    }
+    char *y = take((size_t)rp * Dmax * 4);
+    char *g0 = take((size_t)rp * Dmax * 2);
+    char *g1 = take((size_t)rp * Dmax * 2);
+    char *ls = take(256);
+    if (ws) {
+        ws->Y = reinterpret_cast<float *>(y);
+        ws->G0 = reinterpret_cast<__bf16 *>(g0);
+        ws->G1 = reinterpret_cast<__bf16 *>(g1);
+        ws->loss = reinterpret_cast<float *>(ls);
+    }
+    return off;
+}
+
+int check_device(const tpf_mlp_s &M) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TPF_ERR_DEVICE, "hipGetDevice failed");
+    if (dev != M.device) return fail(TPF_ERR_INVALID_ARG, "the MLP handle belongs to another device");
+    return TPF_OK;
+}
+
+int last_launch(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(TPF_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return TPF_OK;
+}
+
+int sync_weights(tpf_mlp_s &M, hipStream_t st) {
+    for (int l = 0; l <= M.layers; ++l) {
+        hipLaunchKernelGGL(sync_kernel, dim3(grid_for((int64_t)M.dp[l] * M.dp[l + 1])), dim3(256), 0, st, M.p,
+                           M.woff[l], M.d[l], M.d[l + 1], M.dp[l], M.dp[l + 1], M.Wt[l], M.Wn[l], M.bias[l],
+                           M.boff[l]);
+    }
+    return last_launch("weight sync");
+}
+
+template <bool AK, bool BK, int EP>
+void gemm(const __bf16 *A, int64_t sam, int64_t sak, const __bf16 *B, int64_t sbk, int64_t sbn, int64_t Mrows,
+          int N, int K, const float *bias, float *Cf, __bf16 *Cb, int64_t ldc, const float *Z, int64_t ldz, int vm,
+          int vn, int64_t goff, hipStream_t st) {
+    hipLaunchKernelGGL((gemm_bf16_kernel<AK, BK, EP>), dim3((unsigned)(Mrows / 64), (unsigned)(N / 64)), dim3(256),
+                       0, st, A, sam, sak, B, sbk, sbn, K, bias, Cf, Cb, ldc, Z, ldz, vm, vn, goff);
+}
+
+template <typename IO>
+int forward(tpf_mlp_s &M, const IO *S, const int64_t *t, int64_t rows, const MlpWs &ws, hipStream_t st) {
+    const int64_t rp = rows_pad(rows);
+    int Dmax = 0;
+    for (int w : M.dp) Dmax = std::max(Dmax, w);
+    hipLaunchKernelGGL(features_kernel<IO>, dim3(grid_for(rp * M.dp[0])), dim3(256), 0, st, S, t, M.n, rows, rp,
+                       M.dp[0], ws.H[0]);
+    // H[0] is [rp][dp0] packed; later layers use row stride Dmax
+    for (int l = 0; l < M.layers; ++l) {
+        const int64_t lda = l == 0 ? M.dp[0] : Dmax;
+        gemm<true, true, EP_HIDDEN>(ws.H[l], lda, 1, M.Wt[l], 1, M.dp[l], rp, M.dp[l + 1], M.dp[l], M.bias[l],
+                                    ws.Z[l + 1], ws.H[l + 1], Dmax, nullptr, 0, 0, M.d[l + 1], 0, st);
+    }
+    const int L = M.layers;
+    const int64_t lda = L == 0 ? M.dp[0] : Dmax;
+    gemm<true, true, EP_OUT>(ws.H[L], lda, 1, M.Wt[L], 1, M.dp[L], rp, M.dp[L + 1], M.dp[L], M.bias[L], ws.Y, nullptr,
+                             Dmax, nullptr, 0, 0, 0, 0, st);
+    return last_launch("MLP forward");
+}
+
+template <typename IO>
+int loss_grad(tpf_mlp_s &M, const IO *S, const int64_t *t, const IO *V, int64_t rows, float *loss_out, float *gout,
+              const MlpWs &ws, hipStream_t st) {
+    int rc = forward(M, S, t, rows, ws, st);
+    if (rc != TPF_OK) return rc;
+    const int64_t rp = rows_pad(rows);
+    int Dmax = 0;
+    for (int w : M.dp) Dmax = std::max(Dmax, w);
+    const int L = M.layers;
+    hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, st, ws.loss, (int64_t)1);
+    // dY [rp][dp_{L+1}] (row stride Dmax) into G0
+    hipLaunchKernelGGL(output_grad_kernel<IO>, dim3(grid_for(rp * M.dp[L + 1])), dim3(256), 0, st, ws.Y,
+                       (int64_t)Dmax, V, M.n, rows, rp, M.dp[L + 1], M.vs_re, M.vs_im, ws.G0, ws.loss);
+    // output_grad writes packed [rp][dp_{L+1}]; keep that stride for the output layer
+    int64_t ldg = M.dp[L + 1];
+    __bf16 *Gc = ws.G0, *Gn = ws.G1;
+    for (int l = L; l >= 0; --l) {
+        const int in_p = M.dp[l], out_p = M.dp[l + 1];
+        const __bf16 *Hin = ws.H[l];
+        const int64_t ldh = l == 0 ? M.dp[0] : Dmax;
+        // dW_l [out][in] = dZ^T H : C[o][i] = sum_r dZ[r][o] H[r][i]
+        gemm<false, false, EP_DW>(Gc, 1, ldg, Hin, ldh, 1, out_p, in_p, (int)rp, nullptr, gout, nullptr, 0,
+                                  nullptr, 0, M.d[l + 1], M.d[l], M.woff[l], st);
+        hipLaunchKernelGGL(colsum_kernel, dim3(M.d[l + 1]), dim3(256), 0, st, Gc, rp, (int)ldg, M.d[l + 1],
+                           gout + M.boff[l]);
+        if (l > 0) {
+            // dZ_{l-1} = (dZ_l W_l) .* gelu'(Z_l-1) : C[r][i] = sum_o dZ[r][o] W[o][i]
+            gemm<true, false, EP_DGELU>(Gc, ldg, 1, M.Wt[l], in_p, 1, rp, in_p, out_p, nullptr, nullptr, Gn, Dmax,
+                                        ws.Z[l], Dmax, 0, M.d[l], 0, st);
+            std::swap(Gc, Gn);
+            ldg = Dmax;
+        }
+    }
+    if (loss_out)
+        (void)hipMemcpyAsync(loss_out, ws.loss, sizeof(float), hipMemcpyDeviceToDevice, st);
+    return last_launch("MLP backward");
+}
+
+}  // namespace
+
+extern "C" int tpf_mlp_create(int32_t n_pq, int32_t hidden, int32_t layers, const float *params, double vs_re,
+                              double vs_im, tpf_mlp *out) {
+    clear_error();
+    if (!out) return fail(TPF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_pq < 1 || hidden < 1 || layers < 0 || layers > 16 || hidden > 4096 || n_pq > 4096)
+        return fail(TPF_ERR_INVALID_ARG, "bad MLP sizes");
+    auto *M = new (std::nothrow) tpf_mlp_s();
+    if (!M) return fail(TPF_ERR_OOM, "host allocation failed");
+    if (hipGetDevice(&M->device) != hipSuccess) {
+        delete M;
+        return fail(TPF_ERR_DEVICE, "hipGetDevice failed (no GPU?)");
+    }
+    M->n = n_pq;
+    M->hidden = hidden;
+    M->layers = layers;
+    M->vs_re = vs_re;
+    M->vs_im = vs_im;
+    M->d.push_back(2 * n_pq + 4);
+    for (int l = 0; l < layers; ++l) M->d.push_back(hidden);
+    M->d.push_back(2 * n_pq);
+    for (int w : M->d) M->dp.push_back(padw(w));
+    int64_t o = 0;
+    for (int l = 0; l <= layers; ++l) {
+        M->woff.push_back(o);
+        o += (int64_t)M->d[l] * M->d[l + 1];
+        M->boff.push_back(o);
+        o += M->d[l + 1];
+    }
+    M->P = o;
+    auto dalloc = [&](void **ptr, size_t bytes) -> bool {
+        if (hipMalloc(ptr, bytes) != hipSuccess) return false;
+        M->owned.push_back(*ptr);
+        return true;
+    };
+    bool ok = dalloc((void **)&M->p, M->P * 4) && dalloc((void **)&M->m, M->P * 4) &&
+              dalloc((void **)&M->v, M->P * 4) && dalloc((void **)&M->grad, M->P * 4);
+    M->Wt.resize(layers + 1);
+    M->Wn.resize(layers + 1);
+    M->bias.resize(layers + 1);
+    for (int l = 0; ok && l <= layers; ++l)
+        ok = dalloc((void **)&M->Wt[l], (size_t)M->dp[l] * M->dp[l + 1] * 2) &&
+             dalloc((void **)&M->Wn[l], (size_t)M->dp[l] * M->dp[l + 1] * 2) &&
+             dalloc((void **)&M->bias[l], (size_t)M->dp[l + 1] * 4);
+    if (!ok) {
+        tpf_mlp_free(M);
+        return fail(TPF_ERR_OOM, "device allocation failed (MLP)");
+    }
+    std::vector<float> host(M->P, 0.0f);
+    if (params) std::memcpy(host.data(), params, M->P * 4);
+    std::vector<float> zeros(M->P, 0.0f);
+    if (hipMemcpy(M->p, host.data(), M->P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(M->m, zeros.data(), M->P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(M->v, zeros.data(), M->P * 4, hipMemcpyHostToDevice) != hipSuccess) {
+        tpf_mlp_free(M);
+        return fail(TPF_ERR_DEVICE, "host-to-device copy failed (MLP)");
+    }
+    int rc = sync_weights(*M, nullptr);
+    if (rc == TPF_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(TPF_ERR_DEVICE, "MLP init failed");
+    if (rc != TPF_OK) {
+        tpf_mlp_free(M);
+        return rc;
+    }
+    *out = M;
+    return TPF_OK;
+}
+
+extern "C" void tpf_mlp_free(tpf_mlp M) {
+    if (!M) return;
+    for (void *ptr : M->owned) (void)hipFree(ptr);
+    delete M;
+}
+
+extern "C" int64_t tpf_mlp_num_params(tpf_mlp M) { return M ? M->P : fail(TPF_ERR_INVALID_ARG, "mlp is NULL"); }
+
+extern "C" int tpf_mlp_get_params(tpf_mlp M, float *params_out) {
+    clear_error();
+    if (!M || !params_out) return fail(TPF_ERR_INVALID_ARG, "NULL argument");
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(params_out, M->p, M->P * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(TPF_ERR_DEVICE, "device-to-host copy failed");
+    return TPF_OK;
+}
+
+extern "C" int tpf_mlp_set_params(tpf_mlp M, const float *params) {
+    clear_error();
+    if (!M || !params) return fail(TPF_ERR_INVALID_ARG, "NULL argument");
+    int rc = check_device(*M);
+    if (rc != TPF_OK) return rc;
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(M->p, params, M->P * 4, hipMemcpyHostToDevice) != hipSuccess)
+        return fail(TPF_ERR_DEVICE, "host-to-device copy failed");
+    rc = sync_weights(*M, nullptr);
+    if (rc == TPF_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(TPF_ERR_DEVICE, "weight sync failed");
+    return rc;
+}
+
+extern "C" size_t tpf_mlp_workspace_bytes(tpf_mlp M, int64_t rows) {
+    if (!M || rows < 0) return 0;
+    return carve(*M, std::max<int64_t>(rows, 1), nullptr, nullptr);
+}
+
+static int mlp_args(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t, int64_t rows, void *ws, size_t wsb) {
+    if (!M) return fail(TPF_ERR_INVALID_ARG, "mlp is NULL");
+    if (dtype != TPF_C64 && dtype != TPF_C128) return fail(TPF_ERR_INVALID_ARG, "bad dtype");
+    if (rows < 0 || rows > ((int64_t)1 << 31)) return fail(TPF_ERR_INVALID_ARG, "bad row count");
+    if (rows > 0 && (!S || !t)) return fail(TPF_ERR_INVALID_ARG, "NULL array");
+    if (rows > 0 && (!ws || wsb < tpf_mlp_workspace_bytes(M, rows)))
+        return fail(TPF_ERR_INVALID_ARG, "workspace missing or smaller than tpf_mlp_workspace_bytes()");
+    return check_device(*M);
+}
+
+extern "C" int tpf_mlp_loss_grad(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t_index, const void *V,
+                                 int64_t rows, float *loss_out, float *grad_out, void *workspace,
+                                 size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = mlp_args(M, S, dtype, t_index, rows, workspace, workspace_bytes);
+    if (rc != TPF_OK) return rc;
+    if (rows == 0) return fail(TPF_ERR_INVALID_ARG, "a gradient needs at least one row");
+    if (!V || !grad_out) return fail(TPF_ERR_INVALID_ARG, "NULL array");
+    MlpWs ws;
+    carve(*M, rows, workspace, &ws);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (dtype == TPF_C128)
+        return loss_grad(*M, (const double *)S, t_index, (const double *)V, rows, loss_out, grad_out, ws, st);
+    return loss_grad(*M, (const float *)S, t_index, (const float *)V, rows, loss_out, grad_out, ws, st);
+}
+
+extern "C" int tpf_mlp_train_step(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t_index, const void *V,
+                                  int64_t rows, float lr, float weight_decay, float *loss_out, void *workspace,
+                                  size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (!(lr >= 0.0f) || !(weight_decay >= 0.0f)) return fail(TPF_ERR_INVALID_ARG, "lr and weight_decay must be >= 0");
+    int rc = tpf_mlp_loss_grad(M, S, dtype, t_index, V, rows, loss_out, M ? M->grad : nullptr, workspace,
+                               workspace_bytes, stream);
+    if (rc != TPF_OK) return rc;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    M->step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float bc1 = 1.0f - (float)std::pow((double)b1, (double)M->step);
+    const float bc2 = 1.0f - (float)std::pow((double)b2, (double)M->step);
+    hipLaunchKernelGGL(adamw_kernel, dim3(grid_for(M->P)), dim3(256), 0, st, M->p, M->grad, M->m, M->v, M->P, lr,
+                       weight_decay, b1, b2, 1e-8f, bc1, bc2);
+    rc = last_launch("AdamW");
+    if (rc != TPF_OK) return rc;
+    return sync_weights(*M, st);
+}
+
+extern "C" int tpf_mlp_predict(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t_index, int64_t rows,
+                               void *V0_out, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = mlp_args(M, S, dtype, t_index, rows, workspace, workspace_bytes);
+    if (rc != TPF_OK) return rc;
+    if (rows == 0) return TPF_OK;
+    if (!V0_out) return fail(TPF_ERR_INVALID_ARG, "NULL array");
+    MlpWs ws;
+    carve(*M, rows, workspace, &ws);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    int Dmax = 0;
+    for (int w : M->dp) Dmax = std::max(Dmax, w);
+    if (dtype == TPF_C128) {
+        rc = forward(*M, (const double *)S, t_index, rows, ws, st);
+        if (rc == TPF_OK)
+            hipLaunchKernelGGL(predict_out_kernel<double>, dim3(grid_for(rows * M->n)), dim3(256), 0, st, ws.Y,
+                               (int64_t)Dmax, M->n, rows, M->vs_re, M->vs_im, (double *)V0_out);
+    } else {
+        rc = forward(*M, (const float *)S, t_index, rows, ws, st);
+        if (rc == TPF_OK)
+            hipLaunchKernelGGL(predict_out_kernel<float>, dim3(grid_for(rows * M->n)), dim3(256), 0, st, ws.Y,
+                               (int64_t)Dmax, M->n, rows, M->vs_re, M->vs_im, (float *)V0_out);
+    }
+    if (rc != TPF_OK) return rc;
+    return last_launch("MLP predict");
+}
+
+namespace {
+struct MlpFileHeader {
+    char magic[8];
+    int32_t n, hidden, layers, reserved;
+    double vs_re, vs_im;
+    int64_t step, P;
+};
+}  // namespace
+
+extern "C" int tpf_mlp_save(tpf_mlp M, const char *path) {
+    clear_error();
+    if (!M || !path) return fail(TPF_ERR_INVALID_ARG, "NULL argument");
+    std::vector<float> host(M->P);
+    int rc = tpf_mlp_get_params(M, host.data());
+    if (rc != TPF_OK) return rc;
+    MlpFileHeader h{};
+    std::memcpy(h.magic, "TPFMLP01", 8);
+    h.n = M->n;
+    h.hidden = M->hidden;
+    h.layers = M->layers;
+    h.vs_re = M->vs_re;
+    h.vs_im = M->vs_im;
+    h.step = M->step;
+    h.P = M->P;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return fail(TPF_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    const bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 && std::fwrite(host.data(), 4, M->P, f) == (size_t)M->P;
+    std::fclose(f);
+    return ok ? TPF_OK : fail(TPF_ERR_INVALID_ARG, std::string("write failed: ") + path);
+}
+
+extern "C" int tpf_mlp_load(const char *path, tpf_mlp *out) {
+    clear_error();
+    if (!path || !out) return fail(TPF_ERR_INVALID_ARG, "NULL argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return fail(TPF_ERR_INVALID_ARG, std::string("cannot open ") + path);
+    MlpFileHeader h{};
+    bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, "TPFMLP01", 8) == 0 && h.P > 0 &&
+              h.P < ((int64_t)1 << 31);
+    std::vector<float> host(ok ? h.P : 0);
+    ok = ok && std::fread(host.data(), 4, h.P, f) == (size_t)h.P;
+    std::fclose(f);
+    if (!ok) return fail(TPF_ERR_INVALID_ARG, std::string("not a warm-start parameter file: ") + path);
+    int rc = tpf_mlp_create(h.n, h.hidden, h.layers, host.data(), h.vs_re, h.vs_im, out);
+    if (rc != TPF_OK) return rc;
+    if ((*out)->P != h.P) {
+        tpf_mlp_free(*out);
+        *out = nullptr;
+        return fail(TPF_ERR_INVALID_ARG, "parameter count mismatch");
+    }
+    (*out)->step = h.step;
+    return TPF_OK;
+}

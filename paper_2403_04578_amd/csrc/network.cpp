@@ -77,6 +77,29 @@ static void lu_solve(const std::vector<cd> &lu, const std::vector<int> &piv, int
 // one lane.
 static inline int blk_pos(int q, int part) { return 16 * (q / 8) + 8 * part + (q % 8); }
 
+// Order of the FP32-family kernels: Re/Im of a bus on adjacent tile rows so that
+// the 16x16 output layout (rows 4g..4g+3 in lane group g) keeps a bus in one lane.
+static inline int blk_pos32(int q, int part) { return 16 * (q / 8) + 2 * (q % 8) + part; }
+
+static uint16_t to_bf16(float f) {  // round to nearest even
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+static uint16_t to_f16(float f) {
+    _Float16 h = (_Float16)f;
+    uint16_t u;
+    std::memcpy(&u, &h, 2);
+    return u;
+}
+static float from_f16(uint16_t u) {
+    _Float16 h;
+    std::memcpy(&h, &u, 2);
+    return (float)h;
+}
+
 static int upload(tpf_network_s &net, DeviceNet &dn) {
     const int n = net.n;
     auto dalloc = [&](void **p, size_t bytes) -> bool {
@@ -126,6 +149,56 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
         if (!dalloc((void **)&dn.A64, frag.size() * 8) || !dalloc((void **)&dn.w64, wv.size() * 8))
             return fail(TPF_ERR_OOM, "device allocation failed (network staging)");
         if (!h2d(dn.A64, frag.data(), frag.size() * 8) || !h2d(dn.w64, wv.data(), wv.size() * 8))
+            return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
+    }
+    // ---- FP32-family fragments (FP32 and mixed modes)
+    if (n <= 8 * 16) {
+        const int MT = dn.MT, M = 16 * MT, KT = 4 * MT, NW = dn.NW, TPW = dn.TPW;
+        const int KTL = (MT + 1) / 2, KL = 32 * KTL;
+        dn.KTL = KTL;
+        std::vector<double> Ab((size_t)M * KL, 0.0);
+        double zmax = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int k = 0; k < n; ++k) {
+                const cd z = net.Z[(size_t)i * n + k];
+                Ab[(size_t)blk_pos32(i, 0) * KL + blk_pos32(k, 0)] = z.real();
+                Ab[(size_t)blk_pos32(i, 0) * KL + blk_pos32(k, 1)] = -z.imag();
+                Ab[(size_t)blk_pos32(i, 1) * KL + blk_pos32(k, 0)] = z.imag();
+                Ab[(size_t)blk_pos32(i, 1) * KL + blk_pos32(k, 1)] = z.real();
+                zmax = std::max(zmax, std::max(std::abs(z.real()), std::abs(z.imag())));
+            }
+        // FP16 operands carry Z 2^sZ with the largest entry just below 2^14.
+        int e = 0;
+        (void)std::frexp(zmax > 0 ? zmax : 1.0, &e);
+        dn.sZ = 14 - e;
+        const int KP = KT + kFragPadSteps;
+        std::vector<float> f32((size_t)NW * KP * TPW * 64, 0.0f);
+        const size_t nl = (size_t)NW * TPW * KTL * 64 * 8;
+        std::vector<uint16_t> fbf(nl, 0), fh(nl, 0), fl(nl, 0);
+        for (int tw = 0; tw < NW; ++tw)
+            for (int q = 0; q < TPW; ++q) {
+                const int mt = tw + NW * q;
+                if (mt >= MT) continue;
+                for (int l = 0; l < 64; ++l) {
+                    const int row = 16 * mt + (l % 16), kk = l / 16;
+                    for (int kt = 0; kt < KT; ++kt)
+                        f32[(((size_t)tw * KP + kt) * TPW + q) * 64 + l] = (float)Ab[(size_t)row * KL + 4 * kt + kk];
+                    for (int kt = 0; kt < KTL; ++kt)
+                        for (int x = 0; x < 8; ++x) {
+                            const double a = Ab[(size_t)row * KL + 32 * kt + 8 * kk + x];
+                            const size_t idx = ((((size_t)tw * TPW + q) * KTL + kt) * 64 + l) * 8 + x;
+                            fbf[idx] = to_bf16((float)a);
+                            const float as = (float)std::ldexp(a, dn.sZ);
+                            fh[idx] = to_f16(as);
+                            fl[idx] = to_f16(as - from_f16(fh[idx]));
+                        }
+                }
+            }
+        if (!dalloc((void **)&dn.A32, f32.size() * 4) || !dalloc((void **)&dn.Abf, nl * 2) ||
+            !dalloc((void **)&dn.Ah, nl * 2) || !dalloc((void **)&dn.Al, nl * 2))
+            return fail(TPF_ERR_OOM, "device allocation failed (network staging)");
+        if (!h2d(dn.A32, f32.data(), f32.size() * 4) || !h2d(dn.Abf, fbf.data(), nl * 2) ||
+            !h2d(dn.Ah, fh.data(), nl * 2) || !h2d(dn.Al, fl.data(), nl * 2))
             return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
     }
     // ---- CSR Y_dd and c = Y_ds v_s (FP64 mismatch)

@@ -36,6 +36,15 @@ struct DeviceNet {
     int NW = 0, TPW = 0;         // workgroup shape (rows_config)
     double *A64 = nullptr;       // FP64 MFMA A fragments, [NW roles][4*MT+pad k-steps][TPW tiles][64 lanes]
     double *w64 = nullptr;       // [2][8*MT]: Re w then Im w per bus (padding buses: 1, 0)
+    // FP32-family kernels (FP32 and mixed modes), n <= 128.  Rows/cols use the order
+    // of the FP32/BF16/FP16 MFMA output (lane group g holds tile rows 4g..4g+3):
+    // row 16 t + 2 (q % 8) + part for PQ bus q = 8 t + (q % 8).
+    int KTL = 0;                 // 32-wide k-steps of the 16-bit products (K padded to 32 KTL)
+    int sZ = 0;                  // power-of-two scale of Z in the FP16 operands
+    float *A32 = nullptr;        // FP32 fragments, [NW][4*MT+pad][TPW][64]
+    uint16_t *Abf = nullptr;     // BF16 fragments, [NW][TPW][KTL][64][8]
+    uint16_t *Ah = nullptr;      // FP16 fragments of Z 2^sZ, [NW][TPW][KTL][64][8]
+    uint16_t *Al = nullptr;      // FP16 residual Z 2^sZ - Ah, same layout
     // Sparse Y_dd (CSR) and c = Y_ds v_s for the FP64 mismatch.
     int32_t *rowptr = nullptr;   // [n+1]
     int32_t *colidx = nullptr;   // [nnz]
@@ -75,6 +84,9 @@ int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const vo
                          int64_t tau, double tol, int max_iter, const void *V0, void *V,
                          int32_t *iters, int8_t *status, unsigned long long *queue,
                          hipStream_t stream);
+int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype,
+                     int64_t tau, double tol, int max_iter, const void *V0, void *V, int32_t *iters,
+                     int8_t *status, unsigned long long *queue, hipStream_t stream);
 int launch_start_only(int n, const void *V0, int dtype, int64_t tau, void *V, int32_t *iters,
                       int8_t *status, hipStream_t stream);
 int launch_mismatch_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, const void *V,

@@ -210,3 +210,19 @@ def scenario_loads(feeder: Feeder, n_scen: int = 1000, hours: int = HOURS_PER_YE
     bell = np.where((hday >= 6) & (hday <= 18), np.maximum(0.0, np.sin(math.pi * (hday - 6.0) / 12.0)), 0.0)
     PV = bell[:, None] * cap[None, :]
     return ScenarioLoads(c, L, PV)
+
+
+def mlp_sizes(n_pq: int, hidden: int = 256, layers: int = 3):
+    """Layer widths of the warm-start network: 2 n + 4 inputs, `layers` hidden layers, 2 n outputs."""
+    return [2 * n_pq + 4] + [hidden] * layers + [2 * n_pq]
+
+
+def mlp_init_params(sizes, seed: int = SEED_TRAIN) -> np.ndarray:
+    """Seeded initial parameters, flat [W_1 (out x in), b_1, W_2, b_2, ...] in float32:
+    W ~ N(0, 1/fan_in), b = 0."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        parts.append(rng.normal(0.0, 1.0 / math.sqrt(a), (b, a)).ravel())
+        parts.append(np.zeros(b))
+    return np.concatenate(parts).astype(np.float32)
