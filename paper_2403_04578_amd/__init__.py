@@ -66,6 +66,18 @@ def load_library() -> ctypes.CDLL:
         "tpf_solve_tensor": (ctypes.c_int, [P, P, I32, I64, I64, D, I32, P, P, P, P, P, ctypes.c_size_t, P]),
         "tpf_mismatch": (ctypes.c_int, [P, P, P, I32, I64, P, P]),
         "tpf_last_error": (ctypes.c_char_p, []),
+        "tpf_mlp_create": (ctypes.c_int, [I32, I32, I32, P, D, D, ctypes.POINTER(P)]),
+        "tpf_mlp_free": (None, [P]),
+        "tpf_mlp_num_params": (I64, [P]),
+        "tpf_mlp_get_params": (ctypes.c_int, [P, P]),
+        "tpf_mlp_set_params": (ctypes.c_int, [P, P]),
+        "tpf_mlp_workspace_bytes": (ctypes.c_size_t, [P, I64]),
+        "tpf_mlp_loss_grad": (ctypes.c_int, [P, P, I32, P, P, I64, P, P, P, ctypes.c_size_t, P]),
+        "tpf_mlp_train_step": (ctypes.c_int, [P, P, I32, P, P, I64, ctypes.c_float, ctypes.c_float, P, P,
+                                              ctypes.c_size_t, P]),
+        "tpf_mlp_predict": (ctypes.c_int, [P, P, I32, P, I64, P, P, ctypes.c_size_t, P]),
+        "tpf_mlp_save": (ctypes.c_int, [P, ctypes.c_char_p]),
+        "tpf_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(P)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -238,3 +250,136 @@ def mismatch(net: Network, S, V):
                               _stream_ptr(S.device))
     _check(rc)
     return out
+
+
+class WarmStart:
+    """Learned warm start (multilayer perceptron, trained and run by libtpf kernels).
+
+    Maps a time step's loads and minute index to an estimate of its converged
+    voltages; pass the result of :meth:`predict` as ``V0`` to the solve calls.
+    Parameters: flat float32 [W_1 (out x in), b_1, ...]; see include/tpf.h.
+    """
+
+    def __init__(self, n_pq: int, hidden: int = 256, layers: int = 3, params=None, vs: complex = 1.0 + 0.0j,
+                 _handle=None):
+        lib = load_library()
+        if _handle is not None:
+            self._h = _handle
+        else:
+            h = ctypes.c_void_p()
+            pp = None
+            if params is not None:
+                self._init = np.ascontiguousarray(params, np.float32)
+                pp = self._init.ctypes.data
+            _check(lib.tpf_mlp_create(int(n_pq), int(hidden), int(layers), pp, float(np.real(vs)),
+                                      float(np.imag(vs)), ctypes.byref(h)))
+            self._h = h
+        self.n = int(n_pq)
+        self.num_params = int(lib.tpf_mlp_num_params(self._h))
+        self._ws = None
+
+    def _workspace(self, rows, device):
+        torch = _torch()
+        need = int(load_library().tpf_mlp_workspace_bytes(self._h, int(rows)))
+        if self._ws is None or self._ws.numel() < need or self._ws.device != device:
+            self._ws = torch.empty(max(need, 256), dtype=torch.uint8, device=device)
+        return self._ws
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.num_params, np.float32)
+        _check(load_library().tpf_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, np.float32)
+        if p.size != self.num_params:
+            raise ValueError("wrong parameter count")
+        _check(load_library().tpf_mlp_set_params(self._h, p.ctypes.data))
+
+    @staticmethod
+    def _rows(S, t_index):
+        if S.dim() != 2 or not S.is_contiguous() or not t_index.is_contiguous():
+            raise ValueError("S must be a contiguous [rows, n] tensor")
+        torch = _torch()
+        if t_index.dtype != torch.int64 or t_index.numel() != S.shape[0]:
+            raise ValueError("t_index must be int64 [rows]")
+        return S.shape[0]
+
+    def loss_grad(self, S, t_index, V):
+        """(loss [1], grad [num_params]) float32 device tensors for one batch."""
+        torch = _torch()
+        rows = self._rows(S, t_index)
+        loss = torch.zeros(1, dtype=torch.float32, device=S.device)
+        grad = torch.zeros(self.num_params, dtype=torch.float32, device=S.device)
+        ws = self._workspace(rows, S.device)
+        with torch.cuda.device(S.device):
+            _check(load_library().tpf_mlp_loss_grad(self._h, S.data_ptr(), _dtype_code(S), t_index.data_ptr(),
+                                                    V.data_ptr(), rows, loss.data_ptr(), grad.data_ptr(),
+                                                    ws.data_ptr(), ws.numel(), _stream_ptr(S.device)))
+        return loss, grad
+
+    def train_step(self, S, t_index, V, lr: float, weight_decay: float = 1e-4):
+        torch = _torch()
+        rows = self._rows(S, t_index)
+        loss = torch.zeros(1, dtype=torch.float32, device=S.device)
+        ws = self._workspace(rows, S.device)
+        with torch.cuda.device(S.device):
+            _check(load_library().tpf_mlp_train_step(self._h, S.data_ptr(), _dtype_code(S), t_index.data_ptr(),
+                                                     V.data_ptr(), rows, float(lr), float(weight_decay),
+                                                     loss.data_ptr(), ws.data_ptr(), ws.numel(),
+                                                     _stream_ptr(S.device)))
+        return loss
+
+    def predict(self, S, t_index, out=None):
+        """V0 [rows, n] (same dtype as S) for the solve calls' warm start."""
+        torch = _torch()
+        rows = self._rows(S, t_index)
+        V0 = torch.empty_like(S) if out is None else out
+        ws = self._workspace(rows, S.device)
+        with torch.cuda.device(S.device):
+            _check(load_library().tpf_mlp_predict(self._h, S.data_ptr(), _dtype_code(S), t_index.data_ptr(), rows,
+                                                  V0.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(S.device)))
+        return V0
+
+    def fit(self, S, t_index, V, epochs: int = 10, batch: int = 1024, lr: float = 1e-3, lr_min: float = 1e-5,
+            weight_decay: float = 1e-4, seed: int = 0):
+        """Mini-batch AdamW with a cosine learning-rate schedule; returns the mean loss per epoch."""
+        torch = _torch()
+        rows = S.shape[0]
+        nb = max(1, rows // batch)
+        total = epochs * nb
+        gen = torch.Generator(device="cpu").manual_seed(seed)
+        hist = []
+        k = 0
+        for _ in range(epochs):
+            perm = torch.randperm(rows, generator=gen).to(S.device)
+            acc = torch.zeros(1, dtype=torch.float32, device=S.device)
+            for b in range(nb):
+                idx = perm[b * batch:(b + 1) * batch]
+                rate = lr_min + 0.5 * (lr - lr_min) * (1 + np.cos(np.pi * k / max(1, total - 1)))
+                acc += self.train_step(S[idx].contiguous(), t_index[idx].contiguous(), V[idx].contiguous(),
+                                       rate, weight_decay)
+                k += 1
+            hist.append(float(acc) / nb)
+        return hist
+
+    def save(self, path: str):
+        _check(load_library().tpf_mlp_save(self._h, path.encode()))
+
+    @classmethod
+    def load(cls, path: str) -> "WarmStart":
+        lib = load_library()
+        h = ctypes.c_void_p()
+        _check(lib.tpf_mlp_load(path.encode(), ctypes.byref(h)))
+        obj = cls.__new__(cls)
+        obj._h = h
+        obj.num_params = int(lib.tpf_mlp_num_params(h))
+        obj._ws = None
+        obj.n = None
+        return obj
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.tpf_mlp_free(h)
+            self._h = None

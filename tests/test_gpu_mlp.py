@@ -1,0 +1,137 @@
+"""GPU checks of the learned warm start against the FP64 reference (oracle/mlp_ref.py).
+
+The GPU network computes its products in BF16 with FP32 accumulation and keeps
+FP32 master parameters.  The reference is evaluated with the parameters and the
+input features rounded to BF16 exactly as the GPU stores them, so what remains
+is the BF16 rounding of the hidden activations: about 2^-9 relative per layer,
+hence the 3e-2 bound on the relative L2 error of the gradient below.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import mlp_ref as M
+import paper_2403_04578_amd as tpf
+from paper_2403_04578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def bf16_round(a):
+    t = torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.bfloat16).to(torch.float32)
+    return t.numpy().astype(np.float64)
+
+
+def _ref_params(params, sizes):
+    """Weights rounded to BF16 (as the GPU copies are), biases kept FP32."""
+    out = np.array(params, np.float64)
+    o = 0
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        out[o:o + a * b] = bf16_round(params[o:o + a * b])
+        o += a * b + b
+    return out
+
+
+@pytest.fixture(scope="module")
+def data(gpu):
+    f = W.make_feeder(100)
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    T = 6000
+    S = W.profile_minute_year(f, steps=T, seed=W.SEED_TRAIN)
+    t = np.arange(T, dtype=np.int64) * 83 % W.MINUTES_PER_YEAR
+    Sd = torch.from_numpy(S).to(gpu)
+    V, it, st = tpf.solve_timeseries(net, Sd, tol=1e-10, max_iter=100)
+    return f, net, onet, S, t, Sd, torch.from_numpy(t).to(gpu), V
+
+
+def test_loss_and_gradient_match_reference(data):
+    f, net, onet, S, t, Sd, td, V = data
+    sizes = W.mlp_sizes(99)
+    p0 = W.mlp_init_params(sizes, seed=11)
+    mlp = tpf.WarmStart(99, params=p0)
+    rows = 200
+    loss, grad = mlp.loss_grad(Sd[:rows].contiguous(), td[:rows].contiguous(), V[:rows].contiguous())
+    g = grad.cpu().numpy().astype(np.float64)
+    x = bf16_round(M.features(S[:rows], t[:rows]))
+    tgt = M.targets(V[:rows].cpu().numpy())
+    lref, gref = M.loss_and_grad(_ref_params(p0, sizes), sizes, x, tgt)
+    assert abs(float(loss) - lref) <= 1e-2 * lref
+    rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
+    assert rel < 3e-2, rel
+    # every layer's weight and bias gradient points the same way
+    o = 0
+    for a, b in zip(sizes[:-1], sizes[1:]):
+        for seg in (slice(o, o + a * b), slice(o + a * b, o + a * b + b)):
+            cos = g[seg] @ gref[seg] / (np.linalg.norm(g[seg]) * np.linalg.norm(gref[seg]) + 1e-30)
+            assert cos > 0.999, (a, b, cos)
+        o += a * b + b
+
+
+def test_adamw_step_matches_reference(data):
+    f, net, onet, S, t, Sd, td, V = data
+    sizes = W.mlp_sizes(99)
+    p0 = W.mlp_init_params(sizes, seed=12)
+    mlp = tpf.WarmStart(99, params=p0)
+    Sb, tb, Vb = Sd[:256].contiguous(), td[:256].contiguous(), V[:256].contiguous()
+    _, grad = mlp.loss_grad(Sb, tb, Vb)
+    mlp.train_step(Sb, tb, Vb, lr=1e-3, weight_decay=1e-2)
+    p1 = mlp.get_params().astype(np.float64)
+    ref, _, _ = M.adamw_step(p0.astype(np.float64), grad.cpu().numpy().astype(np.float64),
+                             np.zeros(p0.size), np.zeros(p0.size), 1, lr=1e-3, wd=1e-2)
+    assert np.abs(p1 - ref).max() < 2e-6
+
+
+def test_prediction_matches_reference_forward(data):
+    f, net, onet, S, t, Sd, td, V = data
+    sizes = W.mlp_sizes(99)
+    p0 = W.mlp_init_params(sizes, seed=13)
+    mlp = tpf.WarmStart(99, params=p0)
+    rows = 130  # not a multiple of the 64-row tile
+    V0 = mlp.predict(Sd[:rows].contiguous(), td[:rows].contiguous())
+    y, _ = M.forward(_ref_params(p0, sizes), sizes, bf16_round(M.features(S[:rows], t[:rows])))
+    ref = M.to_voltage(y)
+    err = np.abs(V0.cpu().numpy() - ref).max()
+    assert err < 5e-3 * max(1.0, np.abs(y).max() / 20), err
+
+
+def test_training_reduces_sweeps_and_keeps_results(data, tmp_path):
+    """What the trained network gains: fewer sweeps from its start than from a flat
+    start, to the same solution."""
+    f, net, onet, S, t, Sd, td, V = data
+    sizes = W.mlp_sizes(99)
+    mlp = tpf.WarmStart(99, params=W.mlp_init_params(sizes))
+    ntr = 5000
+    hist = mlp.fit(Sd[:ntr].contiguous(), td[:ntr].contiguous(), V[:ntr].contiguous(), epochs=30, batch=500,
+                   lr=2e-3)
+    assert hist[-1] < 0.05 * hist[0], hist
+    Sv, tv = Sd[ntr:].contiguous(), td[ntr:].contiguous()
+    V0 = mlp.predict(Sv, tv)
+    start_err = float((V0 - V[ntr:]).abs().max())
+    assert start_err < 5e-3
+    for mode in ("fp64", "mixed_fp16"):
+        tol = 1e-6
+        Vw, iw, sw = tpf.solve_timeseries(net, Sv, tol, 100, mode=mode, V0=V0)
+        Vf, i_f, sf = tpf.solve_timeseries(net, Sv, tol, 100, mode=mode)
+        assert int(sw.max()) == tpf.ST_CONVERGED
+        assert float(iw.float().mean()) < float(i_f.float().mean()) - 0.5, mode
+        assert float((Vw - V[ntr:]).abs().max()) < 1e-6
+    # save / load round trip keeps the parameters and the prediction
+    path = str(tmp_path / "ws.bin")
+    mlp.save(path)
+    m2 = tpf.WarmStart.load(path)
+    assert np.array_equal(m2.get_params(), mlp.get_params())
+    assert torch.equal(m2.predict(Sv, tv), V0)
+
+
+def test_nonfinite_parameters_fall_back_to_flat_start(data):
+    f, net, onet, S, t, Sd, td, V = data
+    sizes = W.mlp_sizes(99)
+    bad = np.full(M.num_params(sizes), np.nan, np.float32)
+    mlp = tpf.WarmStart(99, params=bad)
+    Sv, tv = Sd[:300].contiguous(), td[:300].contiguous()
+    V0 = mlp.predict(Sv, tv)
+    assert torch.isnan(V0).all()
+    Vw, iw, sw = tpf.solve_timeseries(net, Sv, 1e-8, 100, V0=V0)
+    Vf, i_f, sf = tpf.solve_timeseries(net, Sv, 1e-8, 100)
+    assert torch.equal(Vw, Vf) and torch.equal(iw, i_f)
