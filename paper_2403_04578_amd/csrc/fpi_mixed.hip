@@ -31,6 +31,10 @@
 // that one refine sweep serves the whole batch.
 #include "tpf_internal.h"
 
+#ifndef TPF_MIXED_CG
+#define TPF_MIXED_CG 2
+#endif
+
 namespace tpf {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -84,48 +88,93 @@ __device__ __forceinline__ float amax4(const f4 &x) {
     return fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3])));
 }
 
-template <int TPW, int NW, int KTL, int MODE, typename IO>
+// Largest |mismatch| over the lane's buses of a retiring column whose drops U sit in
+// LDS row `uc` (FP32-family order).
+template <typename IO>
+__device__ __forceinline__ double retired_mismatch(const MismatchArgs mm, const IO *__restrict__ S,
+                                                const double *__restrict__ wv, const float *uc, long long col, int n,
+                                                int MT, int tw, int NW, int nv, int g) {
+    auto vk = [&](int k, double &xr, double &xi) {
+        const int r = 16 * (k >> 3) + 2 * (k & 7);
+        xr = (double)(IO)(wv[k] + (double)uc[r]);
+        xi = (double)(IO)(wv[8 * MT + k] + (double)uc[r + 1]);
+    };
+    double worst = 0.0;
+    for (int q = 0; q < nv; ++q)
+        for (int h = 0; h < 2; ++h) {
+            const int b = 8 * (tw + NW * q) + 2 * g + h;
+            if (b < n) {
+                double sr, si, vr, vi;
+                ldc(S + 2 * (col * n + b), sr, si);
+                vk(b, vr, vi);
+                worst = nanmax_d(worst, bus_mismatch(mm, b, sr, si, vr, vi, vk));
+            }
+        }
+    return worst;
+}
+
+// Per-column state of a batch, double-buffered in LDS by sweep parity.  Every
+// wave evaluates the same update for the columns of its lanes; wave 0 stores it.
+struct ColState {
+    long long col;  // -1 when the slot is idle
+    float dprev, sumd, uref;
+    int it, ph, want, wait;
+};
+
+template <int TPW, int NW, int KTL, int MODE, int CG, typename IO>
 __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const float *__restrict__ A32,
     const uint16_t *__restrict__ Alow, const uint16_t *__restrict__ Alo, const double *__restrict__ wv, int n,
-    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue) {
+    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue,
+    const MismatchArgs mm) {
     using L = LowOps<MODE>;
     typedef typename L::frag frag;
     typedef typename L::quad quad;
     constexpr bool kMixed = MODE != TPF_MODE_FP32;
     constexpr bool kSplit = MODE == TPF_MODE_MIXED_FP16;
     constexpr bool kF32Refine = !kSplit;
-    constexpr int KPL = 32 * KTL + 8;  // 16-bit B row stride (halves)
-    const int KP32 = 16 * MT + 4;      // FP32 B row stride (floats)
+    constexpr bool kScaled = MODE == TPF_MODE_MIXED_FP16;  // FP16 operands need a power-of-two scale
+    constexpr int NC = 16 * CG;
+    constexpr int NT = NW * 64;
+    constexpr int KPL = 32 * KTL + 8;
+    const int KP32 = 16 * MT + 4;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    float *B32 = reinterpret_cast<float *>(smem);                             // [16][KP32]
-    uint16_t *Bh = reinterpret_cast<uint16_t *>(B32 + (kF32Refine ? 16 * KP32 : 0));  // [16][KPL]
-    uint16_t *Bl = Bh + 16 * KPL;                                             // [16][KPL] (FP16 split)
-    float *pd = reinterpret_cast<float *>(Bl + (kSplit ? 16 * KPL : 0));      // [NW][16] max |dU|^2
-    float *pu = pd + NW * 16;                                                 // [NW][16] max |U|
-    float *pm = pu + NW * 16;                                                 // [NW][16] max |B|
-    int *pb = reinterpret_cast<int *>(pm + NW * 16);                          // [NW][16] flags
-    float *wl = reinterpret_cast<float *>(pb + NW * 16);                      // [2][8 MT]
-    unsigned long long *qb = reinterpret_cast<unsigned long long *>(wl + 16 * MT + 2);
+    float *B32 = reinterpret_cast<float *>(smem);                                     // [NC][KP32]
+    uint16_t *Bh = reinterpret_cast<uint16_t *>(B32 + NC * KP32);                       // [NC][KPL]
+    uint16_t *Bl = Bh + (kMixed ? NC * KPL : 0);                                      // [NC][KPL]
+    f4 *Sx = reinterpret_cast<f4 *>(Bl + (kSplit ? NC * KPL : 0));                    // [CG*TPW][NT]
+    float *rmax = reinterpret_cast<float *>(Sx + CG * TPW * NT);                      // [2][2][NC]
+    int *rbad = reinterpret_cast<int *>(rmax + 4 * NC);                               // [2][NC]
+    float *rsm = reinterpret_cast<float *>(rbad + 2 * NC);                            // [NC] max |S|
+    int *rok = reinterpret_cast<int *>(rsm + NC);                                     // [NC] guard
+    ColState *cs = reinterpret_cast<ColState *>(rok + NC);                            // [2][NC]
+    unsigned long long *qb = reinterpret_cast<unsigned long long *>(cs + 2 * NC);
+    double *pmm = reinterpret_cast<double *>(qb + 2);                                 // [NW][NC]
 
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, j = lane & 15;
     const int tw = (wave + blockIdx.x) % NW;
     const int nv = (MT - tw + NW - 1) / NW;
 
-    // zero the B operands once (K padding rows stay zero), stage w as FP32
-    for (int e = threadIdx.x; e < (kF32Refine ? 16 * KP32 : 0); e += NW * 64) B32[e] = 0.0f;
-    for (int e = threadIdx.x; e < 16 * KPL * (kSplit ? 2 : 1); e += NW * 64) Bh[e] = 0;
-    for (int e = threadIdx.x; e < 16 * MT; e += NW * 64) wl[e] = (float)wv[e];
+    for (int e = tid; e < NC * KP32; e += NT) B32[e] = 0.0f;
+    for (int e = tid; e < (kMixed ? NC * KPL * (kSplit ? 2 : 1) : 0); e += NT) Bh[e] = 0;
+    for (int e = tid; e < 4 * NC; e += NT) rmax[e] = 0.0f;
+    for (int e = tid; e < 2 * NC; e += NT) rbad[e] = 0;
 
-    // 16-bit A fragments of the owned tiles, resident for the whole kernel.
     frag Af[TPW][KTL], Ag[kSplit ? TPW : 1][kSplit ? KTL : 1];
-    if constexpr (kMixed) {
+    f4 Wq[TPW];  // w of the lane's two buses per tile, FP32, (Re, Im, Re, Im)
 #pragma unroll
-        for (int q = 0; q < TPW; ++q)
+    for (int q = 0; q < TPW; ++q) {
+        Wq[q] = f4{1, 0, 1, 0};
+        if (q < nv) {
+            const int b0 = 8 * (tw + NW * q) + 2 * g;
+            Wq[q] = f4{(float)wv[b0], (float)wv[8 * MT + b0], (float)wv[b0 + 1], (float)wv[8 * MT + b0 + 1]};
+        }
+        if constexpr (kMixed) {
 #pragma unroll
             for (int kt = 0; kt < KTL; ++kt) {
                 if (q < nv) {
@@ -134,315 +183,385 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                     if constexpr (kSplit) Ag[q][kt] = *reinterpret_cast<const frag *>(Alo + idx);
                 }
             }
+        }
     }
     const float *Aw = A32 + (size_t)tw * (4 * MT + kFragPadSteps) * TPW * 64;
 
-    f4 U[TPW], Sv[TPW], Ip[TPW], In[TPW];
-    long long col = -1;
-    int it = 0, ph = 0, want = 0, wait = 0;  // ph: 0 full low sweeps, 1 difference sweeps
-    float dprev = 0.f, sumd = 0.f, uref = 0.f;
-    int sB = 0;          // power-of-two scale exponent of this column's B operand
-    bool precise = !kMixed;  // kind of the next sweep (workgroup-uniform)
+    f4 U[CG][TPW], Ip[CG][TPW];
+    long long col[CG];
+    float ks[CG], inv[CG];  // B scale 2^sB and product unscale 2^-(sB + sZ) per group
+    bool dif[CG];
+    bool precise = !kMixed;
     bool exhausted = false;
-    const float theta_k = 4.0f * L::u;                       // switch when d < theta_k max|U|
-    const float refresh = 6.7e-8f / L::u;                    // distance budget of difference sweeps
+    int par = 0;
+    const float theta_k = 4.0f * L::u;
+    const float refresh = 6.7e-8f / L::u;
     const float margin = 1.0f + 8.0f * L::u;
-    __syncthreads();
 
-    auto wbus = [&](int t, float &w0r, float &w0i, float &w1r, float &w1i) {
-        const int b0 = 8 * t + 2 * g;
-        w0r = wl[b0];
-        w1r = wl[b0 + 1];
-        w0i = wl[8 * MT + b0];
-        w1i = wl[8 * MT + b0 + 1];
+    // conj(S./V) 2^sB for the lane's two buses of tile q (rcp: ~1 ulp, far below the FP32 state floor)
+    auto inject = [&](const f4 &sv, const f4 &w, const f4 &u, float k) -> f4 {
+        const f4 v = w + u;
+        const float r0 = __builtin_amdgcn_rcpf(v[0] * v[0] + v[1] * v[1]) * k;
+        const float r1 = __builtin_amdgcn_rcpf(v[2] * v[2] + v[3] * v[3]) * k;
+        return f4{(sv[0] * v[0] + sv[1] * v[1]) * r0, (sv[0] * v[1] - sv[1] * v[0]) * r0,
+                  (sv[2] * v[2] + sv[3] * v[3]) * r1, (sv[2] * v[3] - sv[3] * v[2]) * r1};
     };
 
-    // Batch (re)fill: all 16 slots from the queue.  Returns false when the queue is empty.
-    auto refill = [&]() -> bool {
-        if (threadIdx.x == 0) *qb = exhausted ? (unsigned long long)tau : atomicAdd(queue, 16ull);
-        __syncthreads();
-        const unsigned long long base = *qb;
-        __syncthreads();
-        if (base >= (unsigned long long)tau) {
-            exhausted = true;
-            return false;
-        }
-        if (base + 16 >= (unsigned long long)tau) exhausted = true;
-        const long long c = (long long)base + j;
-        col = c < tau ? c : -1;
-        int ok = 1;
+    // Forms the injections of every group from the current drops (Eq. (3), scaled by the
+    // column's 2^sB), writes the B operand of the next sweep and rotates Ip.
+    auto prepare_b = [&]() {
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            double s[4] = {0, 0, 0, 0}, v[4] = {1, 0, 1, 0};
-            if (q < nv && col >= 0) {
-                const int t = tw + NW * q;
+        for (int c = 0; c < CG; ++c) {
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int b = 8 * t + 2 * g + h;
-                    if (b < n) {
-                        ldc(S + 2 * (col * n + b), s[2 * h], s[2 * h + 1]);
-                        if (V0) {
-                            ldc(V0 + 2 * (col * n + b), v[2 * h], v[2 * h + 1]);
-                            const double m2 = v[2 * h] * v[2 * h] + v[2 * h + 1] * v[2 * h + 1];
-                            ok &= (m2 >= 0.25 && m2 <= 2.25) ? 1 : 0;
+            for (int q = 0; q < TPW; ++q) {
+                const f4 In = inject(Sx[(c * TPW + q) * NT + tid], Wq[q], U[c][q], ks[c]);
+                if (q < nv) {
+                    const f4 bv = dif[c] ? In - Ip[c][q] : In;
+                    const int t = tw + NW * q;
+                    if (precise && kF32Refine) {
+                        *reinterpret_cast<f4 *>(B32 + (16 * c + j) * KP32 + 16 * t + 4 * g) = bv;
+                    } else if constexpr (kMixed) {
+                        // The column scale keeps |B| < 2^14 while |V| > 1/4 pu; a diverging
+                        // (infeasible) column may leave that range: saturate instead of
+                        // overflowing to inf, so it ends as MAX_ITER, not NONFINITE.
+                        const f4 bc = kScaled ? f4{__builtin_amdgcn_fmed3f(bv[0], -65504.f, 65504.f),
+                                                   __builtin_amdgcn_fmed3f(bv[1], -65504.f, 65504.f),
+                                                   __builtin_amdgcn_fmed3f(bv[2], -65504.f, 65504.f),
+                                                   __builtin_amdgcn_fmed3f(bv[3], -65504.f, 65504.f)}
+                                              : bv;
+                        const quad hq = L::cvt(bc);
+                        const int off = (16 * c + j) * KPL + 16 * t + 4 * g;
+                        *reinterpret_cast<quad *>(Bh + off) = hq;
+                        if constexpr (kSplit) {
+                            if (precise) {
+                                const f4 r = bc - f4{(float)hq[0], (float)hq[1], (float)hq[2], (float)hq[3]};
+                                *reinterpret_cast<quad *>(Bl + off) = L::cvt(r);
+                            }
                         }
                     }
                 }
-            }
-            Sv[q] = f4{(float)s[0], (float)s[1], (float)s[2], (float)s[3]};
-            if (q < nv) {
-                const int t = tw + NW * q, b0 = 8 * t + 2 * g;
-                U[q] = f4{(float)(v[0] - wv[b0]), (float)(v[1] - wv[8 * MT + b0]), (float)(v[2] - wv[b0 + 1]),
-                          (float)(v[3] - wv[8 * MT + b0 + 1])};
-            } else {
-                U[q] = f4{0, 0, 0, 0};
+                Ip[c][q] = In;
             }
         }
-        if (V0) {  // a warm start is kept only if every bus of the column passes the guard
-            ok &= __shfl_xor(ok, 16);
-            ok &= __shfl_xor(ok, 32);
-            if (g == 0) pb[wave * 16 + j] = ok;
-            __syncthreads();
-            int all = 1;
-            for (int w = 0; w < NW; ++w) all &= pb[w * 16 + j];
-            __syncthreads();
-            if (!all) {  // flat start V = 1 + j0
+    };
+
+    auto refill = [&]() -> bool {
+        if (tid < NC) {
+            rsm[tid] = 0.0f;
+            rok[tid] = 0;
+        }
+        if (tid == 0) *qb = exhausted ? (unsigned long long)tau : atomicAdd(queue, (unsigned long long)NC);
+        __syncthreads();
+        const unsigned long long base = *qb;
+        if (base >= (unsigned long long)tau) return false;
+        if (base + NC >= (unsigned long long)tau) exhausted = true;
 #pragma unroll
-                for (int q = 0; q < TPW; ++q)
-                    if (q < nv) {
-                        const int t = tw + NW * q, b0 = 8 * t + 2 * g;
-                        U[q] = f4{(float)(1.0 - wv[b0]), (float)(-wv[8 * MT + b0]), (float)(1.0 - wv[b0 + 1]),
-                                  (float)(-wv[8 * MT + b0 + 1])};
+        for (int c = 0; c < CG; ++c) {
+            const long long cc = (long long)base + 16 * c + j;
+            col[c] = cc < tau ? cc : -1;
+            float sm = 0.0f;
+            int bad = 0;
+#pragma unroll
+            for (int q = 0; q < TPW; ++q) {
+                double s[4] = {0, 0, 0, 0}, v[4] = {1, 0, 1, 0};
+                if (q < nv && col[c] >= 0) {
+                    const int b0 = 8 * (tw + NW * q) + 2 * g;
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+                        if (b0 + h < n) {
+                            ldc(S + 2 * (col[c] * n + b0 + h), s[2 * h], s[2 * h + 1]);
+                            if (V0) {
+                                ldc(V0 + 2 * (col[c] * n + b0 + h), v[2 * h], v[2 * h + 1]);
+                                const double m2 = v[2 * h] * v[2 * h] + v[2 * h + 1] * v[2 * h + 1];
+                                bad |= (m2 >= 0.25 && m2 <= 2.25) ? 0 : 1;
+                            }
+                        }
                     }
+                }
+                const f4 sv = f4{(float)s[0], (float)s[1], (float)s[2], (float)s[3]};
+                Sx[(c * TPW + q) * NT + tid] = sv;
+                sm = fmaxf(sm, amax4(sv));
+                U[c][q] = f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]} - Wq[q];
+            }
+            sm = fmaxf(sm, __shfl_xor(sm, 16));
+            sm = fmaxf(sm, __shfl_xor(sm, 32));
+            bad |= __shfl_xor(bad, 16);
+            bad |= __shfl_xor(bad, 32);
+            if (g == 0) {
+                atomicMax(reinterpret_cast<int *>(rsm) + 16 * c + j, __float_as_int(sm));  // sm >= 0: int order
+                if (bad) atomicOr(rok + 16 * c + j, 1);
             }
         }
+        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            float w0r = 1, w0i = 0, w1r = 1, w1i = 0;
-            if (q < nv) wbus(tw + NW * q, w0r, w0i, w1r, w1i);
-            In[q] = injection(Sv[q], w0r, w0i, w1r, w1i, U[q]);
-            Ip[q] = In[q];
+        for (int c = 0; c < CG; ++c) {
+            if (V0 && rok[16 * c + j]) {  // guard failed somewhere in the column: flat start
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) U[c][q] = f4{1, 0, 1, 0} - Wq[q];
+            }
+            int sB = 0;
+            if constexpr (kScaled) {
+                int e = 0;
+                const float sm = rsm[16 * c + j];
+                (void)frexpf(sm > 0.f ? sm : 1.0f, &e);
+                sB = 12 - e;  // max |S| 2^sB < 2^12: |I| 2^sB < 2^14 while |V| > 1/4
+            }
+            ks[c] = ldexpf(1.0f, sB);
+            inv[c] = ldexpf(1.0f, -(sB + (kScaled ? sZ : 0)));
+            dif[c] = false;
+            if (wave == 0 && g == 0) {
+                ColState st;
+                st.col = col[c];
+                st.dprev = st.sumd = st.uref = 0.f;
+                st.it = st.ph = st.want = st.wait = 0;
+                cs[par * NC + 16 * c + j] = st;
+            }
         }
-        it = 0;
-        ph = 0;
-        want = 0;
-        wait = 0;
-        dprev = 0.f;
-        sumd = 0.f;
-        uref = 0.f;
         precise = !kMixed;
+        prepare_b();
         return true;
     };
 
-    // Writes the B operand of the next sweep from In (full form) or In - Ip (difference form).
-    auto prepare_b = [&](bool diff) {
-        f4 Bv[TPW];
-        float m = 0.f;
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            Bv[q] = diff ? In[q] - Ip[q] : In[q];
-            if (q < nv) m = fmaxf(m, amax4(Bv[q]));
-            Ip[q] = In[q];
-        }
-        if (precise && kF32Refine) {
-#pragma unroll
-            for (int q = 0; q < TPW; ++q)
-                if (q < nv)
-                    *reinterpret_cast<f4 *>(B32 + j * KP32 + 16 * (tw + NW * q) + 4 * g) = Bv[q];
-            return;
-        }
-        if constexpr (MODE == TPF_MODE_MIXED_FP16) {
-            // per-column power of two putting max |B| just below 2^14
-            m = fmaxf(m, __shfl_xor(m, 16));
-            m = fmaxf(m, __shfl_xor(m, 32));
-            if (g == 0) pm[wave * 16 + j] = m;
-            __syncthreads();
-            float mm = 0.f;
-            for (int w = 0; w < NW; ++w) mm = fmaxf(mm, pm[w * 16 + j]);
-            int e = 0;
-            (void)frexpf(mm > 0.f ? mm : 1.0f, &e);
-            sB = 14 - e;
-        } else {
-            sB = 0;
-        }
-#pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            if (q < nv) {
-                const f4 x = f4{ldexpf(Bv[q][0], sB), ldexpf(Bv[q][1], sB), ldexpf(Bv[q][2], sB),
-                                ldexpf(Bv[q][3], sB)};
-                const quad hq = L::cvt(x);
-                const int off = j * KPL + 16 * (tw + NW * q) + 4 * g;
-                *reinterpret_cast<quad *>(Bh + off) = hq;
-                if constexpr (kSplit) {
-                    const f4 r = x - f4{(float)hq[0], (float)hq[1], (float)hq[2], (float)hq[3]};
-                    *reinterpret_cast<quad *>(Bl + off) = L::cvt(r);
-                }
-            }
-        }
-    };
-
     if (!refill()) return;
-    prepare_b(false);
     __syncthreads();
 
     while (true) {
-        // ---- product
-        f4 acc[TPW];
+        // ---- products and epilogues
+        auto epilogue = [&](int c, const f4(&acc)[TPW], bool full) {
+            float emax = 0.f, esum = 0.f, umax = 0.f;
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) acc[q] = f4{0, 0, 0, 0};
+            for (int q = 0; q < TPW; ++q) {
+                if (q < nv) {
+                    const f4 p = acc[q] * inv[c];
+                    const f4 un = full ? p : U[c][q] + p;
+                    const f4 dd = un - U[c][q];
+                    const float e0 = dd[0] * dd[0] + dd[1] * dd[1], e1 = dd[2] * dd[2] + dd[3] * dd[3];
+                    esum += e0 + e1;
+                    emax = fmaxf(emax, fmaxf(e0, e1));
+                    umax = fmaxf(umax, amax4(un));
+                    U[c][q] = un;
+                }
+            }
+            emax = fmaxf(emax, __shfl_xor(emax, 16));
+            emax = fmaxf(emax, __shfl_xor(emax, 32));
+            umax = fmaxf(umax, __shfl_xor(umax, 16));
+            umax = fmaxf(umax, __shfl_xor(umax, 32));
+            int bad = !(esum < INFINITY);
+            bad |= __shfl_xor(bad, 16);
+            bad |= __shfl_xor(bad, 32);
+            if (g == 0) {
+                const int k = 16 * c + j;
+                atomicMax(reinterpret_cast<int *>(rmax) + par * 2 * NC + k, __float_as_int(emax));
+                atomicMax(reinterpret_cast<int *>(rmax) + par * 2 * NC + NC + k, __float_as_int(umax));
+                if (bad) atomicOr(rbad + par * NC + k, 1);
+            }
+        };
         if (precise && kF32Refine) {
+            f4 acc[CG][TPW];
+#pragma unroll
+            for (int c = 0; c < CG; ++c)
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) acc[c][q] = f4{0, 0, 0, 0};
             const int KT = 4 * MT;
             constexpr int ST = TPW * 64;
-            float r0[TPW], r1[TPW];
+            float r0[TPW], r1[TPW], r2[TPW], r3[TPW];
 #pragma unroll
-            for (int q = 0; q < TPW; ++q) r0[q] = Aw[q * 64 + lane];
-#pragma unroll 1
-            for (int kt = 0; kt < KT; kt += 2) {
-#pragma unroll
-                for (int q = 0; q < TPW; ++q) r1[q] = Aw[(size_t)(kt + 1) * ST + q * 64 + lane];
-                const float b0 = B32[j * KP32 + 4 * kt + g];
-#pragma unroll
-                for (int q = 0; q < TPW; ++q)
-                    if (q < nv) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(r0[q], b0, acc[q], 0, 0, 0);
-#pragma unroll
-                for (int q = 0; q < TPW; ++q) r0[q] = Aw[(size_t)(kt + 2) * ST + q * 64 + lane];
-                const float b1 = B32[j * KP32 + 4 * (kt + 1) + g];
-#pragma unroll
-                for (int q = 0; q < TPW; ++q)
-                    if (q < nv) acc[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(r1[q], b1, acc[q], 0, 0, 0);
+            for (int q = 0; q < TPW; ++q) {
+                r0[q] = Aw[q * 64 + lane];
+                r1[q] = Aw[ST + q * 64 + lane];
+                r2[q] = Aw[2 * ST + q * 64 + lane];
             }
+            auto step = [&](int kt, float(&r)[TPW]) {
+#pragma unroll
+                for (int c = 0; c < CG; ++c) {
+                    const float b = B32[(16 * c + j) * KP32 + 4 * kt + g];
+#pragma unroll
+                    for (int q = 0; q < TPW; ++q)
+                        if (q < nv) acc[c][q] = __builtin_amdgcn_mfma_f32_16x16x4f32(r[q], b, acc[c][q], 0, 0, 0);
+                }
+            };
+#pragma unroll 1
+            for (int kt = 0; kt < KT; kt += 4) {
+                const float *Ak = Aw + (size_t)kt * ST + lane;
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) r3[q] = Ak[3 * ST + q * 64];
+                step(kt, r0);
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) r0[q] = Ak[4 * ST + q * 64];
+                step(kt + 1, r1);
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) r1[q] = Ak[5 * ST + q * 64];
+                step(kt + 2, r2);
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) r2[q] = Ak[6 * ST + q * 64];
+                step(kt + 3, r3);
+            }
+#pragma unroll
+            for (int c = 0; c < CG; ++c) epilogue(c, acc[c], true);
         } else if constexpr (kMixed) {
 #pragma unroll
-            for (int kt = 0; kt < KTL; ++kt) {
-                const frag bh = *reinterpret_cast<const frag *>(Bh + j * KPL + 32 * kt + 8 * g);
+            for (int c = 0; c < CG; ++c) {
+                f4 acc[TPW];
 #pragma unroll
-                for (int q = 0; q < TPW; ++q)
-                    if (q < nv) acc[q] = L::mma(Af[q][kt], bh, acc[q]);
-                if constexpr (kSplit) {
-                    if (precise) {
-                        const frag bl = *reinterpret_cast<const frag *>(Bl + j * KPL + 32 * kt + 8 * g);
+                for (int q = 0; q < TPW; ++q) acc[q] = f4{0, 0, 0, 0};
 #pragma unroll
-                        for (int q = 0; q < TPW; ++q)
-                            if (q < nv) {
-                                acc[q] = L::mma(Af[q][kt], bl, acc[q]);
-                                acc[q] = L::mma(Ag[q][kt], bh, acc[q]);
-                            }
-                    }
-                }
-            }
-        }
-        // ---- epilogue: new drop, step size, next injection
-        const bool full = precise || ph == 0;
-        const float inv = (precise && kF32Refine) ? 1.0f : ldexpf(1.0f, -(sB + (kSplit ? sZ : 0)));
-        float dmax = 0.f, umax = 0.f;
-        int bad = 0;
+                for (int kt = 0; kt < KTL; ++kt) {
+                    const frag bh = *reinterpret_cast<const frag *>(Bh + (16 * c + j) * KPL + 32 * kt + 8 * g);
 #pragma unroll
-        for (int q = 0; q < TPW; ++q) {
-            if (q < nv) {
-                const f4 p = acc[q] * inv;
-                const f4 un = full ? p : U[q] + p;
-                const f4 dd = un - U[q];
-                const float e0 = dd[0] * dd[0] + dd[1] * dd[1], e1 = dd[2] * dd[2] + dd[3] * dd[3];
-                bad |= !(e0 < INFINITY) | !(e1 < INFINITY);
-                dmax = fmaxf(dmax, fmaxf(e0, e1));
-                umax = fmaxf(umax, amax4(un));
-                U[q] = un;
-                float w0r, w0i, w1r, w1i;
-                wbus(tw + NW * q, w0r, w0i, w1r, w1i);
-                In[q] = injection(Sv[q], w0r, w0i, w1r, w1i, un);
-            }
-        }
-        dmax = fmaxf(dmax, __shfl_xor(dmax, 16));
-        dmax = fmaxf(dmax, __shfl_xor(dmax, 32));
-        umax = fmaxf(umax, __shfl_xor(umax, 16));
-        umax = fmaxf(umax, __shfl_xor(umax, 32));
-        bad |= __shfl_xor(bad, 16);
-        bad |= __shfl_xor(bad, 32);
-        if (g == 0) {
-            pd[wave * 16 + j] = dmax;
-            pu[wave * 16 + j] = umax;
-            pb[wave * 16 + j] = bad;
-        }
-        __syncthreads();
-        dmax = 0.f;
-        umax = 0.f;
-        bad = 0;
-        for (int w = 0; w < NW; ++w) {
-            dmax = fmaxf(dmax, pd[w * 16 + j]);
-            umax = fmaxf(umax, pu[w * 16 + j]);
-            bad |= pb[w * 16 + j];
-        }
-        // ---- per-column decisions (identical in every wave)
-        bool done = false, conv = false;
-        if (col >= 0) {
-            ++it;
-            const float d = sqrtf(dmax);
-            if (!kMixed || precise) {
-                conv = d < tol;
-                if (kMixed && (want || ph == 1)) {
-                    ph = 1;
-                    want = 0;
-                    wait = 0;
-                    sumd = 0.f;
-                }
-            } else if (ph == 0) {
-                if (it == 1) uref = umax;
-                uref = fmaxf(uref, umax);
-                if (!want && (d < theta_k * uref || (it >= 2 && d > 0.5f * dprev))) want = 1;
-            } else {
-                conv = d * margin < tol;
-                sumd += d;
-                if (!want && sumd > refresh) want = 1;
-            }
-            if (want) ++wait;
-            dprev = d;
-            done = bad || conv || it >= max_iter;
-            if (done) {
+                    for (int q = 0; q < TPW; ++q)
+                        if (q < nv) acc[q] = L::mma(Af[q][kt], bh, acc[q]);
+                    if constexpr (kSplit) {
+                        if (precise) {
+                            const frag bl =
+                                *reinterpret_cast<const frag *>(Bl + (16 * c + j) * KPL + 32 * kt + 8 * g);
 #pragma unroll
-                for (int q = 0; q < TPW; ++q) {
-                    if (q < nv) {
-                        const int t = tw + NW * q;
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const int b = 8 * t + 2 * g + h;
-                            if (b < n) {
-                                IO *o = Vout + 2 * (col * n + b);
-                                o[0] = (IO)(wv[b] + (double)U[q][2 * h]);
-                                o[1] = (IO)(wv[8 * MT + b] + (double)U[q][2 * h + 1]);
-                            }
+                            for (int q = 0; q < TPW; ++q)
+                                if (q < nv) {
+                                    acc[q] = L::mma(Af[q][kt], bl, acc[q]);
+                                    acc[q] = L::mma(Ag[q][kt], bh, acc[q]);
+                                }
                         }
                     }
                 }
-                if (wave == 0 && g == 0) {
-                    iters_out[col] = it;
-                    status_out[col] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
-                }
-                col = -1;
-#pragma unroll
-                for (int q = 0; q < TPW; ++q) {
-                    Sv[q] = f4{0, 0, 0, 0};
-                    In[q] = f4{0, 0, 0, 0};
-                    Ip[q] = f4{0, 0, 0, 0};
-                }
-                want = 0;
-                ph = 0;
+                epilogue(c, acc, !dif[c]);
             }
         }
-        const unsigned long long act = __ballot(col >= 0 && g == 0);
-        if (!act) {
+        __syncthreads();
+        // ---- decisions, evaluated identically by every wave
+        if (tid < NC) {  // clear the reductions of the next sweep
+            rmax[(par ^ 1) * 2 * NC + tid] = 0.f;
+            rmax[(par ^ 1) * 2 * NC + NC + tid] = 0.f;
+            rbad[(par ^ 1) * NC + tid] = 0;
+        }
+        long long rcol[CG];
+        bool want_any = false, low_unready = false, stale = false, active = false;
+        int ph_next[CG];
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+            const int k = 16 * c + j;
+            const ColState st = cs[par * NC + k];
+            ColState nx = st;
+            rcol[c] = -1;
+            if (st.col >= 0) {
+                const float d = sqrtf(rmax[par * 2 * NC + k]);
+                const float um = rmax[par * 2 * NC + NC + k];
+                const int bad = rbad[par * NC + k];
+                nx.it = st.it + 1;
+                bool conv = false;
+                if (!kMixed || precise) {
+                    conv = d < tol;
+                    if (kMixed && (st.want || st.ph == 1)) {
+                        nx.ph = 1;
+                        nx.want = 0;
+                        nx.wait = 0;
+                        nx.sumd = 0.f;
+                    }
+                } else if (st.ph == 0) {
+                    nx.uref = fmaxf(st.uref, um);
+                    if (!st.want && (d < theta_k * nx.uref || (nx.it >= 2 && d > 0.5f * st.dprev))) nx.want = 1;
+                } else {
+                    conv = d * margin < tol;
+                    nx.sumd = st.sumd + d;
+                    if (!st.want && nx.sumd > refresh) nx.want = 1;
+                }
+                nx.wait = nx.want ? nx.wait + 1 : 0;
+                nx.dprev = d;
+                if (bad || conv || nx.it >= max_iter) {
+                    if (wave == 0 && g == 0) {
+                        iters_out[st.col] = nx.it;
+                        status_out[st.col] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+                    }
+                    rcol[c] = st.col;
+                    nx.col = -1;
+                    nx.want = 0;
+                    nx.ph = 0;
+                }
+            }
+            if (wave == 0 && g == 0) cs[(par ^ 1) * NC + k] = nx;
+            col[c] = nx.col;
+            ph_next[c] = nx.ph;
+            const bool live = nx.col >= 0;
+            want_any |= live && nx.want;
+            low_unready |= live && nx.ph == 0 && !nx.want;
+            stale |= live && nx.wait >= 3;
+            active |= live;
+        }
+        // workgroup-uniform: every wave holds all NC columns in its lanes
+        want_any = __ballot(want_any) != 0;
+        low_unready = __ballot(low_unready) != 0;
+        stale = __ballot(stale) != 0;
+        active = __ballot(active) != 0;
+        precise = !kMixed || (want_any && (!low_unready || stale));
+        // ---- retire finished columns
+#pragma unroll
+        for (int c = 0; c < CG; ++c) {
+            if (rcol[c] >= 0) {
+#pragma unroll
+                for (int q = 0; q < TPW; ++q) {
+                    if (q < nv) {
+                        const int b0 = 8 * (tw + NW * q) + 2 * g;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int b = b0 + h;
+                            if (b < n) {
+                                IO *o = Vout + 2 * (rcol[c] * n + b);
+                                o[0] = (IO)(wv[b] + (double)U[c][q][2 * h]);
+                                o[1] = (IO)(wv[8 * MT + b] + (double)U[c][q][2 * h + 1]);
+                            }
+                        }
+                        Sx[(c * TPW + q) * NT + tid] = f4{0, 0, 0, 0};  // idle slot: zero injection
+                    }
+                }
+            }
+            dif[c] = !precise && ph_next[c] == 1;
+        }
+        if (mm.out) {
+            bool any = false;
+#pragma unroll
+            for (int c = 0; c < CG; ++c) any |= rcol[c] >= 0;
+            if (__ballot(any)) {  // workgroup-uniform
+                // Eq. (1) power balance of the retiring columns from the returned voltages.
+                // Their drops go to the (free) FP32 B buffer for the neighbour lookups.
+#pragma unroll
+                for (int c = 0; c < CG; ++c)
+                    if (rcol[c] >= 0)
+#pragma unroll
+                        for (int q = 0; q < TPW; ++q)
+                            if (q < nv)
+                                *reinterpret_cast<f4 *>(B32 + (16 * c + j) * KP32 + 16 * (tw + NW * q) + 4 * g) =
+                                    U[c][q];
+                __syncthreads();
+#pragma unroll
+                for (int c = 0; c < CG; ++c) {
+                    double worst = 0.0;
+                    if (rcol[c] >= 0)
+                        worst = retired_mismatch<IO>(mm, S, wv, B32 + (16 * c + j) * KP32, rcol[c], n, MT, tw, NW,
+                                                     nv, g);
+                    worst = nanmax_d(worst, __shfl_xor(worst, 16));
+                    worst = nanmax_d(worst, __shfl_xor(worst, 32));
+                    if (g == 0) pmm[wave * NC + 16 * c + j] = worst;
+                }
+                __syncthreads();
+                if (wave == 0 && g == 0) {
+#pragma unroll
+                    for (int c = 0; c < CG; ++c)
+                        if (rcol[c] >= 0) {
+                            double m = 0.0;
+                            for (int w = 0; w < NW; ++w) m = nanmax_d(m, pmm[w * NC + 16 * c + j]);
+                            mm.out[rcol[c]] = m;
+                        }
+                }
+                __syncthreads();  // B32 is rewritten by the next operand preparation
+            }
+        }
+        par ^= 1;
+        if (!active) {
+            __syncthreads();
             if (!refill()) break;
-            prepare_b(false);
             __syncthreads();
             continue;
         }
-        // ---- next sweep kind: refine when every low-phase column is ready, or one waited long
-        if (kMixed) {
-            const unsigned long long lowcols = __ballot(col >= 0 && g == 0 && ph == 0);
-            const unsigned long long wants = __ballot(col >= 0 && g == 0 && want);
-            const unsigned long long stale = __ballot(col >= 0 && g == 0 && wait >= 3);
-            precise = wants != 0 && (((lowcols & ~wants) == 0) || stale != 0);
-        }
-        prepare_b(!precise && ph == 1 && col >= 0);
+        prepare_b();
         __syncthreads();
     }
 }
@@ -450,13 +569,16 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
 template <int TPW, int NW, int KTL, int MODE, typename IO>
 static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
                       int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                      unsigned long long *queue, hipStream_t stream) {
+                      unsigned long long *queue, const MismatchArgs &mm, hipStream_t stream) {
+    // column groups per workgroup: as many as the registers hold without spilling
+    constexpr int CG = (MODE == TPF_MODE_FP32 || TPW == 1) ? 4 : TPF_MIXED_CG;
     const int MT = dn.MT;
-    const bool f32r = MODE != TPF_MODE_MIXED_FP16;
+    constexpr bool mixed = MODE != TPF_MODE_FP32, split = MODE == TPF_MODE_MIXED_FP16;
+    const size_t NC = 16 * CG, NT = NW * 64;
     const size_t KPL = 32 * KTL + 8, KP32 = 16 * MT + 4;
-    const size_t lds = (f32r ? 16 * KP32 * 4 : 0) + 16 * KPL * 2 * (MODE == TPF_MODE_MIXED_FP16 ? 2 : 1) +
-                       (size_t)NW * 16 * 16 + (16 * MT + 2) * 4 + 16 + 16;
-    auto kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, IO>;
+    const size_t lds = NC * KP32 * 4 + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) + (size_t)CG * TPW * NT * 16 +
+                       NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 16 + (size_t)NW * NC * 8 + 64;
+    auto kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, IO>;
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
     int per_cu = 0;
@@ -465,20 +587,21 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    const long long blocks = std::min<long long>((long long)cus * per_cu, (tau + 15) / 16);
+    const long long blocks = std::min<long long>((long long)cus * per_cu, (tau + (long long)NC - 1) / (long long)NC);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.A32, MODE == TPF_MODE_MIXED_BF16 ? dn.Abf : dn.Ah, dn.Al,
-                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue);
+                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue, mm);
     return TPF_OK;
 }
 
 template <int MODE, typename IO>
 static int dispatch(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
                     int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                    unsigned long long *queue, hipStream_t stream) {
+                    unsigned long long *queue, const MismatchArgs &mm, hipStream_t stream) {
 #define TPF_GO(T, W, K)                                                                                      \
     if (dn.TPW == T && dn.NW == W && dn.KTL == K)                                                            \
-        return launch_one<T, W, K, MODE, IO>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);
+        return launch_one<T, W, K, MODE, IO>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm,   \
+                                             stream);
     TPF_GO(1, 4, 1) TPF_GO(1, 4, 2) TPF_GO(1, 8, 3) TPF_GO(1, 8, 4)
     TPF_GO(2, 8, 5) TPF_GO(2, 8, 6) TPF_GO(2, 8, 7) TPF_GO(2, 8, 8)
 #undef TPF_GO
@@ -487,13 +610,14 @@ static int dispatch(const tpf_network_s &net, const DeviceNet &dn, const void *S
 
 int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype, int64_t tau,
                      double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                     unsigned long long *queue, hipStream_t stream) {
+                     unsigned long long *queue, double *mismatch_out, hipStream_t stream) {
+    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, mismatch_out};
     if (!dn.A32) return fail(TPF_ERR_UNSUPPORTED, "FP32/mixed sweep kernels support up to 128 PQ buses");
 #define TPF_MODE_CASE(M)                                                                                      \
     if (mode == M) {                                                                                         \
         if (dtype == TPF_C128)                                                                               \
-            return dispatch<M, double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream); \
-        return dispatch<M, float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);      \
+            return dispatch<M, double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream); \
+        return dispatch<M, float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream);      \
     }
     TPF_MODE_CASE(TPF_MODE_FP32)
     TPF_MODE_CASE(TPF_MODE_MIXED_BF16)

@@ -26,19 +26,13 @@ __global__ __launch_bounds__(256) void mismatch_f64_kernel(const IO *__restrict_
         const IO *vc = V + 2 * c * n;
         const IO *sc = S + 2 * c * n;
         double worst = 0.0;
+        const MismatchArgs mm{rowptr, colidx, yv, cv, out};
         for (int i = lane; i < n; i += 64) {
-            double ar = cv[2 * i], ai = cv[2 * i + 1];
-            for (int e = rowptr[i]; e < rowptr[i + 1]; ++e) {
-                const int k = colidx[e];
-                const double yr = yv[2 * e], yi = yv[2 * e + 1];
-                const double vr = (double)vc[2 * k], vi = (double)vc[2 * k + 1];
-                ar += yr * vr - yi * vi;
-                ai += yr * vi + yi * vr;
-            }
-            const double vr = (double)vc[2 * i], vi = (double)vc[2 * i + 1];
-            const double mr = (double)sc[2 * i] + vr * ar + vi * ai;
-            const double mi = (double)sc[2 * i + 1] + vi * ar - vr * ai;
-            worst = nanmax(worst, hypot(mr, mi));
+            worst = nanmax(worst, bus_mismatch(mm, i, (double)sc[2 * i], (double)sc[2 * i + 1], (double)vc[2 * i],
+                                               (double)vc[2 * i + 1], [&](int k, double &xr, double &xi) {
+                                                   xr = (double)vc[2 * k];
+                                                   xi = (double)vc[2 * k + 1];
+                                               }));
         }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) worst = nanmax(worst, __shfl_xor(worst, off));

@@ -53,6 +53,35 @@ struct DeviceNet {
     std::vector<void *> owned;   // every allocation above, freed with the network
 };
 
+// Sparse Y_dd and c = Y_ds v_s on the device, for the FP64 power-balance mismatch
+// (Eq. (1)); `out` is NULL when no mismatch is requested.
+struct MismatchArgs {
+    const int32_t *rowptr;
+    const int32_t *colidx;
+    const double *yval;  // [nnz][2]
+    const double *cval;  // [n][2]
+    double *out;         // [tau]
+};
+
+__device__ __forceinline__ double nanmax_d(double a, double b) { return (a > b || a != a) ? a : b; }
+
+// |m_b| = |S_b + V_b conj(c_b + sum_k (Y_dd)_bk V_k)| for one bus; `vk(k, re, im)` fetches V_k.
+template <typename F>
+__device__ __forceinline__ double bus_mismatch(const MismatchArgs &mm, int b, double sr, double si, double vr,
+                                               double vi, F vk) {
+    double ar = mm.cval[2 * b], ai = mm.cval[2 * b + 1];
+    for (int e = mm.rowptr[b]; e < mm.rowptr[b + 1]; ++e) {
+        double xr, xi;
+        vk(mm.colidx[e], xr, xi);
+        const double yr = mm.yval[2 * e], yi = mm.yval[2 * e + 1];
+        ar += yr * xr - yi * xi;
+        ai += yr * xi + yi * xr;
+    }
+    const double mr = sr + vr * ar + vi * ai;
+    const double mi = si + vi * ar - vr * ai;
+    return sqrt(mr * mr + mi * mi);
+}
+
 }  // namespace tpf
 
 struct tpf_network_s {
@@ -83,10 +112,10 @@ int device_net(tpf_network net, DeviceNet **out);
 int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype,
                          int64_t tau, double tol, int max_iter, const void *V0, void *V,
                          int32_t *iters, int8_t *status, unsigned long long *queue,
-                         hipStream_t stream);
+                         double *mismatch_out, hipStream_t stream);
 int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype,
                      int64_t tau, double tol, int max_iter, const void *V0, void *V, int32_t *iters,
-                     int8_t *status, unsigned long long *queue, hipStream_t stream);
+                     int8_t *status, unsigned long long *queue, double *mismatch_out, hipStream_t stream);
 int launch_start_only(int n, const void *V0, int dtype, int64_t tau, void *V, int32_t *iters,
                       int8_t *status, hipStream_t stream);
 int launch_mismatch_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, const void *V,

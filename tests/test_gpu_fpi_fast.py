@@ -93,7 +93,12 @@ def test_fast_forms_edge_columns(gpu, mode):
     S = np.array([[0.18 + 0.11j], [0.25 + 0.15j], [np.nan + 0j], [0.0 + 0j]])
     V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=300, mode=mode)
     st = st.cpu().numpy()
-    assert list(st) == [tpf.ST_CONVERGED, tpf.ST_MAX_ITER, tpf.ST_NONFINITE, tpf.ST_CONVERGED]
+    # Column 1 has no solution (Eq. (11) violated): the map is not a contraction and its
+    # orbit is chaotic, so a reduced-precision run may leave the oracle's orbit and even
+    # pass through V = 0 (then the iterate is non-finite).  It must never be reported
+    # converged; the FP64 form reproduces the oracle's MAX_ITER exactly (FP64 tests).
+    assert st[1] in (tpf.ST_MAX_ITER, tpf.ST_NONFINITE)
+    assert [st[0], st[2], st[3]] == [tpf.ST_CONVERGED, tpf.ST_NONFINITE, tpf.ST_CONVERGED]
     ref = oracle.fpi(onet, S[[0, 3]], 1e-12, 1000)
     assert np.abs(V.cpu().numpy()[[0, 3]] - ref.V).max() < 2e-6  # k = 0.61: bound k/(1-k) tol
 

@@ -79,8 +79,11 @@ def test_complex64_io(gpu, feeder100):
     f, net, onet = feeder100
     S = W.profile_minute_year(f, steps=3000, t0=5000, dtype=np.complex64)
     Sd = _to_dev(S, gpu, torch.complex64)
-    V, it, st = tpf.solve_timeseries(net, Sd, tol=1e-6, max_iter=100)
+    V, it, st, mm = tpf.solve_timeseries(net, Sd, tol=1e-6, max_iter=100, mismatch=True)
     assert V.dtype == torch.complex64
+    # mismatch of the returned (complex64) voltages, as the standalone check computes it
+    m2 = tpf.mismatch(net, Sd, V)
+    assert float((m2 - mm).abs().max()) <= 1e-13 * float(mm.max()) + 1e-18
     # FP64 arithmetic on exactly-widened inputs; only the output is rounded to complex64
     _parity(onet, S.astype(np.complex128), V, it, st, 1e-6, 100, bound=2e-7)
 
@@ -199,8 +202,10 @@ def test_mismatch_kernel_matches_oracle(gpu, feeder100):
     assert np.all(np.abs(g - ref) <= 1e-12 + 1e-9 * ref)
     # power balance at tol 1e-6: |m_i| <= |S_i| d / |V_i| (about 3e-8 on this feeder)
     assert g.max() < 1e-7
+    # the solve computes the mismatch inside the sweep kernel at retirement; the
+    # standalone kernel must agree on the same voltages (summation order may differ)
     m2 = tpf.mismatch(net, _to_dev(S, gpu), V)
-    assert torch.equal(m2, mm)
+    assert float((m2 - mm).abs().max()) <= 1e-13 * float(mm.max()) + 1e-18
 
 
 def test_full_year_sampled(gpu, feeder100):
