@@ -4,11 +4,13 @@ resolution (525,600 power flows), solved to 1e-6 pu.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-One step is one pass of the whole solve path over the year: start voltages,
-all sweeps of every column until it converges, and the FP64 power-balance
-mismatch check, with S already resident in device memory.  The FP64 form
-(every sweep in FP64) is timed; `value` is its whole-job throughput.  Prints
-ONE JSON line.
+One step is one pass of the whole solve path over the year: start voltages
+(the learned warm start's inference where used), all sweeps of every column
+until it converges, and the FP64 power-balance mismatch check, with S already
+resident in device memory.  Every form is timed: FP64, FP32, mixed BF16, mixed
+FP16, and the mixed forms from the learned warm start.  `value` is the fastest
+mixed + warm-start form's whole-job throughput; the FP64 form is reported beside
+it (`fp64_form`).  Prints ONE JSON line.
 
 Inputs are synthetic and seeded (no dataset): a random radial feeder grown as
 a k-ary tree (1-5 children per node), line r ~ U(0.005, 0.02) pu, x = r U(0.5, 2),
@@ -81,6 +83,9 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-warm-start", action="store_true")
+    ap.add_argument("--train-steps", type=int, default=100_000)
+    ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one plain device copy of known size (HBM counter calibration)")
     ap.add_argument("--kernel-only", action="store_true",
@@ -118,10 +123,15 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
 
-    def time_form(mode, V0=None):
-        """K timed steps of one form (solve + FP64 mismatch), plus the sweep kernel alone."""
+    def time_form(mode, V0=None, mlp=None):
+        """K timed steps of one form (warm-start inference if any + solve + FP64 mismatch),
+        plus the sweep kernel alone."""
         out = tpf.alloc_outputs(net, S, mode, mismatch=True)
-        step = lambda: tpf.solve_timeseries(net, S, tol, max_iter, mode, V0=V0, mismatch=True, out=out)
+
+        def step():
+            if mlp is not None:
+                mlp[0].predict(S, mlp[1], out=V0)
+            return tpf.solve_timeseries(net, S, tol, max_iter, mode, V0=V0, mismatch=True, out=out)
         for _ in range(args.warmup):
             step()
         torch.cuda.synchronize()
@@ -152,6 +162,40 @@ def main():
     forms["fp64"] = time_form("fp64")
     for mode in ("fp32", "mixed_bf16", "mixed_fp16"):
         forms[mode] = time_form(mode)
+
+    # ---- learned warm start: trained (outside the timed region) on FPI-solved steps of a
+    # separately seeded year, then its inference runs inside every timed step
+    warm = None
+    if not args.no_warm_start:
+        t0 = time.perf_counter()
+        S_tr = torch.from_numpy(W.profile_minute_year(f, steps=args.train_steps, seed=W.SEED_TRAIN)).to(dev)
+        t_tr = torch.arange(args.train_steps, dtype=torch.int64, device=dev)
+        V_tr, _, st_tr = tpf.solve_timeseries(net, S_tr, 1e-10, 100, "fp64")
+        torch.cuda.synchronize()
+        data_s = time.perf_counter() - t0
+        mlp = tpf.WarmStart(n, params=W.mlp_init_params(W.mlp_sizes(n)))
+        t0 = time.perf_counter()
+        hist = mlp.fit(S_tr, t_tr, V_tr, epochs=args.train_epochs, batch=1024, lr=1e-3)
+        torch.cuda.synchronize()
+        train_s = time.perf_counter() - t0
+        del S_tr, V_tr
+        t_year = torch.arange(T, dtype=torch.int64, device=dev)
+        V0buf = torch.empty_like(S)
+        # inference alone
+        evp = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
+        for a, b in evp:
+            a.record(stream)
+            mlp.predict(S, t_year, out=V0buf)
+            b.record(stream)
+        torch.cuda.synchronize()
+        pred_ms = float(np.mean([a.elapsed_time(b) for a, b in evp]))
+        start_err = float((V0buf - forms["fp64"]["V"]).abs().max())
+        warm = {"train_steps": args.train_steps, "epochs": args.train_epochs, "final_loss": hist[-1],
+                "training_s": train_s, "training_data_s": data_s, "predict_ms": pred_ms,
+                "max_start_error_pu": start_err}
+        for mode in ("fp64", "mixed_fp16", "mixed_bf16"):
+            r = time_form(mode, V0=V0buf, mlp=(mlp, t_year))
+            forms[mode + "+warm"] = r
     Vref = forms["fp64"]["V"]
     for mode, r in forms.items():
         r["max_err_vs_fp64_pu"] = float((r["V"] - Vref).abs().max())
@@ -174,7 +218,8 @@ def main():
     torch.cuda.synchronize()
     mm_ms = float(np.mean([a.elapsed_time(b) for a, b in ev2]))
 
-    head = min(("mixed_bf16", "mixed_fp16"), key=lambda m: forms[m]["ms_per_step"])
+    cands = [m for m in forms if m.startswith("mixed") and m.endswith("+warm")] or ["mixed_bf16", "mixed_fp16"]
+    head = min(cands, key=lambda m: forms[m]["ms_per_step"])
     hf = forms[head]
     base = forms["fp64"]
     for r in forms.values():
@@ -195,14 +240,15 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f16" if head == "mixed_fp16" else "bf16",
+        "dtype": "f16" if head.startswith("mixed_fp16") else "bf16",
         "data": "synthetic (seeded k-ary radial feeder, sinusoid x lognormal minute profiles)",
         "config": {"workload": "100-bus radial feeder (99 PQ), 525,600 one-minute steps, complex128 S, "
-                               "flat start, tol 1e-6 pu max|dV|, max 100 sweeps, + FP64 mismatch",
+                               "tol 1e-6 pu max|dV|, max 100 sweeps, + FP64 mismatch",
                    "form": head, "n_pq": n, "power_flows": T},
+        "warm_start": warm,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_F16_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_F16_TFLOPS, "traffic": _traffic_from_profiles(f"{head}/year100"),
-                     "kernel": f"fpi_mixed_kernel<2,8,7,{head}>", "kernel_ms": hf["kernel_ms"],
+                     "kernel": f"fpi_mixed_kernel<2,8,7,{head.split('+')[0]}>", "kernel_ms": hf["kernel_ms"],
                      "algorithmic_flops": flops},
         "fp64_form": {"value": base["power_flows_per_s"], "ms_per_step": base["ms_per_step"],
                       "roofline": {"bound": "mfma", "achieved": ach64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",

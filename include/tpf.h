@@ -56,9 +56,18 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
 /* Arithmetic of the sweeps.
  *   FP64        every sweep in FP64 (MFMA FP64), state in FP64;
  *   FP32        every sweep in FP32 (MFMA FP32), state kept as FP32 drop V - w;
- *   MIXED_BF16  low-precision sweeps on BF16 MFMA (FP32 accumulation) refined by
- *   MIXED_FP16  FP32 sweeps; convergence is only declared on a refined iterate.
- *   In FP32 and mixed modes tol must be >= 5e-7 pu (the FP32 state floor). */
+ *   MIXED_BF16  sweeps on BF16 MFMA with FP32 accumulation until the low-precision
+ *               iteration stalls, then FP32-accurate sweeps (one full FP32 sweep, then
+ *               sweeps on the change of the injections) to the tolerance;
+ *   MIXED_FP16  the same with FP16 operands under a per-column power-of-two scale; its
+ *               FP32-accurate sweep splits Z and I into FP16 high and low parts.
+ *   Convergence is only declared on an FP32-accurate iterate.  In FP32 and mixed
+ *   modes tol must be >= 5e-7 pu (the FP32 state floor).
+ * Network size: FP64 runs any n; FP32 any n; the mixed modes run n <= 128 and return
+ * TPF_ERR_UNSUPPORTED above.  FP64 beyond 320 and FP32 beyond 128 PQ buses use a
+ * per-sweep kernel sequence (dense Z no longer fits one workgroup's registers) whose
+ * host loop waits for the device once per sweep; smaller networks run one persistent
+ * kernel per solve. */
 enum { TPF_MODE_FP64 = 0, TPF_MODE_FP32 = 1, TPF_MODE_MIXED_BF16 = 2, TPF_MODE_MIXED_FP16 = 3 };
 
 /* Per-column outcome written to status_out. */
@@ -102,7 +111,9 @@ int tpf_network_n_pq(tpf_network net);
 int tpf_network_get_zw(tpf_network net, double *Z_out, double *w_out);
 
 /* Bytes of device workspace that tpf_solve_* needs for tau columns with these
- * options (opts may be NULL).  The solve calls allocate nothing themselves. */
+ * options (opts may be NULL).  The solve calls allocate nothing themselves.  Small
+ * networks need 256 B; the per-sweep path for large networks holds its state, operand
+ * and active lists there (about tau * 2n * 16 B in FP64). */
 size_t tpf_workspace_bytes(tpf_network net, int64_t tau, const tpf_options *opts);
 
 /* Algorithm 1 over a [T][n] load matrix (Sec. IV-A: each time step is a column).

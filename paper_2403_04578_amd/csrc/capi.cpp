@@ -20,9 +20,9 @@ int check_launch(const char *what) {
 }  // namespace
 
 extern "C" size_t tpf_workspace_bytes(tpf_network net, int64_t tau, const tpf_options *opts) {
-    (void)net;
-    (void)tau;
-    (void)opts;
+    if (!net || tau < 0) return kQueueBytes;
+    const int mode = opts ? opts->mode : TPF_MODE_FP64;
+    if (uses_large_path(net->n, mode)) return large_workspace_bytes(net->n, tau, mode);
     return kQueueBytes;
 }
 
@@ -54,6 +54,9 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
     bool fused_mismatch = false;  // the sweep kernel computed the mismatch at retirement
     if (max_iter == 0) {
         rc = launch_start_only(n, V0, dtype, T, V_out, iters_out, status_out, st);
+    } else if (uses_large_path(n, mode)) {
+        rc = launch_fpi_large(*net, *dn, mode, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out,
+                              workspace, st);
     } else if (n <= 8 * kMaxSmallTiles) {
         auto *queue = reinterpret_cast<unsigned long long *>(workspace);
         rc = launch_zero_u64(queue, 1, st);
@@ -69,7 +72,7 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
             fused_mismatch = true;
         }
     } else {
-        return fail(TPF_ERR_UNSUPPORTED, "networks with more than 320 PQ buses are not implemented yet");
+        return fail(TPF_ERR_UNSUPPORTED, "no sweep path for this network size and mode");
     }
     if (rc != TPF_OK) return rc;
     rc = check_launch("sweep kernel launch");

@@ -1,0 +1,712 @@
+// Sweep path for networks too large for the register-resident kernels (the dense
+// operator no longer fits one workgroup): every sweep of Algorithm 1 runs as
+//   inject  I = conj(S./V) for the active columns (Eq. (3)), written as the B operand
+//           [active][K] with K = interleaved Re/Im per bus;
+//   gemm    V' = Z I + w on MFMA (64 x 64 output tiles, K staged through LDS), whose
+//           epilogue updates the state in place and reduces max |V' - V| per column
+//           with atomics;
+//   finish  one wave per active column: sweep count, stopping rule, retirement to the
+//           output and compaction of the active list for the next sweep.
+// FP64 mode keeps the state V in FP64; FP32 mode keeps the FP32 drop U = V - w.
+// The host reads the active count back once per sweep to size the next launches and
+// to stop once every column has retired.
+#include "tpf_internal.h"
+
+namespace tpf {
+
+typedef double d4x __attribute__((ext_vector_type(4)));
+typedef float f4x __attribute__((ext_vector_type(4)));
+
+namespace {
+
+template <typename T>
+struct Acc;
+template <>
+struct Acc<double> {
+    typedef d4x v4;
+    __device__ static v4 mma(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // FP64 16x16x4 output: lane group g holds tile rows g + 4 r
+    __device__ static int row(int g, int r) { return g + 4 * r; }
+};
+template <>
+struct Acc<float> {
+    typedef f4x v4;
+    __device__ static v4 mma(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    // FP32 16x16x4 output: lane group g holds tile rows 4 g + r
+    __device__ static int row(int g, int r) { return 4 * g + r; }
+};
+
+// Row r of the operator (output order) -> (bus, part).  FP64: 16-row tiles of 8 buses,
+// Re in rows 0-7, Im in rows 8-15 (so a lane holds both parts of a bus); FP32:
+// interleaved Re/Im.  The K order is always interleaved.
+template <typename T>
+__device__ __forceinline__ void row_bus(int r, int &bus, int &part) {
+    if constexpr (sizeof(T) == 8) {
+        bus = 8 * (r >> 4) + (r & 7);
+        part = (r >> 3) & 1;
+    } else {
+        bus = r >> 1;
+        part = r & 1;
+    }
+}
+
+// State x[col][2 n]: FP64 mode holds V, FP32 mode holds U = V - w.
+template <typename T, typename IO>
+__global__ void init_kernel(const IO *__restrict__ V0, const double *__restrict__ w, int n, long long tau, T *x,
+                            int32_t *iters, long long *act, int *na, unsigned long long *dmax) {
+    const long long c = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= tau) return;
+    int ok = V0 != nullptr;
+    if (V0)
+        for (int b = lane; b < n; b += 64) {
+            const double vr = (double)V0[2 * (c * n + b)], vi = (double)V0[2 * (c * n + b) + 1];
+            const double m2 = vr * vr + vi * vi;
+            ok &= (m2 >= 0.25 && m2 <= 2.25) ? 1 : 0;
+        }
+    for (int off = 32; off > 0; off >>= 1) ok &= __shfl_xor(ok, off);
+    for (int b = lane; b < n; b += 64) {
+        double vr = 1.0, vi = 0.0;
+        if (ok) vr = (double)V0[2 * (c * n + b)], vi = (double)V0[2 * (c * n + b) + 1];
+        if constexpr (sizeof(T) == 8) {
+            x[2 * (c * n + b)] = vr;
+            x[2 * (c * n + b) + 1] = vi;
+        } else {
+            x[2 * (c * n + b)] = (T)(vr - w[2 * b]);
+            x[2 * (c * n + b) + 1] = (T)(vi - w[2 * b + 1]);
+        }
+    }
+    if (lane == 0) {
+        iters[c] = 0;
+        act[c] = c;
+        dmax[c] = 0ull;
+        if (c == 0) na[0] = (int)tau;
+    }
+}
+
+template <typename T, typename IO>
+__global__ void inject_kernel(const IO *__restrict__ S, const T *__restrict__ x, const double *__restrict__ w, int n,
+                              int KP, const long long *__restrict__ act, const int *__restrict__ na, int rows,
+                              T *__restrict__ B) {
+    const long long total = (long long)rows * KP;
+    const int nact = *na;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total / 2;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long a = e / (KP / 2);
+        const int b = (int)(e - a * (KP / 2));
+        T ir = 0, ii = 0;
+        if (a < nact && b < n) {
+            const long long c = act[a];
+            const double sr = (double)S[2 * (c * n + b)], si = (double)S[2 * (c * n + b) + 1];
+            double vr = (double)x[2 * (c * n + b)], vi = (double)x[2 * (c * n + b) + 1];
+            if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
+            const double inv = 1.0 / (vr * vr + vi * vi);
+            ir = (T)((sr * vr + si * vi) * inv);
+            ii = (T)((sr * vi - si * vr) * inv);
+        }
+        B[a * KP + 2 * b] = ir;
+        B[a * KP + 2 * b + 1] = ii;
+    }
+}
+
+// C tile [64 rows][64 active columns] = A[rows][K] B[cols][K]^T; epilogue on the state.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_kernel(const T *__restrict__ A, int KP, const T *__restrict__ B,
+                                                   const long long *__restrict__ act, const int *__restrict__ na,
+                                                   const double *__restrict__ w, int n, T *__restrict__ x,
+                                                   unsigned long long *__restrict__ dmax, int *__restrict__ badf) {
+    using Ops = Acc<T>;
+    typedef typename Ops::v4 v4;
+    const int nact = *na;
+    const int c0 = blockIdx.x * 64;
+    if (c0 >= nact) return;
+    const int r0 = blockIdx.y * 64;
+    __shared__ T As[64][17];
+    __shared__ T Bs[64][17];
+    __shared__ double red[2][64];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    v4 acc[2][2];
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+    for (int k0 = 0; k0 < KP; k0 += 16) {
+        {
+            const int rr = tid >> 2, kk = (tid & 3) * 4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                As[rr][kk + e] = A[(size_t)(r0 + rr) * KP + k0 + kk + e];
+                Bs[rr][kk + e] = B[(size_t)(c0 + rr) * KP + k0 + kk + e];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            T af[2], bf[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) af[a] = As[wr + 16 * a + j][4 * ks + g];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[wc + 16 * b + j][4 * ks + g];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = Ops::mma(af[a], bf[b], acc[a][b]);
+        }
+        __syncthreads();
+    }
+    // epilogue: each lane holds both parts of two buses (FP64 layout) or of two buses
+    // (FP32 interleaved layout: rows 4g..4g+3 = Re/Im of two buses) of column j
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+        const int ac = c0 + wc + 16 * b + j;
+        double emax = 0.0;
+        int bad = 0;
+        const bool live = ac < nact;
+        const long long c = live ? act[ac] : 0;
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            const int tile0 = r0 + wr + 16 * a;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                // the two registers holding Re and Im of one bus
+                const int rre = sizeof(T) == 8 ? h : 2 * h, rim = sizeof(T) == 8 ? h + 2 : 2 * h + 1;
+                int bus, part;
+                row_bus<T>(tile0 + Ops::row(g, rre), bus, part);
+                if (live && bus < n) {
+                    const double nr = (double)acc[a][b][rre] + (sizeof(T) == 8 ? w[2 * bus] : 0.0);
+                    const double ni = (double)acc[a][b][rim] + (sizeof(T) == 8 ? w[2 * bus + 1] : 0.0);
+                    T *xp = x + 2 * (c * n + bus);
+                    const double dr = nr - (double)xp[0], di = ni - (double)xp[1];
+                    const double e2 = dr * dr + di * di;
+                    bad |= !(e2 < HUGE_VAL);
+                    emax = e2 > emax ? e2 : emax;
+                    xp[0] = (T)nr;
+                    xp[1] = (T)ni;
+                }
+            }
+        }
+        emax = fmax(emax, __shfl_xor(emax, 16));
+        emax = fmax(emax, __shfl_xor(emax, 32));
+        bad |= __shfl_xor(bad, 16);
+        bad |= __shfl_xor(bad, 32);
+        if (g == 0) {
+            red[wave >> 1][wc + 16 * b + j] = emax;
+            if (live && bad) atomicOr(badf + c, 1);
+        }
+    }
+    __syncthreads();
+    if (tid < 64 && c0 + tid < nact) {  // non-negative doubles order like their bit patterns
+        const double e = fmax(red[0][tid], red[1][tid]);
+        atomicMax(dmax + act[c0 + tid], (unsigned long long)__double_as_longlong(e));
+    }
+}
+
+template <typename T, typename IO>
+__global__ void finish_kernel(const long long *__restrict__ act, const int *__restrict__ na, const T *__restrict__ x,
+                              const double *__restrict__ w, int n, double tol, int max_iter,
+                              unsigned long long *__restrict__ dmax, int *__restrict__ badf, int32_t *iters,
+                              int8_t *status, IO *__restrict__ V, long long *__restrict__ act_next, int *na_next) {
+    const long long a = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (a >= *na) return;
+    const long long c = act[a];
+    const double e = __longlong_as_double((long long)dmax[c]);
+    const int bad = badf[c];
+    const int it = iters[c] + 1;
+    const bool conv = !bad && sqrt(e) < tol;
+    const bool done = bad || conv || it >= max_iter;
+    if (done) {
+        for (int b = lane; b < n; b += 64) {
+            double vr = (double)x[2 * (c * n + b)], vi = (double)x[2 * (c * n + b) + 1];
+            if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
+            V[2 * (c * n + b)] = (IO)vr;
+            V[2 * (c * n + b) + 1] = (IO)vi;
+        }
+    }
+    if (lane == 0) {
+        iters[c] = it;
+        dmax[c] = 0ull;
+        if (done) {
+            status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+        } else {
+            act_next[atomicAdd(na_next, 1)] = c;
+        }
+    }
+}
+
+__global__ void zero_i32_kernel(int *p, long long count) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// ---- mixed precision (BF16 / FP16 operands) for large networks
+//
+// Each column follows the schedule of the register-resident mixed kernel: full
+// low-precision sweeps U' = Z I until its step reaches the low-precision floor or
+// stalls; one FP32 sweep (refine) that makes U = Z I_prev FP32-accurate; then
+// low-precision sweeps on the change of the injection, U' = U + Z (I - I_prev), with a
+// new refine once the distance they travelled makes their rounding matter.  Columns
+// are kept in two lists per sweep, refine and low, each with its own product.
+
+struct MixState {
+    int it, ph, want;            // sweeps done; 0 = full low sweeps, 1 = difference sweeps; refine wanted
+    float dprev, sumd, uref;     // previous step, steps since the last refine, max |U| seen
+    float ks, inv;               // B scale 2^sB and product unscale 2^-(sB + sZ) (FP16); 1, 1 (BF16)
+};
+
+typedef short s8x __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8x __attribute__((ext_vector_type(8)));
+typedef _Float16 h8x __attribute__((ext_vector_type(8)));
+
+template <int MODE>
+struct Low16;
+template <>
+struct Low16<TPF_MODE_MIXED_BF16> {
+    static constexpr float u = 0.00390625f;  // 2^-8
+    __device__ static uint32_t enc2(float a, float b) {
+        return (uint32_t)__builtin_bit_cast(uint16_t, (__bf16)a) |
+               ((uint32_t)__builtin_bit_cast(uint16_t, (__bf16)b) << 16);
+    }
+    __device__ static f4x mma(const uint4 &a, const uint4 &b, const f4x &c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8x, a), __builtin_bit_cast(bf8x, b), c,
+                                                       0, 0, 0);
+    }
+};
+template <>
+struct Low16<TPF_MODE_MIXED_FP16> {
+    static constexpr float u = 0.00048828125f;  // 2^-11
+    __device__ static uint32_t enc2(float a, float b) {
+        a = __builtin_amdgcn_fmed3f(a, -65504.f, 65504.f);
+        b = __builtin_amdgcn_fmed3f(b, -65504.f, 65504.f);
+        return (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)a) |
+               ((uint32_t)__builtin_bit_cast(uint16_t, (_Float16)b) << 16);
+    }
+    __device__ static f4x mma(const uint4 &a, const uint4 &b, const f4x &c) {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8x, a), __builtin_bit_cast(h8x, b), c, 0,
+                                                      0, 0);
+    }
+};
+
+// One wave per column: FP16 scale from max |S| and the initial schedule state.
+template <int MODE, typename IO>
+__global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, int sZ, MixState *ms,
+                                unsigned *umax) {
+    const long long c = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (c >= tau) return;
+    float sm = 0.f;
+    if (MODE == TPF_MODE_MIXED_FP16)
+        for (int b = lane; b < n; b += 64) {
+            const float sr = fabsf((float)S[2 * (c * n + b)]), si = fabsf((float)S[2 * (c * n + b) + 1]);
+            sm = fmaxf(sm, fmaxf(sr, si));  // non-finite loads retire after one sweep anyway
+        }
+    for (int off = 32; off > 0; off >>= 1) sm = fmaxf(sm, __shfl_xor(sm, off));
+    if (lane == 0) {
+        int sB = 0;
+        if (MODE == TPF_MODE_MIXED_FP16) {
+            int e = 0;
+            (void)frexpf(sm > 0.f && sm < 1e30f ? sm : 1.0f, &e);
+            sB = 12 - e;  // max |S| 2^sB < 2^12: |I| 2^sB < 2^15 while |V| > 1/4
+        }
+        MixState m;
+        m.it = m.ph = m.want = 0;
+        m.dprev = m.sumd = m.uref = 0.f;
+        m.ks = ldexpf(1.0f, sB);
+        m.inv = ldexpf(1.0f, -(sB + (MODE == TPF_MODE_MIXED_FP16 ? sZ : 0)));
+        ms[c] = m;
+        umax[c] = 0u;
+    }
+}
+
+// I = conj(S./V) in FP32 for the refine list: B32 [rows][KP] and I_prev.
+template <typename IO>
+__global__ void inject_refine_kernel(const IO *__restrict__ S, const float *__restrict__ U,
+                                     const double *__restrict__ w, float *__restrict__ Ip, int n, int KP,
+                                     const long long *__restrict__ act, const int *__restrict__ na, int rows,
+                                     float *__restrict__ B) {
+    const int nact = *na;
+    const int half = KP / 2;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)rows * half;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long a = e / half;
+        const int b = (int)(e - a * half);
+        float2 out = make_float2(0.f, 0.f);
+        if (a < nact && b < n) {
+            const long long c = act[a], o = 2 * (c * n + b);
+            const float sr = (float)S[o], si = (float)S[o + 1];
+            const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
+            const float r = 1.0f / (vr * vr + vi * vi);
+            out = make_float2((sr * vr + si * vi) * r, (sr * vi - si * vr) * r);
+            *reinterpret_cast<float2 *>(Ip + o) = out;
+        }
+        *reinterpret_cast<float2 *>(B + a * KP + 2 * b) = out;
+    }
+}
+
+// Low list: B16 [rows][KP16] holds (I 2^sB) for full sweeps, ((I - I_prev) 2^sB) for
+// difference sweeps; I_prev <- I.
+template <int MODE, typename IO>
+__global__ void inject_low_kernel(const IO *__restrict__ S, const float *__restrict__ U,
+                                  const double *__restrict__ w, float *__restrict__ Ip,
+                                  const MixState *__restrict__ ms, int n, int KP16,
+                                  const long long *__restrict__ act, const int *__restrict__ na, int rows,
+                                  uint32_t *__restrict__ B) {
+    const int nact = *na;
+    const int half = KP16 / 2;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)rows * half;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long a = e / half;
+        const int b = (int)(e - a * half);
+        uint32_t out = 0u;
+        if (a < nact && b < n) {
+            const long long c = act[a], o = 2 * (c * n + b);
+            const int ph = ms[c].ph;
+            const float ks = ms[c].ks;
+            const float sr = (float)S[o], si = (float)S[o + 1];
+            const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
+            const float r = 1.0f / (vr * vr + vi * vi);
+            const float ir = (sr * vr + si * vi) * r, ii = (sr * vi - si * vr) * r;
+            float br = ir, bi = ii;
+            float2 *ip = reinterpret_cast<float2 *>(Ip + o);
+            if (ph) {
+                const float2 p = *ip;
+                br -= p.x;
+                bi -= p.y;
+            }
+            *ip = make_float2(ir, ii);
+            out = Low16<MODE>::enc2(br * ks, bi * ks);
+        }
+        B[a * half + b] = out;
+    }
+}
+
+// C tile [128 rows][128 active columns] = A16[rows][K] B16[cols][K]^T on 16x16x32 MFMA;
+// epilogue U' = C inv (full) or U + C inv (difference), step and max |U'| per column.
+template <int MODE>
+__global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restrict__ A, int KP16,
+                                                       const uint16_t *__restrict__ B,
+                                                       const long long *__restrict__ act, const int *__restrict__ na,
+                                                       const MixState *__restrict__ ms, int n, float *__restrict__ U,
+                                                       unsigned long long *__restrict__ dmax,
+                                                       unsigned *__restrict__ umax, int *__restrict__ badf) {
+    const int nact = *na;
+    const int c0 = blockIdx.x * 128;
+    if (c0 >= nact) return;
+    const int r0 = blockIdx.y * 128;
+    __shared__ uint4 As[128][5];  // 32 K values per row + one pad quad against bank conflicts
+    __shared__ uint4 Bs[128][5];
+    __shared__ float redd[2][128], redu[2][128];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, j = lane & 15;
+    const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
+    f4x acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = f4x{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < KP16; k0 += 32) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int idx = tid + 256 * h, row = idx >> 2, q = idx & 3;
+            As[row][q] = *reinterpret_cast<const uint4 *>(A + (size_t)(r0 + row) * KP16 + k0 + 8 * q);
+            Bs[row][q] = *reinterpret_cast<const uint4 *>(B + (size_t)(c0 + row) * KP16 + k0 + 8 * q);
+        }
+        __syncthreads();
+        uint4 af[4], bf[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = As[wr + 16 * a + j][g];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bf[b] = Bs[wc + 16 * b + j][g];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = Low16<MODE>::mma(af[a], bf[b], acc[a][b]);
+        __syncthreads();
+    }
+    // lane group g holds rows 4g..4g+3 of each 16-row tile: Re/Im of two buses
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+        const int ac = c0 + wc + 16 * b + j;
+        const bool live = ac < nact;
+        const long long c = live ? act[ac] : 0;
+        int ph = 0;
+        float inv = 1.f;
+        if (live) {
+            ph = ms[c].ph;
+            inv = ms[c].inv;
+        }
+        float emax = 0.f, umx = 0.f;
+        int bad = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int bus = (r0 + wr + 16 * a + 4 * g + 2 * h) >> 1;
+                if (live && bus < n) {
+                    float2 *up = reinterpret_cast<float2 *>(U + 2 * (c * n + bus));
+                    const float2 old = *up;
+                    const float pr = acc[a][b][2 * h] * inv, pi = acc[a][b][2 * h + 1] * inv;
+                    const float nr = ph ? old.x + pr : pr, ni = ph ? old.y + pi : pi;
+                    const float dr = nr - old.x, di = ni - old.y;
+                    const float e2 = dr * dr + di * di;
+                    bad |= !(e2 < HUGE_VALF);
+                    emax = e2 > emax ? e2 : emax;
+                    umx = fmaxf(umx, fmaxf(fabsf(nr), fabsf(ni)));
+                    *up = make_float2(nr, ni);
+                }
+            }
+        }
+        emax = fmaxf(emax, __shfl_xor(emax, 16));
+        emax = fmaxf(emax, __shfl_xor(emax, 32));
+        umx = fmaxf(umx, __shfl_xor(umx, 16));
+        umx = fmaxf(umx, __shfl_xor(umx, 32));
+        bad |= __shfl_xor(bad, 16);
+        bad |= __shfl_xor(bad, 32);
+        if (g == 0) {
+            redd[wave >> 1][wc + 16 * b + j] = emax;
+            redu[wave >> 1][wc + 16 * b + j] = umx;
+            if (live && bad) atomicOr(badf + c, 1);
+        }
+    }
+    __syncthreads();
+    if (tid < 128 && c0 + tid < nact) {  // non-negative values order like their bit patterns
+        const long long c = act[c0 + tid];
+        const double e = (double)fmaxf(redd[0][tid], redd[1][tid]);
+        atomicMax(dmax + c, (unsigned long long)__double_as_longlong(e));
+        atomicMax(umax + c, __float_as_uint(fmaxf(redu[0][tid], redu[1][tid])));
+    }
+}
+
+// One wave per column of the refine list (first) and the low list: schedule update,
+// retirement, and the next sweep's lists.
+template <int MODE, typename IO>
+__global__ void finish_mixed_kernel(const long long *__restrict__ actR, const long long *__restrict__ actL,
+                                    const int *__restrict__ cnt, const float *__restrict__ U,
+                                    const double *__restrict__ w, int n, float tol, int max_iter,
+                                    unsigned long long *__restrict__ dmax, unsigned *__restrict__ umax,
+                                    const int *__restrict__ badf, MixState *__restrict__ ms, int32_t *iters,
+                                    int8_t *status, IO *__restrict__ V, long long *__restrict__ nextR,
+                                    long long *__restrict__ nextL, int *cnt_next) {
+    const long long a = blockIdx.x * 4LL + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int nl = cnt[0], nr = cnt[1];
+    if (a >= (long long)nr + nl) return;
+    const bool refine = a < nr;
+    const long long c = refine ? actR[a] : actL[a - nr];
+    MixState m = ms[c];
+    const float d = (float)sqrt(__longlong_as_double((long long)dmax[c]));
+    const float um = __uint_as_float(umax[c]);
+    const int bad = badf[c];
+    constexpr float u = Low16<MODE>::u;
+    const float theta = 4.0f * u, refresh = 6.7e-8f / u, margin = 1.0f + 8.0f * u;
+    m.it += 1;
+    bool conv = false;
+    if (refine) {
+        conv = d < tol;
+        m.ph = 1;
+        m.want = 0;
+        m.sumd = 0.f;
+    } else if (m.ph == 0) {
+        m.uref = fmaxf(m.uref, um);
+        if (!m.want && (d < theta * m.uref || (m.it >= 2 && d > 0.5f * m.dprev))) m.want = 1;
+    } else {
+        conv = d * margin < tol;
+        m.sumd += d;
+        if (!m.want && m.sumd > refresh) m.want = 1;
+    }
+    m.dprev = d;
+    const bool done = bad || conv || m.it >= max_iter;
+    if (done)
+        for (int b = lane; b < n; b += 64) {
+            V[2 * (c * n + b)] = (IO)(w[2 * b] + (double)U[2 * (c * n + b)]);
+            V[2 * (c * n + b) + 1] = (IO)(w[2 * b + 1] + (double)U[2 * (c * n + b) + 1]);
+        }
+    if (lane == 0) {
+        iters[c] = m.it;
+        dmax[c] = 0ull;
+        umax[c] = 0u;
+        ms[c] = m;
+        if (done)
+            status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+        else if (m.want)
+            nextR[atomicAdd(cnt_next + 1, 1)] = c;
+        else
+            nextL[atomicAdd(cnt_next, 1)] = c;
+    }
+}
+
+}  // namespace
+
+// Workspace of the large path: state [tau][2n] (T), B operand [tau rounded to 64][KP] (T),
+// dmax [tau] (u64), bad flags [tau] (int), two active lists [tau] (i64), counters.
+// Mixed modes add I_prev [tau][2n] (FP32), the 16-bit B operand [tau rounded to 128][KP16],
+// per-column schedule state and max |U| [tau], and two more active lists.
+size_t large_workspace_bytes(int n, int64_t tau, int mode) {
+    const size_t ts = mode == TPF_MODE_FP64 ? 8 : 4;
+    const size_t KP = (size_t)(2 * n + 15) / 16 * 16;
+    const size_t rows = (size_t)(tau + 63) / 64 * 64;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t bytes = al((size_t)tau * 2 * n * ts) + al(rows * KP * ts) + al((size_t)tau * 8) + al((size_t)tau * 4) +
+                   2 * al((size_t)tau * 8) + 256;
+    if (mode == TPF_MODE_MIXED_BF16 || mode == TPF_MODE_MIXED_FP16) {
+        const size_t K16 = (size_t)(2 * n + 31) / 32 * 32, rows16 = (size_t)(tau + 127) / 128 * 128;
+        bytes += al((size_t)tau * 2 * n * 4) + al(rows16 * K16 * 2) + al((size_t)tau * sizeof(MixState)) +
+                 al((size_t)tau * 4) + 2 * al((size_t)tau * 8);
+    }
+    return bytes;
+}
+
+template <typename T, typename IO>
+static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
+                     int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status, void *ws,
+                     hipStream_t st) {
+    const int n = net.n;
+    const int KP = (2 * n + 15) / 16 * 16;
+    const int64_t rows = (tau + 63) / 64 * 64;
+    const int MP = sizeof(T) == 8 ? dn.MPL64 : dn.MPL32;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    char *p = static_cast<char *>(ws);
+    T *x = reinterpret_cast<T *>(p);
+    p += al((size_t)tau * 2 * n * sizeof(T));
+    T *B = reinterpret_cast<T *>(p);
+    p += al((size_t)rows * KP * sizeof(T));
+    auto *dmax = reinterpret_cast<unsigned long long *>(p);
+    p += al((size_t)tau * 8);
+    int *badf = reinterpret_cast<int *>(p);
+    p += al((size_t)tau * 4);
+    long long *act[2];
+    act[0] = reinterpret_cast<long long *>(p);
+    p += al((size_t)tau * 8);
+    act[1] = reinterpret_cast<long long *>(p);
+    p += al((size_t)tau * 8);
+    int *cnt = reinterpret_cast<int *>(p);  // [0], [1]: active counts of the two lists
+    const T *A = sizeof(T) == 8 ? (const T *)(const void *)dn.AL64 : (const T *)(const void *)dn.AL32;
+    const double *w = dn.wl;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)std::min<int64_t>(65536, (tau + 255) / 256)), dim3(256), 0, st,
+                       badf, (long long)tau);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cnt, 2LL);
+    hipLaunchKernelGGL((init_kernel<T, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)V0, w, n,
+                       (long long)tau, x, iters, act[0], cnt, dmax);
+    int na = (int)tau, cur = 0;
+    for (int sweep = 0; sweep < max_iter && na > 0; ++sweep) {
+        const long long arows = (na + 63) / 64 * 64;
+        hipLaunchKernelGGL((inject_kernel<T, IO>), dim3((unsigned)std::min<long long>(65536, (arows * KP / 2 + 255) / 256)),
+                           dim3(256), 0, st, (const IO *)S, x, w, n, KP, act[cur], cnt + cur, (int)arows, B);
+        hipLaunchKernelGGL((gemm_kernel<T>), dim3((unsigned)(arows / 64), (unsigned)(MP / 64)), dim3(256), 0, st, A, KP,
+                           B, act[cur], cnt + cur, w, n, x, dmax, badf);
+        hipLaunchKernelGGL((finish_kernel<T, IO>), dim3((unsigned)((na + 3) / 4)), dim3(256), 0, st, act[cur],
+                           cnt + cur, x, w, n, tol, max_iter, dmax, badf, iters, status, (IO *)V,
+                           act[cur ^ 1], cnt + (cur ^ 1));
+        // next sweep's count to the host; the list just consumed is cleared for reuse
+        int next = 0;
+        if (hipMemcpyAsync(&next, cnt + (cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+            return fail(TPF_ERR_DEVICE, "active-count copy failed");
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cnt + cur, 1LL);
+        if (hipStreamSynchronize(st) != hipSuccess) return fail(TPF_ERR_DEVICE, "large sweep failed");
+        na = next;
+        cur ^= 1;
+    }
+    return TPF_OK;
+}
+
+template <int MODE, typename IO>
+static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
+                           int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status, void *ws,
+                           hipStream_t st) {
+    const int n = net.n;
+    const int KP = (2 * n + 15) / 16 * 16, K16 = (2 * n + 31) / 32 * 32;
+    const int64_t rows = (tau + 63) / 64 * 64, rows16 = (tau + 127) / 128 * 128;
+    const int MP = dn.MPL32;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    // same carve as large_workspace_bytes: the FP32 part first, then the mixed additions
+    char *p = static_cast<char *>(ws);
+    float *U = reinterpret_cast<float *>(p);
+    p += al((size_t)tau * 2 * n * 4);
+    float *B32 = reinterpret_cast<float *>(p);
+    p += al((size_t)rows * KP * 4);
+    auto *dmax = reinterpret_cast<unsigned long long *>(p);
+    p += al((size_t)tau * 8);
+    int *badf = reinterpret_cast<int *>(p);
+    p += al((size_t)tau * 4);
+    long long *actL[2], *actR[2];
+    actL[0] = reinterpret_cast<long long *>(p);
+    p += al((size_t)tau * 8);
+    actL[1] = reinterpret_cast<long long *>(p);
+    p += al((size_t)tau * 8);
+    int *cnt = reinterpret_cast<int *>(p);  // [2 * parity + {0: low, 1: refine}]
+    p += 256;
+    float *Ip = reinterpret_cast<float *>(p);
+    p += al((size_t)tau * 2 * n * 4);
+    uint16_t *B16 = reinterpret_cast<uint16_t *>(p);
+    p += al((size_t)rows16 * K16 * 2);
+    MixState *ms = reinterpret_cast<MixState *>(p);
+    p += al((size_t)tau * sizeof(MixState));
+    unsigned *umax = reinterpret_cast<unsigned *>(p);
+    p += al((size_t)tau * 4);
+    actR[0] = reinterpret_cast<long long *>(p);
+    p += al((size_t)tau * 8);
+    actR[1] = reinterpret_cast<long long *>(p);
+    const double *w = dn.wl;
+    const uint16_t *A16 = MODE == TPF_MODE_MIXED_FP16 ? dn.ALh : dn.ALbf;
+    hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)std::min<int64_t>(65536, (tau + 255) / 256)), dim3(256), 0, st,
+                       badf, (long long)tau);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cnt, 4LL);
+    hipLaunchKernelGGL((init_kernel<float, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)V0, w,
+                       n, (long long)tau, U, iters, actL[0], cnt, dmax);
+    hipLaunchKernelGGL((init_mix_kernel<MODE, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)S,
+                       n, (long long)tau, dn.sZ, ms, umax);
+    int nl = (int)tau, nr = 0, cur = 0;
+    for (int sweep = 0; sweep < max_iter && nl + nr > 0; ++sweep) {
+        int *cc = cnt + 2 * cur, *cn = cnt + 2 * (cur ^ 1);
+        if (nr > 0) {
+            const long long ar = (nr + 63) / 64 * 64;
+            hipLaunchKernelGGL((inject_refine_kernel<IO>), dim3((unsigned)std::min<long long>(65536, (ar * KP / 2 + 255) / 256)),
+                               dim3(256), 0, st, (const IO *)S, U, w, Ip, n, KP, actR[cur], cc + 1, (int)ar, B32);
+            hipLaunchKernelGGL((gemm_kernel<float>), dim3((unsigned)(ar / 64), (unsigned)(MP / 64)), dim3(256), 0, st,
+                               dn.AL32, KP, B32, actR[cur], cc + 1, w, n, U, dmax, badf);
+        }
+        if (nl > 0) {
+            const long long ar = (nl + 127) / 128 * 128;
+            hipLaunchKernelGGL((inject_low_kernel<MODE, IO>),
+                               dim3((unsigned)std::min<long long>(65536, (ar * K16 / 2 + 255) / 256)), dim3(256), 0, st,
+                               (const IO *)S, U, w, Ip, ms, n, K16, actL[cur], cc, (int)ar,
+                               reinterpret_cast<uint32_t *>(B16));
+            hipLaunchKernelGGL((gemm_low_kernel<MODE>), dim3((unsigned)(ar / 128), (unsigned)(MP / 128)), dim3(256), 0,
+                               st, A16, K16, B16, actL[cur], cc, ms, n, U, dmax, umax, badf);
+        }
+        hipLaunchKernelGGL((finish_mixed_kernel<MODE, IO>), dim3((unsigned)(((long long)nl + nr + 3) / 4)), dim3(256), 0,
+                           st, actR[cur], actL[cur], cc, U, w, n, (float)tol, max_iter, dmax, umax, badf, ms, iters,
+                           status, (IO *)V, actR[cur ^ 1], actL[cur ^ 1], cn);
+        int next[2] = {0, 0};
+        if (hipMemcpyAsync(next, cn, 2 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
+            return fail(TPF_ERR_DEVICE, "active-count copy failed");
+        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cc, 2LL);
+        if (hipStreamSynchronize(st) != hipSuccess) return fail(TPF_ERR_DEVICE, "large sweep failed");
+        nl = next[0];
+        nr = next[1];
+        cur ^= 1;
+    }
+    return TPF_OK;
+}
+
+int launch_fpi_large(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype, int64_t tau,
+                     double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status, void *ws,
+                     hipStream_t st) {
+    if (!dn.AL64) return fail(TPF_ERR_UNSUPPORTED, "large-network operator not staged");
+    if (mode == TPF_MODE_FP64)
+        return dtype == TPF_C128 ? run_large<double, double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, ws, st)
+                                 : run_large<double, float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, ws, st);
+    if (mode == TPF_MODE_FP32)
+        return dtype == TPF_C128 ? run_large<float, double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, ws, st)
+                                 : run_large<float, float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, ws, st);
+    if (!dn.ALbf) return fail(TPF_ERR_UNSUPPORTED, "16-bit large-network operator not staged");
+    if (mode == TPF_MODE_MIXED_BF16)
+        return dtype == TPF_C128
+                   ? run_large_mixed<TPF_MODE_MIXED_BF16, double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, ws, st)
+                   : run_large_mixed<TPF_MODE_MIXED_BF16, float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, ws, st);
+    return dtype == TPF_C128
+               ? run_large_mixed<TPF_MODE_MIXED_FP16, double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, ws, st)
+               : run_large_mixed<TPF_MODE_MIXED_FP16, float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, ws, st);
+}
+
+}  // namespace tpf

@@ -201,6 +201,48 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
             !h2d(dn.Ah, fh.data(), nl * 2) || !h2d(dn.Al, fl.data(), nl * 2))
             return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
     }
+    // ---- large-network operator (FP64 beyond the register kernels, FP32 beyond 128 buses)
+    if (n > 128) {
+        const int KP = (2 * n + 15) / 16 * 16, K16 = (2 * n + 31) / 32 * 32;
+        const int M64 = (16 * ((n + 7) / 8) + 63) / 64 * 64, M32 = (2 * n + 127) / 128 * 128;
+        dn.KPL = KP;
+        dn.KPL16 = K16;
+        dn.MPL64 = M64;
+        dn.MPL32 = M32;
+        double zmax = 0.0;
+        for (size_t i = 0; i < (size_t)n * n; ++i)
+            zmax = std::max(zmax, std::max(std::abs(net.Z[i].real()), std::abs(net.Z[i].imag())));
+        int e = 0;
+        (void)std::frexp(zmax > 0 ? zmax : 1.0, &e);
+        dn.sZ = 14 - e;  // FP16 operand Z 2^sZ: largest entry just below 2^14
+        std::vector<double> a64((size_t)M64 * KP, 0.0);
+        std::vector<float> a32((size_t)M32 * KP, 0.0f);
+        std::vector<uint16_t> abf((size_t)M32 * K16, 0), ah((size_t)M32 * K16, 0);
+        std::vector<double> wn(2 * n);
+        for (int i = 0; i < n; ++i) {
+            wn[2 * i] = net.w[i].real();
+            wn[2 * i + 1] = net.w[i].imag();
+            for (int k = 0; k < n; ++k) {
+                const cd z = net.Z[(size_t)i * n + k];
+                const double blk[2][2] = {{z.real(), -z.imag()}, {z.imag(), z.real()}};
+                for (int pi = 0; pi < 2; ++pi)
+                    for (int pk = 0; pk < 2; ++pk) {
+                        a64[(size_t)blk_pos(i, pi) * KP + 2 * k + pk] = blk[pi][pk];
+                        a32[(size_t)(2 * i + pi) * KP + 2 * k + pk] = (float)blk[pi][pk];
+                        abf[(size_t)(2 * i + pi) * K16 + 2 * k + pk] = to_bf16((float)blk[pi][pk]);
+                        ah[(size_t)(2 * i + pi) * K16 + 2 * k + pk] = to_f16((float)std::ldexp(blk[pi][pk], dn.sZ));
+                    }
+            }
+        }
+        if (!dalloc((void **)&dn.AL64, a64.size() * 8) || !dalloc((void **)&dn.AL32, a32.size() * 4) ||
+            !dalloc((void **)&dn.ALbf, abf.size() * 2) || !dalloc((void **)&dn.ALh, ah.size() * 2) ||
+            !dalloc((void **)&dn.wl, wn.size() * 8))
+            return fail(TPF_ERR_OOM, "device allocation failed (network staging)");
+        if (!h2d(dn.AL64, a64.data(), a64.size() * 8) || !h2d(dn.AL32, a32.data(), a32.size() * 4) ||
+            !h2d(dn.ALbf, abf.data(), abf.size() * 2) || !h2d(dn.ALh, ah.data(), ah.size() * 2) ||
+            !h2d(dn.wl, wn.data(), wn.size() * 8))
+            return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
+    }
     // ---- CSR Y_dd and c = Y_ds v_s (FP64 mismatch)
     {
         const size_t nnz = net.colidx.size();

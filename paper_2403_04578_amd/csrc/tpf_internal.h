@@ -45,6 +45,15 @@ struct DeviceNet {
     uint16_t *Abf = nullptr;     // BF16 fragments, [NW][TPW][KTL][64][8]
     uint16_t *Ah = nullptr;      // FP16 fragments of Z 2^sZ, [NW][TPW][KTL][64][8]
     uint16_t *Al = nullptr;      // FP16 residual Z 2^sZ - Ah, same layout
+    // Large-network path (fpi_large.hip): operator [MPL][KPL] row-major, K interleaved
+    // Re/Im per bus; FP64 rows in 16-row tiles of 8 buses (Re rows 0-7, Im rows 8-15),
+    // FP32-family rows interleaved (2 q + part).  wl = w as [n][2].  The 16-bit
+    // operands (BF16 Z, FP16 Z 2^sZ) have K padded to KPL16, a multiple of 32.
+    int MPL64 = 0, MPL32 = 0, KPL = 0, KPL16 = 0;
+    double *AL64 = nullptr;
+    float *AL32 = nullptr;
+    uint16_t *ALbf = nullptr, *ALh = nullptr;
+    double *wl = nullptr;
     // Sparse Y_dd (CSR) and c = Y_ds v_s for the FP64 mismatch.
     int32_t *rowptr = nullptr;   // [n+1]
     int32_t *colidx = nullptr;   // [nnz]
@@ -116,6 +125,13 @@ int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const vo
 int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype,
                      int64_t tau, double tol, int max_iter, const void *V0, void *V, int32_t *iters,
                      int8_t *status, unsigned long long *queue, double *mismatch_out, hipStream_t stream);
+int launch_fpi_large(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype,
+                     int64_t tau, double tol, int max_iter, const void *V0, void *V, int32_t *iters,
+                     int8_t *status, void *workspace, hipStream_t stream);
+size_t large_workspace_bytes(int n, int64_t tau, int mode);
+// The register-resident kernels cover FP64 up to 8 * kMaxSmallTiles PQ buses and the
+// FP32/mixed ones up to 128; larger networks use the large path (FP64, FP32).
+inline bool uses_large_path(int n, int mode) { return mode == TPF_MODE_FP64 ? n > 8 * kMaxSmallTiles : n > 128; }
 int launch_start_only(int n, const void *V0, int dtype, int64_t tau, void *V, int32_t *iters,
                       int8_t *status, hipStream_t stream);
 int launch_mismatch_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, const void *V,

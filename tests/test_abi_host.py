@@ -107,3 +107,23 @@ def test_solve_argument_checks_before_device_use():
     assert lib.tpf_solve_tensor(net.handle, fake, 1, -2, 5, 1e-6, 10, ctypes.byref(o), fake, fake, fake, ws, 256,
                                 None) == tpf.TPF_ERR_INVALID_ARG
     assert lib.tpf_workspace_bytes(net.handle, 1000, None) >= 8
+
+
+def test_workspace_sizes_by_path():
+    """Small networks need only the column queue; the per-sweep path for large networks
+    holds its state and operand (each tau x 2n values) in the workspace."""
+    lib = tpf.load_library()
+    small = tpf.Network.from_feeder(W.make_feeder(100))
+    o = tpf._Options()
+    assert lib.tpf_workspace_bytes(small.handle, 525_600, ctypes.byref(o)) == 256
+    big = tpf.Network.from_feeder(W.make_feeder(1000))
+    tau, n = 200_000, 999
+    for mode, size in [(tpf.MODE_FP64, 8), (tpf.MODE_FP32, 4)]:
+        o.mode = mode
+        need = lib.tpf_workspace_bytes(big.handle, tau, ctypes.byref(o))
+        assert 2 * tau * 2 * n * size <= need <= 2 * (tau + 64) * 2 * (n + 8) * size + 64 * tau
+    mid = tpf.Network.from_feeder(W.make_feeder(200))  # FP32 goes per-sweep above 128 PQ buses
+    o.mode = tpf.MODE_FP64
+    assert lib.tpf_workspace_bytes(mid.handle, 1000, ctypes.byref(o)) == 256
+    o.mode = tpf.MODE_FP32
+    assert lib.tpf_workspace_bytes(mid.handle, 1000, ctypes.byref(o)) > 1000 * 2 * 199 * 4

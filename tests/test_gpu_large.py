@@ -1,0 +1,188 @@
+"""GPU parity of the per-sweep path for networks beyond the register-resident kernels
+(FP64 above 320 PQ buses, FP32 above 128) against the CPU oracle (Algorithm 1).
+
+Bounds: FP64 1e-9 pu (same sweep count: rounding order only); FP32 1e-6 pu (the
+fast-form contract).  The 1,000-bus feeder solves 200,000 minute steps; the oracle
+recomputes a sample of columns and the FP64 mismatch bounds every column.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_04578_amd as tpf
+from paper_2403_04578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-9
+FAST_BOUND = 1e-6
+
+
+def _dev(S, gpu, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(S)).to(gpu).to(dtype).contiguous()
+
+
+def _compare(onet, S, V, it, st, tol, max_iter, bound, V0=None, rows=None):
+    """Columns with equal sweep counts agree to `bound`; a column whose last step sits on
+    the tolerance may stop one sweep apart and is re-run on the oracle with that count."""
+    ref = oracle.fpi(onet, S, tol, max_iter, V0)
+    Vg = V.cpu().numpy().astype(np.complex128).reshape(ref.V.shape)
+    ig = it.cpu().numpy().reshape(-1)
+    sg = st.cpu().numpy().reshape(-1)
+    same = ig == ref.iters
+    assert np.sum(~same) <= max(2, 0.002 * len(same)), f"sweep counts differ on {np.sum(~same)} columns"
+    err = np.abs(Vg[same] - ref.V[same]).max(initial=0.0)
+    assert err <= bound, f"max |dV| = {err:.3e}"
+    assert np.array_equal(sg[same], ref.status[same])
+    for c in np.nonzero(~same)[0]:
+        assert abs(int(ig[c]) - int(ref.iters[c])) <= 1
+        r2 = oracle.fpi(onet, S[c:c + 1], 0.0, int(ig[c]), None if V0 is None else V0[c:c + 1])
+        assert np.abs(Vg[c] - r2.V[0]).max() <= bound
+    return err
+
+
+@pytest.fixture(scope="module")
+def feeder1000():
+    f = W.make_feeder(1000)
+    return f, tpf.Network.from_feeder(f), oracle.build_feeder(f)
+
+
+@pytest.mark.parametrize("n_bus,T", [(322, 1), (322, 65), (401, 1000), (1000, 300)])
+def test_fp64_every_column(gpu, n_bus, T):
+    f = W.make_feeder(n_bus)
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=T, t0=4321)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-9, max_iter=100)
+    _compare(onet, S, V, it, st, 1e-9, 100, TOL_FP64)
+    assert int(st.max()) == tpf.ST_CONVERGED
+
+
+@pytest.mark.parametrize("k", [1, 3, 7])
+def test_fp64_fixed_sweeps(gpu, feeder1000, k):
+    f, net, onet = feeder1000
+    S = W.profile_minute_year(f, steps=129, t0=99)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=0.0, max_iter=k)
+    assert int(it.min()) == k and int(it.max()) == k
+    assert int(st.min()) == tpf.ST_MAX_ITER
+    _compare(onet, S, V, it, st, 0.0, k, 1e-12)
+
+
+@pytest.mark.parametrize("n_bus,T", [(130, 200), (300, 333), (1000, 300)])
+def test_fp32_every_column(gpu, n_bus, T):
+    f = W.make_feeder(n_bus)
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=T, t0=2024)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode="fp32")
+    ref = oracle.fpi(onet, S, 1e-10, 200)
+    assert int(st.max()) == tpf.ST_CONVERGED
+    err = np.abs(V.cpu().numpy() - ref.V).max()
+    assert err <= FAST_BOUND, f"max error {err:.3e}"
+
+
+def test_complex64_io_and_mismatch(gpu, feeder1000):
+    f, net, onet = feeder1000
+    S = W.profile_minute_year(f, steps=200, t0=60000, dtype=np.complex64)
+    V, it, st, mm = tpf.solve_timeseries(net, _dev(S, gpu, torch.complex64), tol=1e-6, max_iter=100, mismatch=True)
+    assert V.dtype == torch.complex64
+    _compare(onet, S.astype(np.complex128), V, it, st, 1e-6, 100, 2e-7)
+    ref_mm = oracle.mismatch(onet, S.astype(np.complex128), V.cpu().numpy().astype(np.complex128))
+    assert np.all(np.abs(mm.cpu().numpy() - ref_mm) <= 1e-12 + 1e-9 * ref_mm)
+
+
+def test_edge_columns(gpu, feeder1000):
+    """Non-finite loads retire NONFINITE after one sweep; zero load converges to w;
+    a warm start from the solution converges in one sweep; a bad V0 column starts flat."""
+    f, net, onet = feeder1000
+    S = W.profile_minute_year(f, steps=6, t0=300)
+    S[1, 17] = np.nan
+    S[2] = 0.0
+    S[3, 500] = np.inf
+    sol = oracle.fpi(onet, S[[0]], 1e-12, 200).V[0]
+    V0 = np.ones_like(S)
+    V0[4] = sol
+    V0[5] = sol
+    S[4] = S[0]
+    S[5] = S[0]
+    V0[5, 3] = 3.0  # modulus outside [0.5, 1.5]: the column starts flat
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-9, max_iter=100, V0=_dev(V0, gpu))
+    st, it = st.cpu().numpy(), it.cpu().numpy()
+    assert list(st) == [0, 2, 0, 2, 0, 0]
+    assert it[1] == 1 and it[3] == 1
+    assert it[4] <= 2 and it[5] == it[0]
+    good = [0, 2, 4, 5]
+    V0g = V0[good].copy()
+    V0g[3] = 1.0
+    _compare(onet, S[good], V[good], torch.from_numpy(it[good]), torch.from_numpy(st[good]), 1e-9, 100, TOL_FP64,
+             V0=V0g)
+
+
+def test_max_iter_zero_and_empty(gpu, feeder1000):
+    f, net, onet = feeder1000
+    S = W.profile_minute_year(f, steps=5)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=0)
+    assert torch.all(V == 1) and int(it.max()) == 0
+    V, it, st = tpf.solve_timeseries(net, _dev(S[:0], gpu), tol=1e-6, max_iter=10)
+    assert V.shape == (0, 999)
+
+
+@pytest.mark.parametrize("mode", ["mixed_bf16", "mixed_fp16"])
+@pytest.mark.parametrize("n_bus,T", [(130, 129), (300, 257), (1000, 300)])
+def test_mixed_every_column(gpu, mode, n_bus, T):
+    f = W.make_feeder(n_bus)
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=T, t0=777)
+    V, it, st, mm = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode=mode, mismatch=True)
+    assert int(st.max()) == tpf.ST_CONVERGED
+    ref = oracle.fpi(onet, S, 1e-10, 200)
+    err = np.abs(V.cpu().numpy() - ref.V).max()
+    assert err <= FAST_BOUND, f"max error {err:.3e}"
+    # the low-precision sweeps must have done part of the work: fewer FP32 sweeps would
+    # not show here, but the sweep count stays within a few of the FP64 count
+    assert int(it.max()) <= int(ref.iters.max()) + 12
+    ymax = np.abs(onet.Ydd).sum(axis=1).max()
+    assert float(mm.max()) <= ymax * 1e-8 + 1e-7 + 1e-7
+
+
+@pytest.mark.parametrize("mode", ["mixed_bf16", "mixed_fp16"])
+def test_mixed_edge_columns(gpu, feeder1000, mode):
+    f, net, onet = feeder1000
+    S = W.profile_minute_year(f, steps=5, t0=1000)
+    S[1, 3] = np.nan
+    S[2] = 0.0
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode=mode)
+    st = st.cpu().numpy()
+    assert list(st) == [0, 2, 0, 0, 0]
+    good = [0, 2, 3, 4]
+    ref = oracle.fpi(onet, S[good], 1e-10, 200)
+    assert np.abs(V.cpu().numpy()[good] - ref.V).max() <= FAST_BOUND
+    V, it, st = tpf.solve_timeseries(net, _dev(S[[0]], gpu), tol=1e-6, max_iter=2, mode=mode)
+    assert int(st[0]) == tpf.ST_MAX_ITER and int(it[0]) == 2
+
+
+@pytest.mark.parametrize("mode,dtype", [("fp64", np.complex128), ("fp32", np.complex64),
+                                        ("mixed_fp16", np.complex64), ("mixed_bf16", np.complex64)])
+def test_1000bus_200k_steps_sampled(gpu, feeder1000, mode, dtype):
+    f, net, onet = feeder1000
+    T = 200_000
+    S = W.profile_minute_year(f, steps=T, dtype=dtype)
+    Sd = _dev(S, gpu, torch.complex128 if dtype == np.complex128 else torch.complex64)
+    V, it, st, mm = tpf.solve_timeseries(net, Sd, tol=1e-6, max_iter=100, mode=mode, mismatch=True)
+    torch.cuda.synchronize()
+    assert int(st.max()) == tpf.ST_CONVERGED
+    rng = np.random.default_rng(5)
+    idx = np.unique(np.concatenate([rng.integers(0, T, 300), [0, T - 1]]))
+    Sh = S[idx].astype(np.complex128)
+    Vg = V[torch.from_numpy(idx).to(gpu)]
+    ig = it[torch.from_numpy(idx).to(gpu)]
+    sg = st[torch.from_numpy(idx).to(gpu)]
+    if mode == "fp64":
+        _compare(onet, Sh, Vg, ig, sg, 1e-6, 100, TOL_FP64 if dtype == np.complex128 else 2e-7)
+    elif dtype == np.complex64:
+        ref = oracle.fpi(onet, Sh, 1e-10, 200)
+        assert np.abs(Vg.cpu().numpy().astype(np.complex128) - ref.V).max() <= FAST_BOUND + 2e-7
+    else:
+        ref = oracle.fpi(onet, Sh, 1e-10, 200)
+        assert np.abs(Vg.cpu().numpy().astype(np.complex128) - ref.V).max() <= FAST_BOUND
+    ymax = np.abs(onet.Ydd).sum(axis=1).max()
+    assert float(mm.max()) < ymax * 1.2e-7 + 2e-7
