@@ -60,6 +60,68 @@ def _traffic_from_profiles(kernel_key: str):
         return None
 
 
+def _pmc_per_kernel(run_dir: str, counter: str):
+    """Median counter value (KiB) per kernel name over the dispatches of one rocprofv3
+    --pmc run, plus the value of the calibration negation kernel."""
+    import csv
+    import glob
+    vals = {}
+    for path in glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row["Counter_Name"] == counter:
+                    vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return {k: float(np.median(v)) for k, v in vals.items()}, {k: len(v) for k, v in vals.items()}
+
+
+def ingest_pmc(fetch_dir: str, write_dir: str):
+    """HBM bytes per launch of the FP64 and mixed sweep kernels from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for the
+    1 GiB negation (2^30 bytes read and 2^30 bytes written)."""
+    fetch, nf = _pmc_per_kernel(fetch_dir, "FETCH_SIZE")
+    write, _ = _pmc_per_kernel(write_dir, "WRITE_SIZE")
+
+    def targs(name, kernel):
+        """Template arguments of a demangled `kernel<...>` name."""
+        i = name.find(kernel + "<")
+        if i < 0:
+            return None
+        return [a.strip() for a in name[i + len(kernel) + 1:name.find(">", i)].split(",")]
+
+    def pick(d, match):
+        names = [k for k in d if match(k)]
+        if not names:
+            return None
+        return max(names, key=lambda k: nf.get(k, 0))
+
+    def neg(k):
+        return "neg" in k
+
+    calib_f, calib_w = pick(fetch, neg), pick(write, neg)
+    if calib_f is None or calib_w is None:
+        raise SystemExit("no calibration negation kernel in the PMC runs (run them with --calib-copy)")
+    cf = 2.0 ** 30 / (fetch[calib_f] * 1024.0)
+    cw = 2.0 ** 30 / (write[calib_w] * 1024.0)
+    out = {"calibration": {"kernel": calib_f, "fetch_kib": fetch[calib_f], "write_kib": write[calib_w],
+                           "fetch_scale": cf, "write_scale": cw}}
+
+    def mixed(mode):  # fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, IO>
+        return lambda k: (targs(k, "fpi_mixed_kernel") or [""] * 4)[3] == mode
+    for key, match in (("fp64/year100", lambda k: "fpi_f64_kernel<" in k),
+                       ("mixed_fp16+warm/year100", mixed("3")),
+                       ("mixed_bf16+warm/year100", mixed("2"))):
+        kf, kw = pick(fetch, match), pick(write, match)
+        if kf is None or kw is None:
+            continue
+        b = fetch[kf] * 1024.0 * cf + write[kw] * 1024.0 * cw
+        out[key] = {"kernel": kf, "fetch_kib": fetch[kf], "write_kib": write[kw], "bytes_per_launch": b,
+                    "source_digest": _kernel_sources_digest(), "dispatches": nf.get(kf, 0)}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def cpu_baseline(net_args, S, tol, max_iter, budget_s=12.0):
     """The CPU oracle (plain FP64 C, OpenMP over columns) on a bounded sample of the
     same workload, extrapolated to power flows per second."""
@@ -87,10 +149,16 @@ def main():
     ap.add_argument("--train-steps", type=int, default=100_000)
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--calib-copy", action="store_true",
-                    help="also run one plain device copy of known size (HBM counter calibration)")
-    ap.add_argument("--kernel-only", action="store_true",
-                    help="time only the sweep kernel launches (for profiling runs)")
+                    help="also run one plain 1 GiB device copy (a negation) for HBM counter calibration")
+    ap.add_argument("--forms", default="",
+                    help="comma-separated subset of forms to time (profiling runs); default: all")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
+                         "--calib-copy into profiles/hbm_traffic.json and exit")
     args = ap.parse_args()
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
@@ -117,9 +185,13 @@ def main():
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        torch.neg(src, out=dst)  # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del src, dst
+    wanted = set(x for x in args.forms.split(",") if x)
+
+    def want(form):
+        return not wanted or form in wanted
 
     stream = torch.cuda.current_stream(dev)
 
@@ -159,14 +231,15 @@ def main():
                 "total_sweeps": int(it.sum())}
 
     forms = {}
-    forms["fp64"] = time_form("fp64")
+    forms["fp64"] = time_form("fp64")  # the reference form is always timed
     for mode in ("fp32", "mixed_bf16", "mixed_fp16"):
-        forms[mode] = time_form(mode)
+        if want(mode):
+            forms[mode] = time_form(mode)
 
     # ---- learned warm start: trained (outside the timed region) on FPI-solved steps of a
     # separately seeded year, then its inference runs inside every timed step
     warm = None
-    if not args.no_warm_start:
+    if not args.no_warm_start and any(want(m + "+warm") for m in ("fp64", "mixed_fp16", "mixed_bf16")):
         t0 = time.perf_counter()
         S_tr = torch.from_numpy(W.profile_minute_year(f, steps=args.train_steps, seed=W.SEED_TRAIN)).to(dev)
         t_tr = torch.arange(args.train_steps, dtype=torch.int64, device=dev)
@@ -194,8 +267,8 @@ def main():
                 "training_s": train_s, "training_data_s": data_s, "predict_ms": pred_ms,
                 "max_start_error_pu": start_err}
         for mode in ("fp64", "mixed_fp16", "mixed_bf16"):
-            r = time_form(mode, V0=V0buf, mlp=(mlp, t_year))
-            forms[mode + "+warm"] = r
+            if want(mode + "+warm"):
+                forms[mode + "+warm"] = time_form(mode, V0=V0buf, mlp=(mlp, t_year))
     Vref = forms["fp64"]["V"]
     for mode, r in forms.items():
         r["max_err_vs_fp64_pu"] = float((r["V"] - Vref).abs().max())
@@ -218,7 +291,8 @@ def main():
     torch.cuda.synchronize()
     mm_ms = float(np.mean([a.elapsed_time(b) for a, b in ev2]))
 
-    cands = [m for m in forms if m.startswith("mixed") and m.endswith("+warm")] or ["mixed_bf16", "mixed_fp16"]
+    cands = ([m for m in forms if m.startswith("mixed") and m.endswith("+warm")]
+             or [m for m in forms if m.startswith("mixed")] or list(forms))
     head = min(cands, key=lambda m: forms[m]["ms_per_step"])
     hf = forms[head]
     base = forms["fp64"]

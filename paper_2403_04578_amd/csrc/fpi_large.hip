@@ -295,12 +295,16 @@ __global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, 
     const int lane = threadIdx.x & 63;
     if (c >= tau) return;
     float sm = 0.f;
-    if (MODE == TPF_MODE_MIXED_FP16)
-        for (int b = lane; b < n; b += 64) {
-            const float sr = fabsf((float)S[2 * (c * n + b)]), si = fabsf((float)S[2 * (c * n + b) + 1]);
-            sm = fmaxf(sm, fmaxf(sr, si));  // non-finite loads retire after one sweep anyway
-        }
-    for (int off = 32; off > 0; off >>= 1) sm = fmaxf(sm, __shfl_xor(sm, off));
+    int sbad = 0;
+    for (int b = lane; b < n; b += 64) {
+        const double sr = fabs((double)S[2 * (c * n + b)]), si = fabs((double)S[2 * (c * n + b) + 1]);
+        sbad |= !(sr + si < HUGE_VAL);
+        sm = fmaxf(sm, (float)fmax(sr, si));
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        sm = fmaxf(sm, __shfl_xor(sm, off));
+        sbad |= __shfl_xor(sbad, off);
+    }
     if (lane == 0) {
         int sB = 0;
         if (MODE == TPF_MODE_MIXED_FP16) {
@@ -313,6 +317,9 @@ __global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, 
         m.dprev = m.sumd = m.uref = 0.f;
         m.ks = ldexpf(1.0f, sB);
         m.inv = ldexpf(1.0f, -(sB + (MODE == TPF_MODE_MIXED_FP16 ? sZ : 0)));
+        // the FP16 saturation would clip a non-finite load; the unscale carries it into
+        // the iterate instead, so the column ends NONFINITE
+        if (sbad) m.inv = __builtin_nanf("");
         ms[c] = m;
         umax[c] = 0u;
     }

@@ -260,7 +260,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
             const long long cc = (long long)base + 16 * c + j;
             col[c] = cc < tau ? cc : -1;
             float sm = 0.0f;
-            int bad = 0;
+            int bad = 0, sbad = 0;
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
                 double s[4] = {0, 0, 0, 0}, v[4] = {1, 0, 1, 0};
@@ -279,6 +279,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                     }
                 }
                 const f4 sv = f4{(float)s[0], (float)s[1], (float)s[2], (float)s[3]};
+                sbad |= !(fabs(s[0]) + fabs(s[1]) + fabs(s[2]) + fabs(s[3]) < HUGE_VAL);
                 Sx[(c * TPW + q) * NT + tid] = sv;
                 sm = fmaxf(sm, amax4(sv));
                 U[c][q] = f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]} - Wq[q];
@@ -287,15 +288,17 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
             sm = fmaxf(sm, __shfl_xor(sm, 32));
             bad |= __shfl_xor(bad, 16);
             bad |= __shfl_xor(bad, 32);
+            sbad |= __shfl_xor(sbad, 16);
+            sbad |= __shfl_xor(sbad, 32);
             if (g == 0) {
                 atomicMax(reinterpret_cast<int *>(rsm) + 16 * c + j, __float_as_int(sm));  // sm >= 0: int order
-                if (bad) atomicOr(rok + 16 * c + j, 1);
+                if (bad | sbad) atomicOr(rok + 16 * c + j, bad | (sbad << 1));
             }
         }
         __syncthreads();
 #pragma unroll
         for (int c = 0; c < CG; ++c) {
-            if (V0 && rok[16 * c + j]) {  // guard failed somewhere in the column: flat start
+            if (V0 && (rok[16 * c + j] & 1)) {  // guard failed somewhere in the column: flat start
 #pragma unroll
                 for (int q = 0; q < TPW; ++q) U[c][q] = f4{1, 0, 1, 0} - Wq[q];
             }
@@ -308,6 +311,9 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
             }
             ks[c] = ldexpf(1.0f, sB);
             inv[c] = ldexpf(1.0f, -(sB + (kScaled ? sZ : 0)));
+            // A non-finite load would be clipped by the FP16 saturation; the product's
+            // unscale carries it into the iterate instead, so the column ends NONFINITE.
+            if (rok[16 * c + j] & 2) inv[c] = __builtin_nanf("");
             dif[c] = false;
             if (wave == 0 && g == 0) {
                 ColState st;
