@@ -515,7 +515,7 @@ __global__ void finish_mixed_kernel(const long long *__restrict__ actR, const lo
         m.sumd = 0.f;
     } else if (m.ph == 0) {
         m.uref = fmaxf(m.uref, um);
-        if (!m.want && (d < theta * m.uref || (m.it >= 2 && d > 0.5f * m.dprev))) m.want = 1;
+        if (!m.want && (d <= theta * m.uref || (m.it >= 2 && d > 0.5f * m.dprev))) m.want = 1;
     } else {
         conv = d * margin < tol;
         m.sumd += d;

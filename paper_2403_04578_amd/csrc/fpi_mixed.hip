@@ -127,7 +127,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const float *__restrict__ A32,
     const uint16_t *__restrict__ Alow, const uint16_t *__restrict__ Alo, const double *__restrict__ wv, int n,
     int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue,
-    const MismatchArgs mm) {
+    const MismatchArgs mm_in) {
     using L = LowOps<MODE>;
     typedef typename L::frag frag;
     typedef typename L::quad quad;
@@ -152,6 +152,8 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     ColState *cs = reinterpret_cast<ColState *>(rok + NC);                            // [2][NC]
     unsigned long long *qb = reinterpret_cast<unsigned long long *>(cs + 2 * NC);
     double *pmm = reinterpret_cast<double *>(qb + 2);                                 // [NW][NC]
+    double *wl = pmm + NW * NC;                                                       // [2][8 MT] w
+    void *mml = wl + 16 * MT;                                                         // staged CSR
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -164,6 +166,8 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     for (int e = tid; e < (kMixed ? NC * KPL * (kSplit ? 2 : 1) : 0); e += NT) Bh[e] = 0;
     for (int e = tid; e < 4 * NC; e += NT) rmax[e] = 0.0f;
     for (int e = tid; e < 2 * NC; e += NT) rbad[e] = 0;
+    for (int e = tid; e < 16 * MT; e += NT) wl[e] = wv[e];
+    const MismatchArgs mm = mm_in.out && mm_in.staged ? stage_mismatch(mm_in, n, mml, tid, NT) : mm_in;
 
     frag Af[TPW][KTL], Ag[kSplit ? TPW : 1][kSplit ? KTL : 1];
     f4 Wq[TPW];  // w of the lane's two buses per tile, FP32, (Re, Im, Re, Im)
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                     }
                 } else if (st.ph == 0) {
                     nx.uref = fmaxf(st.uref, um);
-                    if (!st.want && (d < theta_k * nx.uref || (nx.it >= 2 && d > 0.5f * st.dprev))) nx.want = 1;
+                    if (!st.want && (d <= theta_k * nx.uref || (nx.it >= 2 && d > 0.5f * st.dprev))) nx.want = 1;
                 } else {
                     conv = d * margin < tol;
                     nx.sumd = st.sumd + d;
@@ -511,8 +515,8 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                             const int b = b0 + h;
                             if (b < n) {
                                 IO *o = Vout + 2 * (rcol[c] * n + b);
-                                o[0] = (IO)(wv[b] + (double)U[c][q][2 * h]);
-                                o[1] = (IO)(wv[8 * MT + b] + (double)U[c][q][2 * h + 1]);
+                                o[0] = (IO)(wl[b] + (double)U[c][q][2 * h]);
+                                o[1] = (IO)(wl[8 * MT + b] + (double)U[c][q][2 * h + 1]);
                             }
                         }
                         Sx[(c * TPW + q) * NT + tid] = f4{0, 0, 0, 0};  // idle slot: zero injection
@@ -541,7 +545,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                 for (int c = 0; c < CG; ++c) {
                     double worst = 0.0;
                     if (rcol[c] >= 0)
-                        worst = retired_mismatch<IO>(mm, S, wv, B32 + (16 * c + j) * KP32, rcol[c], n, MT, tw, NW,
+                        worst = retired_mismatch<IO>(mm, S, wl, B32 + (16 * c + j) * KP32, rcol[c], n, MT, tw, NW,
                                                      nv, g);
                     worst = nanmax_d(worst, __shfl_xor(worst, 16));
                     worst = nanmax_d(worst, __shfl_xor(worst, 32));
@@ -583,7 +587,8 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     const size_t NC = 16 * CG, NT = NW * 64;
     const size_t KPL = 32 * KTL + 8, KP32 = 16 * MT + 4;
     const size_t lds = NC * KP32 * 4 + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) + (size_t)CG * TPW * NT * 16 +
-                       NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 16 + (size_t)NW * NC * 8 + 64;
+                       NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 16 + (size_t)NW * NC * 8 + 64 +
+                       (size_t)16 * MT * 8 + (mm.out ? mm.staged : 0);
     auto kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, IO>;
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
@@ -617,7 +622,8 @@ static int dispatch(const tpf_network_s &net, const DeviceNet &dn, const void *S
 int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype, int64_t tau,
                      double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
                      unsigned long long *queue, double *mismatch_out, hipStream_t stream) {
-    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, mismatch_out};
+    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, mismatch_out, dn.nnz,
+                          mismatch_lds_bytes(net.n, dn.nnz, 32 * 1024)};
     if (!dn.A32) return fail(TPF_ERR_UNSUPPORTED, "FP32/mixed sweep kernels support up to 128 PQ buses");
 #define TPF_MODE_CASE(M)                                                                                      \
     if (mode == M) {                                                                                         \

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const double *__restrict__ A,
     const double *__restrict__ wv, int n, int MT, long long tau, double tol, int max_iter,
-    unsigned long long *__restrict__ queue, const MismatchArgs mm) {
+    unsigned long long *__restrict__ queue, const MismatchArgs mm_in) {
     extern __shared__ double lds[];
     double *Ib = lds;                                 // [16*MT][16]
     double *part = lds + 256 * MT;                    // [NW][16] partial max |dV|^2
@@ -189,6 +189,8 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
     };
 
     for (int e = threadIdx.x; e < 16 * MT; e += NW * 64) wl[e] = wv[e];
+    const MismatchArgs mm =
+        mm_in.out && mm_in.staged ? stage_mismatch(mm_in, n, wl + 16 * MT, threadIdx.x, NW * 64) : mm_in;
     // Initial fill: 16 consecutive queue entries per workgroup.
     if (threadIdx.x == 0) *qb = atomicAdd(queue, 16ull);
     __syncthreads();
@@ -375,7 +377,7 @@ static int launch_rows(const tpf_network_s &net, const DeviceNet &dn, const void
                        unsigned long long *queue, const MismatchArgs &mm, hipStream_t stream) {
     const int MT = dn.MT;
     const size_t lds = (size_t)256 * MT * sizeof(double) + (size_t)NW * 16 * (sizeof(double) + sizeof(int)) + 16 +
-                       (size_t)16 * MT * sizeof(double);
+                       (size_t)16 * MT * sizeof(double) + (mm.out ? mm.staged : 0);
     if (hipFuncSetAttribute((const void *)fpi_f64_kernel<TPW, NW, IO>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
@@ -405,7 +407,8 @@ static int dispatch_rows(const tpf_network_s &net, const DeviceNet &dn, const vo
 int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype, int64_t tau,
                          double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
                          unsigned long long *queue, double *mismatch_out, hipStream_t stream) {
-    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, mismatch_out};
+    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, mismatch_out, dn.nnz,
+                          mismatch_lds_bytes(net.n, dn.nnz, 48 * 1024)};
     if (dtype == TPF_C128)
         return dispatch_rows<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream);
     return dispatch_rows<float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream);

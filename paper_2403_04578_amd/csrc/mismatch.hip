@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void mismatch_f64_kernel(const IO *__restrict_
         const IO *vc = V + 2 * c * n;
         const IO *sc = S + 2 * c * n;
         double worst = 0.0;
-        const MismatchArgs mm{rowptr, colidx, yv, cv, out};
+        const MismatchArgs mm{rowptr, colidx, yv, cv, out, 0, 0};
         for (int i = lane; i < n; i += 64) {
             worst = nanmax(worst, bus_mismatch(mm, i, (double)sc[2 * i], (double)sc[2 * i + 1], (double)vc[2 * i],
                                                (double)vc[2 * i + 1], [&](int k, double &xr, double &xi) {

@@ -209,6 +209,144 @@ __global__ void sync_kernel(const float *__restrict__ p, int64_t woff, int in, i
     }
 }
 
+// ---- fused inference (every padded layer width <= 256)
+//
+// One workgroup of 4 waves carries a 64-row tile from the loads to the start voltages:
+// features into LDS, every layer as BF16 MFMA products whose activations stay in LDS
+// ([64][264] BF16, two buffers), and the voltage write.  Wave w owns output neurons
+// 64 w .. 64 w + 63 (4 x 4 tiles of 16x16x32) and reads its weight fragments straight
+// from global memory, one k-step ahead; the 0.47 MB of BF16 weights stay in L2.  The
+// output layer goes to LDS as FP32 so that the voltages leave as contiguous complex
+// stores.  Nothing but S and V0 touches HBM.
+constexpr int kFusedWidth = 256, kFusedRows = 64, kHStride = 264, kYStride = 257;
+constexpr size_t kFusedLds = (size_t)2 * kFusedRows * kHStride * 2;  // >= 64 x 257 FP32 (aliased)
+
+struct MlpView {
+    const __bf16 *W[17];  // [out_p][in_p] per layer
+    const float *b[17];   // padded bias per layer
+    int dp[18];           // padded widths
+    int L, n;
+};
+
+// GELU with erf from Abramowitz and Stegun 7.1.26 (|error| < 1.5e-7, below the BF16
+// rounding of the activation it produces).
+__device__ __forceinline__ float gelu_as(float z) {
+    const float x = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+    const float p =
+        t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+    const float e = 1.0f - p * __expf(-x * x);
+    return 0.5f * z * (1.0f + copysignf(e, z));
+}
+
+template <typename IO>
+__global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict__ S,
+                                                            const int64_t *__restrict__ t_index, int64_t rows,
+                                                            const MlpView mv, double vs_re, double vs_im,
+                                                            IO *__restrict__ V0) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    __bf16 *H0 = reinterpret_cast<__bf16 *>(smem);
+    __bf16 *H1 = H0 + kFusedRows * kHStride;
+    float *Yf = reinterpret_cast<float *>(smem);  // [64][257], written once H0/H1 are consumed
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int g = lane >> 4, j = lane & 15;
+    const int n = mv.n, dp0 = mv.dp[0];
+    const int64_t r0 = (int64_t)blockIdx.x * kFusedRows;
+    // features: 50 P, 50 Q, then the calendar phases; zero padding and zero rows past the end
+    for (int e = tid; e < kFusedRows * n; e += 256) {
+        const int r = e / n, b = e - r * n;
+        float pr = 0.0f, pi = 0.0f;
+        if (r0 + r < rows) {
+            pr = kFeatScale * (float)S[2 * ((r0 + r) * n + b)];
+            pi = kFeatScale * (float)S[2 * ((r0 + r) * n + b) + 1];
+        }
+        H0[r * kHStride + b] = (__bf16)pr;
+        H0[r * kHStride + n + b] = (__bf16)pi;
+    }
+    const int tail = dp0 - 2 * n;
+    for (int e = tid; e < kFusedRows * tail; e += 256) {
+        const int r = e / tail, f = 2 * n + (e - r * tail);
+        float v = 0.0f;
+        if (r0 + r < rows && f < 2 * n + 4) {
+            const int64_t t = t_index[r0 + r];
+            const double mod = (double)(t % 1440) / 1440.0;
+            const double day = (double)((t / 1440) % 365) / 365.0;
+            const double ang = 2.0 * M_PI * (f < 2 * n + 2 ? mod : day);
+            v = (float)(((f - 2 * n) & 1) ? cos(ang) : sin(ang));
+        }
+        H0[r * kHStride + f] = (__bf16)v;
+    }
+    __syncthreads();
+    __bf16 *hin = H0, *hout = H1;
+    for (int l = 0; l <= mv.L; ++l) {
+        const int K = mv.dp[l], N = mv.dp[l + 1];
+        const int n0 = 64 * wave;
+        const bool mine = n0 < N;
+        const bool last = l == mv.L;
+        f4 acc[4][4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+        if (mine) {
+            const __bf16 *Wl = mv.W[l] + (int64_t)(n0 + j) * K + 8 * g;
+            b8 bf[4], bn[4];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) bf[b] = *reinterpret_cast<const b8 *>(Wl + (int64_t)16 * b * K);
+            for (int k0 = 0; k0 < K; k0 += 32) {
+                if (k0 + 32 < K) {
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) bn[b] = *reinterpret_cast<const b8 *>(Wl + (int64_t)16 * b * K + k0 + 32);
+                }
+                b8 af[4];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+                    af[a] = *reinterpret_cast<const b8 *>(hin + (16 * a + j) * kHStride + k0 + 8 * g);
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bf[b] = bn[b];
+            }
+        }
+        if (last) __syncthreads();  // every wave is done with hin: the FP32 staging overwrites it
+        if (mine) {
+            const float *bias = mv.b[l];
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int col = n0 + 16 * b + j;
+                const float bc = bias[col];
+#pragma unroll
+                for (int a = 0; a < 4; ++a)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = 16 * a + 4 * g + r;
+                        const float v = acc[a][b][r] + bc;
+                        if (last)
+                            Yf[row * kYStride + col] = v;
+                        else
+                            hout[row * kHStride + col] = (__bf16)gelu_as(v);  // padding: W, b = 0 -> 0
+                    }
+            }
+        }
+        __syncthreads();
+        __bf16 *tmp = hin;
+        hin = hout;
+        hout = tmp;
+    }
+    for (int e = tid; e < kFusedRows * n; e += 256) {
+        const int r = e / n, b = e - r * n;
+        if (r0 + r < rows) {
+            IO *o = V0 + 2 * ((r0 + r) * n + b);
+            o[0] = (IO)(vs_re + (double)Yf[r * kYStride + b] / kOutScale);
+            o[1] = (IO)(vs_im + (double)Yf[r * kYStride + n + b] / kOutScale);
+        }
+    }
+}
+
 template <typename IO>
 __global__ void predict_out_kernel(const float *__restrict__ Y, int64_t ldy, int n, int64_t rows, double vs_re,
                                    double vs_im, IO *__restrict__ V0) {
@@ -545,6 +683,33 @@ extern "C" int tpf_mlp_predict(tpf_mlp M, const void *S, int32_t dtype, const in
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     int Dmax = 0;
     for (int w : M->dp) Dmax = std::max(Dmax, w);
+    if (Dmax <= kFusedWidth && 2 * M->n + 4 <= M->dp[0]) {
+        MlpView mv{};
+        for (int l = 0; l <= M->layers; ++l) {
+            mv.W[l] = M->Wt[l];
+            mv.b[l] = M->bias[l];
+        }
+        for (int l = 0; l < M->layers + 2; ++l) mv.dp[l] = M->dp[l];
+        mv.L = M->layers;
+        mv.n = M->n;
+        const unsigned blocks = (unsigned)((rows + kFusedRows - 1) / kFusedRows);
+        if (dtype == TPF_C128) {
+            auto k = predict_fused_kernel<double>;
+            if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds) !=
+                hipSuccess)
+                return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), kFusedLds, st, (const double *)S, t_index, rows, mv,
+                               M->vs_re, M->vs_im, (double *)V0_out);
+        } else {
+            auto k = predict_fused_kernel<float>;
+            if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds) !=
+                hipSuccess)
+                return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), kFusedLds, st, (const float *)S, t_index, rows, mv,
+                               M->vs_re, M->vs_im, (float *)V0_out);
+        }
+        return last_launch("MLP fused predict");
+    }
     if (dtype == TPF_C128) {
         rc = forward(*M, (const double *)S, t_index, rows, ws, st);
         if (rc == TPF_OK)

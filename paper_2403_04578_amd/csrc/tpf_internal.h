@@ -55,6 +55,7 @@ struct DeviceNet {
     uint16_t *ALbf = nullptr, *ALh = nullptr;
     double *wl = nullptr;
     // Sparse Y_dd (CSR) and c = Y_ds v_s for the FP64 mismatch.
+    int nnz = 0;                 // entries of the CSR below
     int32_t *rowptr = nullptr;   // [n+1]
     int32_t *colidx = nullptr;   // [nnz]
     double *yval = nullptr;      // [nnz][2]
@@ -70,7 +71,36 @@ struct MismatchArgs {
     const double *yval;  // [nnz][2]
     const double *cval;  // [n][2]
     double *out;         // [tau]
+    int nnz = 0;
+    int staged = 0;      // bytes of LDS the sweep kernel reserves for a copy of the CSR (0: none)
 };
+
+// LDS bytes of a copy of the mismatch CSR (yval, cval, then rowptr, colidx), or 0 when it
+// exceeds `cap` (dense rows of a meshed network) and the kernel reads global memory.
+inline int mismatch_lds_bytes(int n, int nnz, int cap) {
+    const long long b = ((16LL * nnz + 16LL * n + 4LL * (n + 1) + 4LL * nnz) + 15) / 16 * 16;
+    return b <= cap ? (int)b : 0;
+}
+
+// Copies the CSR into `lds` (all threads of the block take part; the caller synchronises
+// before use) and returns arguments that point there.  The retiring columns' mismatch
+// then walks the sparse rows at LDS latency instead of chains of global loads.
+__device__ inline MismatchArgs stage_mismatch(const MismatchArgs &mm, int n, void *lds, int tid, int nthr) {
+    double *yv = static_cast<double *>(lds);
+    double *cv = yv + 2 * mm.nnz;
+    int32_t *rp = reinterpret_cast<int32_t *>(cv + 2 * n);
+    int32_t *ci = rp + n + 1;
+    for (int i = tid; i < 2 * mm.nnz; i += nthr) yv[i] = mm.yval[i];
+    for (int i = tid; i < 2 * n; i += nthr) cv[i] = mm.cval[i];
+    for (int i = tid; i <= n; i += nthr) rp[i] = mm.rowptr[i];
+    for (int i = tid; i < mm.nnz; i += nthr) ci[i] = mm.colidx[i];
+    MismatchArgs r = mm;
+    r.rowptr = rp;
+    r.colidx = ci;
+    r.yval = yv;
+    r.cval = cv;
+    return r;
+}
 
 __device__ __forceinline__ double nanmax_d(double a, double b) { return (a > b || a != a) ? a : b; }
 
