@@ -122,6 +122,36 @@ def ingest_pmc(fetch_dir: str, write_dir: str):
     print(json.dumps(out, indent=1))
 
 
+def summarize_trace(trace_dir: str, out_txt: str, command: str):
+    """Per-kernel call counts and durations from rocprofv3 --kernel-trace --stats CSV output,
+    with the sweep kernels' individual launches listed in order (the timed steps and the
+    kernel-only timings of each form)."""
+    import csv
+    import glob
+    stats = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    trace = glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True)
+    if not stats or not trace:
+        raise SystemExit(f"no rocprofv3 kernel stats/trace under {trace_dir}")
+    lines = [f"# rocprofv3 kernel summary", f"command: {command}", "",
+             f"{'kernel':70s} {'calls':>7s} {'avg_us':>10s} {'total_ms':>10s} {'pct':>6s}"]
+    for r in list(csv.DictReader(open(stats[0])))[:20]:
+        lines.append(f"{r['Name'][:70]:70s} {int(r['Calls']):7d} {float(r['AverageNs']) / 1e3:10.1f} "
+                     f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.1f}")
+    rows = sorted(csv.DictReader(open(trace[0])), key=lambda r: int(r["Start_Timestamp"]))
+    lines += ["", "launches of the year-long sweep, inference and mismatch kernels, in order (us):"]
+    for key in ("fpi_f64_kernel", "fpi_mixed_kernel", "predict_fused_kernel", "mismatch_tile_kernel"):
+        by = {}
+        for r in rows:
+            if key in r["Kernel_Name"]:
+                name = r["Kernel_Name"].split("(")[0].replace("void ", "")
+                by.setdefault(name, []).append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+        for name, d in by.items():
+            lines.append(f"  {name}: " + " ".join(f"{x:.0f}" for x in d))
+    with open(out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def cpu_baseline(net_args, S, tol, max_iter, budget_s=12.0):
     """The CPU oracle (plain FP64 C, OpenMP over columns) on a bounded sample of the
     same workload, extrapolated to power flows per second."""
@@ -155,9 +185,14 @@ def main():
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
                          "--calib-copy into profiles/hbm_traffic.json and exit")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT_TXT", "COMMAND"),
+                    help="write a short text summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
     if args.ingest_pmc:
         ingest_pmc(*args.ingest_pmc)
+        return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",

@@ -51,7 +51,6 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
     DeviceNet *dn = nullptr;
     int rc = device_net(net, &dn);
     if (rc != TPF_OK) return rc;
-    bool fused_mismatch = false;  // the sweep kernel computed the mismatch at retirement
     if (max_iter == 0) {
         rc = launch_start_only(n, V0, dtype, T, V_out, iters_out, status_out, st);
     } else if (uses_large_path(n, mode)) {
@@ -63,13 +62,11 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
         if (rc == TPF_OK) rc = check_launch("queue reset");
         if (rc == TPF_OK && mode == TPF_MODE_FP64) {
             rc = launch_fpi_small_f64(*net, *dn, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out,
-                                      queue, opts ? opts->mismatch_out : nullptr, st);
-            fused_mismatch = true;
+                                      queue, st);
         }
         else if (rc == TPF_OK) {
             rc = launch_fpi_mixed(*net, *dn, mode, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out,
-                                  queue, opts ? opts->mismatch_out : nullptr, st);
-            fused_mismatch = true;
+                                  queue, st);
         }
     } else {
         return fail(TPF_ERR_UNSUPPORTED, "no sweep path for this network size and mode");
@@ -77,7 +74,7 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
     if (rc != TPF_OK) return rc;
     rc = check_launch("sweep kernel launch");
     if (rc != TPF_OK) return rc;
-    if (opts && opts->mismatch_out && !fused_mismatch) {
+    if (opts && opts->mismatch_out) {  // FP64 check of the returned voltages, as its own pass
         rc = launch_mismatch_f64(*net, *dn, S, V_out, dtype, T, opts->mismatch_out, st);
         if (rc == TPF_OK) rc = check_launch("mismatch kernel launch");
     }

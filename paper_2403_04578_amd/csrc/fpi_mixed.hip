@@ -88,31 +88,6 @@ __device__ __forceinline__ float amax4(const f4 &x) {
     return fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3])));
 }
 
-// Largest |mismatch| over the lane's buses of a retiring column whose drops U sit in
-// LDS row `uc` (FP32-family order).
-template <typename IO>
-__device__ __forceinline__ double retired_mismatch(const MismatchArgs mm, const IO *__restrict__ S,
-                                                const double *__restrict__ wv, const float *uc, long long col, int n,
-                                                int MT, int tw, int NW, int nv, int g) {
-    auto vk = [&](int k, double &xr, double &xi) {
-        const int r = 16 * (k >> 3) + 2 * (k & 7);
-        xr = (double)(IO)(wv[k] + (double)uc[r]);
-        xi = (double)(IO)(wv[8 * MT + k] + (double)uc[r + 1]);
-    };
-    double worst = 0.0;
-    for (int q = 0; q < nv; ++q)
-        for (int h = 0; h < 2; ++h) {
-            const int b = 8 * (tw + NW * q) + 2 * g + h;
-            if (b < n) {
-                double sr, si, vr, vi;
-                ldc(S + 2 * (col * n + b), sr, si);
-                vk(b, vr, vi);
-                worst = nanmax_d(worst, bus_mismatch(mm, b, sr, si, vr, vi, vk));
-            }
-        }
-    return worst;
-}
-
 // Per-column state of a batch, double-buffered in LDS by sweep parity.  Every
 // wave evaluates the same update for the columns of its lanes; wave 0 stores it.
 struct ColState {
@@ -126,8 +101,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const float *__restrict__ A32,
     const uint16_t *__restrict__ Alow, const uint16_t *__restrict__ Alo, const double *__restrict__ wv, int n,
-    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue,
-    const MismatchArgs mm_in) {
+    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue) {
     using L = LowOps<MODE>;
     typedef typename L::frag frag;
     typedef typename L::quad quad;
@@ -151,9 +125,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     int *rok = reinterpret_cast<int *>(rsm + NC);                                     // [NC] guard
     ColState *cs = reinterpret_cast<ColState *>(rok + NC);                            // [2][NC]
     unsigned long long *qb = reinterpret_cast<unsigned long long *>(cs + 2 * NC);
-    double *pmm = reinterpret_cast<double *>(qb + 2);                                 // [NW][NC]
-    double *wl = pmm + NW * NC;                                                       // [2][8 MT] w
-    void *mml = wl + 16 * MT;                                                         // staged CSR
+    double *wl = reinterpret_cast<double *>(qb + 2);                                  // [2][8 MT] w
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -167,7 +139,6 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     for (int e = tid; e < 4 * NC; e += NT) rmax[e] = 0.0f;
     for (int e = tid; e < 2 * NC; e += NT) rbad[e] = 0;
     for (int e = tid; e < 16 * MT; e += NT) wl[e] = wv[e];
-    const MismatchArgs mm = mm_in.out && mm_in.staged ? stage_mismatch(mm_in, n, mml, tid, NT) : mm_in;
 
     frag Af[TPW][KTL], Ag[kSplit ? TPW : 1][kSplit ? KTL : 1];
     f4 Wq[TPW];  // w of the lane's two buses per tile, FP32, (Re, Im, Re, Im)
@@ -324,10 +295,13 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                 st.col = col[c];
                 st.dprev = st.sumd = st.uref = 0.f;
                 st.it = st.ph = st.want = st.wait = 0;
+                // A warm start that passed the guard is already near the FP16 floor: the
+                // column skips the full FP16 sweeps and begins with the accurate one.
+                if (kMixed && V0 && !(rok[16 * c + j] & 1)) st.want = 1;
                 cs[par * NC + 16 * c + j] = st;
             }
         }
-        precise = !kMixed;
+        precise = !kMixed || V0 != nullptr;
         prepare_b();
         return true;
     };
@@ -525,45 +499,6 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
             }
             dif[c] = !precise && ph_next[c] == 1;
         }
-        if (mm.out) {
-            bool any = false;
-#pragma unroll
-            for (int c = 0; c < CG; ++c) any |= rcol[c] >= 0;
-            if (__ballot(any)) {  // workgroup-uniform
-                // Eq. (1) power balance of the retiring columns from the returned voltages.
-                // Their drops go to the (free) FP32 B buffer for the neighbour lookups.
-#pragma unroll
-                for (int c = 0; c < CG; ++c)
-                    if (rcol[c] >= 0)
-#pragma unroll
-                        for (int q = 0; q < TPW; ++q)
-                            if (q < nv)
-                                *reinterpret_cast<f4 *>(B32 + (16 * c + j) * KP32 + 16 * (tw + NW * q) + 4 * g) =
-                                    U[c][q];
-                __syncthreads();
-#pragma unroll
-                for (int c = 0; c < CG; ++c) {
-                    double worst = 0.0;
-                    if (rcol[c] >= 0)
-                        worst = retired_mismatch<IO>(mm, S, wl, B32 + (16 * c + j) * KP32, rcol[c], n, MT, tw, NW,
-                                                     nv, g);
-                    worst = nanmax_d(worst, __shfl_xor(worst, 16));
-                    worst = nanmax_d(worst, __shfl_xor(worst, 32));
-                    if (g == 0) pmm[wave * NC + 16 * c + j] = worst;
-                }
-                __syncthreads();
-                if (wave == 0 && g == 0) {
-#pragma unroll
-                    for (int c = 0; c < CG; ++c)
-                        if (rcol[c] >= 0) {
-                            double m = 0.0;
-                            for (int w = 0; w < NW; ++w) m = nanmax_d(m, pmm[w * NC + 16 * c + j]);
-                            mm.out[rcol[c]] = m;
-                        }
-                }
-                __syncthreads();  // B32 is rewritten by the next operand preparation
-            }
-        }
         par ^= 1;
         if (!active) {
             __syncthreads();
@@ -579,7 +514,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
 template <int TPW, int NW, int KTL, int MODE, typename IO>
 static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
                       int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                      unsigned long long *queue, const MismatchArgs &mm, hipStream_t stream) {
+                      unsigned long long *queue, hipStream_t stream) {
     // column groups per workgroup: as many as the registers hold without spilling
     constexpr int CG = (MODE == TPF_MODE_FP32 || TPW == 1) ? 4 : TPF_MIXED_CG;
     const int MT = dn.MT;
@@ -587,8 +522,7 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     const size_t NC = 16 * CG, NT = NW * 64;
     const size_t KPL = 32 * KTL + 8, KP32 = 16 * MT + 4;
     const size_t lds = NC * KP32 * 4 + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) + (size_t)CG * TPW * NT * 16 +
-                       NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 16 + (size_t)NW * NC * 8 + 64 +
-                       (size_t)16 * MT * 8 + (mm.out ? mm.staged : 0);
+                       NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 16 + 64 + (size_t)16 * MT * 8;
     auto kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, IO>;
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
@@ -601,18 +535,17 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     const long long blocks = std::min<long long>((long long)cus * per_cu, (tau + (long long)NC - 1) / (long long)NC);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.A32, MODE == TPF_MODE_MIXED_BF16 ? dn.Abf : dn.Ah, dn.Al,
-                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue, mm);
+                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue);
     return TPF_OK;
 }
 
 template <int MODE, typename IO>
 static int dispatch(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
                     int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                    unsigned long long *queue, const MismatchArgs &mm, hipStream_t stream) {
+                    unsigned long long *queue, hipStream_t stream) {
 #define TPF_GO(T, W, K)                                                                                      \
     if (dn.TPW == T && dn.NW == W && dn.KTL == K)                                                            \
-        return launch_one<T, W, K, MODE, IO>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm,   \
-                                             stream);
+        return launch_one<T, W, K, MODE, IO>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);
     TPF_GO(1, 4, 1) TPF_GO(1, 4, 2) TPF_GO(1, 8, 3) TPF_GO(1, 8, 4)
     TPF_GO(2, 8, 5) TPF_GO(2, 8, 6) TPF_GO(2, 8, 7) TPF_GO(2, 8, 8)
 #undef TPF_GO
@@ -621,15 +554,13 @@ static int dispatch(const tpf_network_s &net, const DeviceNet &dn, const void *S
 
 int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype, int64_t tau,
                      double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                     unsigned long long *queue, double *mismatch_out, hipStream_t stream) {
-    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, mismatch_out, dn.nnz,
-                          mismatch_lds_bytes(net.n, dn.nnz, 32 * 1024)};
+                     unsigned long long *queue, hipStream_t stream) {
     if (!dn.A32) return fail(TPF_ERR_UNSUPPORTED, "FP32/mixed sweep kernels support up to 128 PQ buses");
 #define TPF_MODE_CASE(M)                                                                                      \
     if (mode == M) {                                                                                         \
         if (dtype == TPF_C128)                                                                               \
-            return dispatch<M, double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream); \
-        return dispatch<M, float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream);      \
+            return dispatch<M, double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream); \
+        return dispatch<M, float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);      \
     }
     TPF_MODE_CASE(TPF_MODE_FP32)
     TPF_MODE_CASE(TPF_MODE_MIXED_BF16)

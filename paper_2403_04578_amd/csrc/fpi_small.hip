@@ -118,7 +118,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const double *__restrict__ A,
     const double *__restrict__ wv, int n, int MT, long long tau, double tol, int max_iter,
-    unsigned long long *__restrict__ queue, const MismatchArgs mm_in) {
+    unsigned long long *__restrict__ queue) {
     extern __shared__ double lds[];
     double *Ib = lds;                                 // [16*MT][16]
     double *part = lds + 256 * MT;                    // [NW][16] partial max |dV|^2
@@ -189,8 +189,6 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
     };
 
     for (int e = threadIdx.x; e < 16 * MT; e += NW * 64) wl[e] = wv[e];
-    const MismatchArgs mm =
-        mm_in.out && mm_in.staged ? stage_mismatch(mm_in, n, wl + 16 * MT, threadIdx.x, NW * 64) : mm_in;
     // Initial fill: 16 consecutive queue entries per workgroup.
     if (threadIdx.x == 0) *qb = atomicAdd(queue, 16ull);
     __syncthreads();
@@ -273,51 +271,6 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
                     status_out[col] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
                 }
             }
-            if (mm.out) {
-                // Eq. (1) power balance of the retiring columns, from the returned voltages
-                // (rounded to the output type).  Their LDS injection column is free: it holds
-                // V for the neighbour lookups of the sparse row of Y_dd.
-                if (done) {
-#pragma unroll
-                    for (int q = 0; q < TPW; ++q)
-                        if (q < nv)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h) {
-                                const int t = tw + NW * q;
-                                Ib[256 * t + 64 * h + lane] = (double)(IO)st.v[q][h];
-                                Ib[256 * t + 64 * (h + 2) + lane] = (double)(IO)st.v[q][h + 2];
-                            }
-                }
-                __syncthreads();
-                double worst = 0.0;
-                if (done) {
-#pragma unroll
-                    for (int q = 0; q < TPW; ++q)
-                        if (q < nv)
-#pragma unroll
-                            for (int h = 0; h < 2; ++h) {
-                                const int b = 8 * (tw + NW * q) + g + 4 * h;
-                                if (b < n) {
-                                    const double vr = (double)(IO)st.v[q][h], vi = (double)(IO)st.v[q][h + 2];
-                                    worst = nanmax_d(worst, bus_mismatch(mm, b, st.s[q][h], st.s[q][h + 2], vr, vi,
-                                                                         [&](int k, double &xr, double &xi) {
-                                                                             const int r = 16 * (k >> 3) + (k & 7);
-                                                                             xr = Ib[r * 16 + j];
-                                                                             xi = Ib[(r + 8) * 16 + j];
-                                                                         }));
-                                }
-                            }
-                }
-                worst = nanmax_d(worst, __shfl_xor(worst, 16));
-                worst = nanmax_d(worst, __shfl_xor(worst, 32));
-                if (g == 0) part[wave * 16 + j] = worst;
-                __syncthreads();
-                if (done && wave == 0 && g == 0) {
-                    double m = 0.0;
-                    for (int w = 0; w < NW; ++w) m = nanmax_d(m, part[w * 16 + j]);
-                    mm.out[col] = m;
-                }
-            }
             const int cnt = __popcll(dm);
             if (threadIdx.x == 0) *qb = exhausted ? (unsigned long long)tau : atomicAdd(queue, (unsigned long long)cnt);
             __syncthreads();
@@ -374,10 +327,10 @@ static int num_cus() {
 template <int TPW, int NW, typename IO>
 static int launch_rows(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
                        int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                       unsigned long long *queue, const MismatchArgs &mm, hipStream_t stream) {
+                       unsigned long long *queue, hipStream_t stream) {
     const int MT = dn.MT;
     const size_t lds = (size_t)256 * MT * sizeof(double) + (size_t)NW * 16 * (sizeof(double) + sizeof(int)) + 16 +
-                       (size_t)16 * MT * sizeof(double) + (mm.out ? mm.staged : 0);
+                       (size_t)16 * MT * sizeof(double);
     if (hipFuncSetAttribute((const void *)fpi_f64_kernel<TPW, NW, IO>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
@@ -388,17 +341,17 @@ static int launch_rows(const tpf_network_s &net, const DeviceNet &dn, const void
     const long long blocks = std::min<long long>((long long)num_cus() * per_cu, (tau + 15) / 16);
     hipLaunchKernelGGL((fpi_f64_kernel<TPW, NW, IO>), dim3((unsigned)blocks), dim3(NW * 64), lds, stream,
                        (const IO *)S, (IO *)V, iters, status, (const IO *)V0, dn.A64, dn.w64, net.n, MT,
-                       (long long)tau, tol, max_iter, queue, mm);
+                       (long long)tau, tol, max_iter, queue);
     return TPF_OK;
 }
 
 template <typename IO>
 static int dispatch_rows(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
                          int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                         unsigned long long *queue, const MismatchArgs &mm, hipStream_t stream) {
+                         unsigned long long *queue, hipStream_t stream) {
 #define TPF_GO(T, W)                                                                                      \
     if (dn.TPW == T && dn.NW == W)                                                                        \
-        return launch_rows<T, W, IO>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream);
+        return launch_rows<T, W, IO>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);
     TPF_GO(1, 4) TPF_GO(1, 8) TPF_GO(2, 8) TPF_GO(3, 8) TPF_GO(4, 8) TPF_GO(5, 8)
 #undef TPF_GO
     return fail(TPF_ERR_UNSUPPORTED, "register-resident sweep kernel: no instance for this network size");
@@ -406,12 +359,10 @@ static int dispatch_rows(const tpf_network_s &net, const DeviceNet &dn, const vo
 
 int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype, int64_t tau,
                          double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                         unsigned long long *queue, double *mismatch_out, hipStream_t stream) {
-    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, mismatch_out, dn.nnz,
-                          mismatch_lds_bytes(net.n, dn.nnz, 48 * 1024)};
+                         unsigned long long *queue, hipStream_t stream) {
     if (dtype == TPF_C128)
-        return dispatch_rows<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream);
-    return dispatch_rows<float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, mm, stream);
+        return dispatch_rows<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);
+    return dispatch_rows<float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);
 }
 
 int launch_start_only(int n, const void *V0, int dtype, int64_t tau, void *V, int32_t *iters, int8_t *status,

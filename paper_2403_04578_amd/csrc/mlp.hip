@@ -220,6 +220,14 @@ __global__ void sync_kernel(const float *__restrict__ p, int64_t woff, int in, i
 // stores.  Nothing but S and V0 touches HBM.
 constexpr int kFusedWidth = 256, kFusedRows = 64, kHStride = 264, kYStride = 257;
 constexpr size_t kFusedLds = (size_t)2 * kFusedRows * kHStride * 2;  // >= 64 x 257 FP32 (aliased)
+static_assert(kFusedRows * 4 == 256, "one (row, calendar phase) pair per thread");
+
+// Complex pairs as clang vectors, so that the streamed loads and stores can carry the
+// nontemporal hint (S and V0 pass once; the weights should stay in L2).
+template <typename IO>
+struct Pair {
+    typedef IO T __attribute__((ext_vector_type(2)));
+};
 
 struct MlpView {
     const __bf16 *W[17];  // [out_p][in_p] per layer
@@ -253,22 +261,45 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
     const int g = lane >> 4, j = lane & 15;
     const int n = mv.n, dp0 = mv.dp[0];
     const int64_t r0 = (int64_t)blockIdx.x * kFusedRows;
-    // features: 50 P, 50 Q, then the calendar phases; zero padding and zero rows past the end
-    for (int e = tid; e < kFusedRows * n; e += 256) {
-        const int r = e / n, b = e - r * n;
-        float pr = 0.0f, pi = 0.0f;
-        if (r0 + r < rows) {
-            pr = kFeatScale * (float)S[2 * ((r0 + r) * n + b)];
-            pi = kFeatScale * (float)S[2 * ((r0 + r) * n + b) + 1];
+    // features: 50 P, 50 Q, then the calendar phases; zero padding and zero rows past the
+    // end.  The tile's loads are one contiguous block of 64 n complex values: each thread
+    // issues 8 independent loads before converting any, so HBM latency is paid per chunk.
+    // Element e = 256 i + tid of the block is (row e / n, bus e % n), tracked incrementally.
+    {
+        typedef typename Pair<IO>::T P2;
+        const int total = kFusedRows * n;
+        const int64_t valid = (rows - r0) * (int64_t)n;
+        const P2 *src = reinterpret_cast<const P2 *>(S) + r0 * n;
+        int r = tid / n, b = tid - (tid / n) * n;  // position of element tid
+        const int dr = 256 / n, db = 256 - dr * n;   // step of 256 elements
+        for (int e0 = tid; e0 < total; e0 += 256 * 8) {
+            P2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int e = e0 + 256 * u;
+                v[u] = P2{0, 0};
+                if (e < total && e < valid) v[u] = __builtin_nontemporal_load(src + e);
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (e0 + 256 * u < total) {
+                    H0[r * kHStride + b] = (__bf16)(kFeatScale * (float)v[u].x);
+                    H0[r * kHStride + n + b] = (__bf16)(kFeatScale * (float)v[u].y);
+                }
+                r += dr;
+                b += db;
+                if (b >= n) {
+                    b -= n;
+                    r += 1;
+                }
+            }
         }
-        H0[r * kHStride + b] = (__bf16)pr;
-        H0[r * kHStride + n + b] = (__bf16)pi;
     }
-    const int tail = dp0 - 2 * n;
-    for (int e = tid; e < kFusedRows * tail; e += 256) {
-        const int r = e / tail, f = 2 * n + (e - r * tail);
+    // calendar phases (one (row, phase) pair per thread) and zero padding up to dp0
+    {
+        const int r = tid >> 2, f = 2 * n + (tid & 3);
         float v = 0.0f;
-        if (r0 + r < rows && f < 2 * n + 4) {
+        if (r0 + r < rows) {
             const int64_t t = t_index[r0 + r];
             const double mod = (double)(t % 1440) / 1440.0;
             const double day = (double)((t / 1440) % 365) / 365.0;
@@ -276,6 +307,8 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
             v = (float)(((f - 2 * n) & 1) ? cos(ang) : sin(ang));
         }
         H0[r * kHStride + f] = (__bf16)v;
+        for (int c = 2 * n + 4 + (tid & 63); c < dp0; c += 64)
+            for (int rr = tid >> 6; rr < kFusedRows; rr += 4) H0[rr * kHStride + c] = (__bf16)0.0f;
     }
     __syncthreads();
     __bf16 *hin = H0, *hout = H1;
@@ -290,15 +323,14 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
         if (mine) {
+            // weight fragments ping-pong between two register sets: the next k-step's
+            // loads are in flight while this one's products run (K is a multiple of 64)
             const __bf16 *Wl = mv.W[l] + (int64_t)(n0 + j) * K + 8 * g;
-            b8 bf[4], bn[4];
+            auto ldw = [&](b8(&w)[4], int k0) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) bf[b] = *reinterpret_cast<const b8 *>(Wl + (int64_t)16 * b * K);
-            for (int k0 = 0; k0 < K; k0 += 32) {
-                if (k0 + 32 < K) {
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) bn[b] = *reinterpret_cast<const b8 *>(Wl + (int64_t)16 * b * K + k0 + 32);
-                }
+                for (int b = 0; b < 4; ++b) w[b] = *reinterpret_cast<const b8 *>(Wl + (int64_t)16 * b * K + k0);
+            };
+            auto step = [&](const b8(&w)[4], int k0) {
                 b8 af[4];
 #pragma unroll
                 for (int a = 0; a < 4; ++a)
@@ -307,9 +339,15 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
                 for (int a = 0; a < 4; ++a)
 #pragma unroll
                     for (int b = 0; b < 4; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], bf[b], acc[a][b], 0, 0, 0);
-#pragma unroll
-                for (int b = 0; b < 4; ++b) bf[b] = bn[b];
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], w[b], acc[a][b], 0, 0, 0);
+            };
+            b8 w0[4], w1[4];
+            ldw(w0, 0);
+            for (int k0 = 0; k0 < K; k0 += 64) {
+                ldw(w1, k0 + 32);
+                step(w0, k0);
+                if (k0 + 64 < K) ldw(w0, k0 + 64);
+                step(w1, k0 + 32);
             }
         }
         if (last) __syncthreads();  // every wave is done with hin: the FP32 staging overwrites it
@@ -337,12 +375,23 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
         hin = hout;
         hout = tmp;
     }
-    for (int e = tid; e < kFusedRows * n; e += 256) {
-        const int r = e / n, b = e - r * n;
-        if (r0 + r < rows) {
-            IO *o = V0 + 2 * ((r0 + r) * n + b);
-            o[0] = (IO)(vs_re + (double)Yf[r * kYStride + b] / kOutScale);
-            o[1] = (IO)(vs_im + (double)Yf[r * kYStride + n + b] / kOutScale);
+    {
+        typedef typename Pair<IO>::T P2;
+        P2 *dst = reinterpret_cast<P2 *>(V0) + r0 * n;
+        const int64_t valid = (rows - r0) * (int64_t)n;
+        const double inv_scale = 1.0 / kOutScale;
+        int r = tid / n, b = tid - (tid / n) * n;
+        const int dr = 256 / n, db = 256 - dr * n;
+        for (int e = tid; e < kFusedRows * n && e < valid; e += 256) {
+            const P2 o = P2{(IO)(vs_re + (double)Yf[r * kYStride + b] * inv_scale),
+                            (IO)(vs_im + (double)Yf[r * kYStride + n + b] * inv_scale)};
+            __builtin_nontemporal_store(o, dst + e);
+            r += dr;
+            b += db;
+            if (b >= n) {
+                b -= n;
+                r += 1;
+            }
         }
     }
 }

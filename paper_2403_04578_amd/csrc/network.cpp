@@ -246,7 +246,6 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
     // ---- CSR Y_dd and c = Y_ds v_s (FP64 mismatch)
     {
         const size_t nnz = net.colidx.size();
-        dn.nnz = (int)nnz;
         std::vector<double> yv(2 * nnz), cv(2 * n);
         for (size_t e = 0; e < nnz; ++e) yv[2 * e] = net.yval[e].real(), yv[2 * e + 1] = net.yval[e].imag();
         for (int i = 0; i < n; ++i) cv[2 * i] = net.c[i].real(), cv[2 * i + 1] = net.c[i].imag();

@@ -55,7 +55,6 @@ struct DeviceNet {
     uint16_t *ALbf = nullptr, *ALh = nullptr;
     double *wl = nullptr;
     // Sparse Y_dd (CSR) and c = Y_ds v_s for the FP64 mismatch.
-    int nnz = 0;                 // entries of the CSR below
     int32_t *rowptr = nullptr;   // [n+1]
     int32_t *colidx = nullptr;   // [nnz]
     double *yval = nullptr;      // [nnz][2]
@@ -65,62 +64,6 @@ struct DeviceNet {
 
 // Sparse Y_dd and c = Y_ds v_s on the device, for the FP64 power-balance mismatch
 // (Eq. (1)); `out` is NULL when no mismatch is requested.
-struct MismatchArgs {
-    const int32_t *rowptr;
-    const int32_t *colidx;
-    const double *yval;  // [nnz][2]
-    const double *cval;  // [n][2]
-    double *out;         // [tau]
-    int nnz = 0;
-    int staged = 0;      // bytes of LDS the sweep kernel reserves for a copy of the CSR (0: none)
-};
-
-// LDS bytes of a copy of the mismatch CSR (yval, cval, then rowptr, colidx), or 0 when it
-// exceeds `cap` (dense rows of a meshed network) and the kernel reads global memory.
-inline int mismatch_lds_bytes(int n, int nnz, int cap) {
-    const long long b = ((16LL * nnz + 16LL * n + 4LL * (n + 1) + 4LL * nnz) + 15) / 16 * 16;
-    return b <= cap ? (int)b : 0;
-}
-
-// Copies the CSR into `lds` (all threads of the block take part; the caller synchronises
-// before use) and returns arguments that point there.  The retiring columns' mismatch
-// then walks the sparse rows at LDS latency instead of chains of global loads.
-__device__ inline MismatchArgs stage_mismatch(const MismatchArgs &mm, int n, void *lds, int tid, int nthr) {
-    double *yv = static_cast<double *>(lds);
-    double *cv = yv + 2 * mm.nnz;
-    int32_t *rp = reinterpret_cast<int32_t *>(cv + 2 * n);
-    int32_t *ci = rp + n + 1;
-    for (int i = tid; i < 2 * mm.nnz; i += nthr) yv[i] = mm.yval[i];
-    for (int i = tid; i < 2 * n; i += nthr) cv[i] = mm.cval[i];
-    for (int i = tid; i <= n; i += nthr) rp[i] = mm.rowptr[i];
-    for (int i = tid; i < mm.nnz; i += nthr) ci[i] = mm.colidx[i];
-    MismatchArgs r = mm;
-    r.rowptr = rp;
-    r.colidx = ci;
-    r.yval = yv;
-    r.cval = cv;
-    return r;
-}
-
-__device__ __forceinline__ double nanmax_d(double a, double b) { return (a > b || a != a) ? a : b; }
-
-// |m_b| = |S_b + V_b conj(c_b + sum_k (Y_dd)_bk V_k)| for one bus; `vk(k, re, im)` fetches V_k.
-template <typename F>
-__device__ __forceinline__ double bus_mismatch(const MismatchArgs &mm, int b, double sr, double si, double vr,
-                                               double vi, F vk) {
-    double ar = mm.cval[2 * b], ai = mm.cval[2 * b + 1];
-    for (int e = mm.rowptr[b]; e < mm.rowptr[b + 1]; ++e) {
-        double xr, xi;
-        vk(mm.colidx[e], xr, xi);
-        const double yr = mm.yval[2 * e], yi = mm.yval[2 * e + 1];
-        ar += yr * xr - yi * xi;
-        ai += yr * xi + yi * xr;
-    }
-    const double mr = sr + vr * ar + vi * ai;
-    const double mi = si + vi * ar - vr * ai;
-    return sqrt(mr * mr + mi * mi);
-}
-
 }  // namespace tpf
 
 struct tpf_network_s {
@@ -150,11 +93,10 @@ int device_net(tpf_network net, DeviceNet **out);
 // Launchers (device code in fpi_small.hip / mismatch.hip).  All asynchronous on `stream`.
 int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype,
                          int64_t tau, double tol, int max_iter, const void *V0, void *V,
-                         int32_t *iters, int8_t *status, unsigned long long *queue,
-                         double *mismatch_out, hipStream_t stream);
+                         int32_t *iters, int8_t *status, unsigned long long *queue, hipStream_t stream);
 int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype,
                      int64_t tau, double tol, int max_iter, const void *V0, void *V, int32_t *iters,
-                     int8_t *status, unsigned long long *queue, double *mismatch_out, hipStream_t stream);
+                     int8_t *status, unsigned long long *queue, hipStream_t stream);
 int launch_fpi_large(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype,
                      int64_t tau, double tol, int max_iter, const void *V0, void *V, int32_t *iters,
                      int8_t *status, void *workspace, hipStream_t stream);

@@ -42,6 +42,13 @@ def _compare(onet, S, V, it, st, tol, max_iter, bound, V0=None, rows=None):
     return err
 
 
+def _mm_rounding(onet):
+    """Rounding scale of an FP64 mismatch: its terms Y_bk V_k cancel from about
+    rowsum |Y_dd| down to the mismatch, so summation orders differ by a few units of
+    2^-52 rowsum |Y_dd|."""
+    return 16 * 2.0 ** -52 * float(np.abs(onet.Ydd).sum(axis=1).max())
+
+
 @pytest.fixture(scope="module")
 def feeder1000():
     f = W.make_feeder(1000)
@@ -87,7 +94,7 @@ def test_complex64_io_and_mismatch(gpu, feeder1000):
     assert V.dtype == torch.complex64
     _compare(onet, S.astype(np.complex128), V, it, st, 1e-6, 100, 2e-7)
     ref_mm = oracle.mismatch(onet, S.astype(np.complex128), V.cpu().numpy().astype(np.complex128))
-    assert np.all(np.abs(mm.cpu().numpy() - ref_mm) <= 1e-12 + 1e-9 * ref_mm)
+    assert np.all(np.abs(mm.cpu().numpy() - ref_mm) <= _mm_rounding(onet) + 1e-9 * ref_mm)
 
 
 def test_edge_columns(gpu, feeder1000):
@@ -144,7 +151,7 @@ def test_mixed_every_column(gpu, mode, n_bus, T):
     # against the (near-exact) tol-1e-10 oracle solution
     mref = oracle.mismatch(onet, S, Vg)
     g = mm.cpu().numpy()
-    assert np.all(np.abs(g - mref) <= 1e-12 + 1e-9 * mref)
+    assert np.all(np.abs(g - mref) <= _mm_rounding(onet) + 1e-9 * mref)
     ymax = np.abs(onet.Ydd).sum(axis=1).max()
     assert np.all(g <= 1.2 * ymax * err + 1e-9)
 
