@@ -323,31 +323,33 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
         if (mine) {
-            // weight fragments ping-pong between two register sets: the next k-step's
-            // loads are in flight while this one's products run (K is a multiple of 64)
+            // weight fragments stream from L2 through a ring of four register sets, three
+            // k-steps ahead of the products that use them (K <= 256: at most 8 k-steps)
             const __bf16 *Wl = mv.W[l] + (int64_t)(n0 + j) * K + 8 * g;
+            const int ks = K / 32;
             auto ldw = [&](b8(&w)[4], int k0) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) w[b] = *reinterpret_cast<const b8 *>(Wl + (int64_t)16 * b * K + k0);
             };
-            auto step = [&](const b8(&w)[4], int k0) {
-                b8 af[4];
+            b8 w[4][4];
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
-                    af[a] = *reinterpret_cast<const b8 *>(hin + (16 * a + j) * kHStride + k0 + 8 * g);
+            for (int st = 0; st < 3; ++st)
+                if (st < ks) ldw(w[st], 32 * st);
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+            for (int st = 0; st < kFusedWidth / 32; ++st) {
+                if (st < ks) {
+                    if (st + 3 < ks) ldw(w[(st + 3) & 3], 32 * (st + 3));
+                    b8 af[4];
 #pragma unroll
-                    for (int b = 0; b < 4; ++b)
-                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], w[b], acc[a][b], 0, 0, 0);
-            };
-            b8 w0[4], w1[4];
-            ldw(w0, 0);
-            for (int k0 = 0; k0 < K; k0 += 64) {
-                ldw(w1, k0 + 32);
-                step(w0, k0);
-                if (k0 + 64 < K) ldw(w0, k0 + 64);
-                step(w1, k0 + 32);
+                    for (int a = 0; a < 4; ++a)
+                        af[a] = *reinterpret_cast<const b8 *>(hin + (16 * a + j) * kHStride + 32 * st + 8 * g);
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int b = 0; b < 4; ++b)
+                            acc[a][b] =
+                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], w[st & 3][b], acc[a][b], 0, 0, 0);
+                }
             }
         }
         if (last) __syncthreads();  // every wave is done with hin: the FP32 staging overwrites it
