@@ -169,6 +169,94 @@ def cpu_baseline(net_args, S, tol, max_iter, budget_s=12.0):
             "sample": f"first {n} of {len(S)} one-minute steps of the year, tol {tol:g} pu, FP64, {dt:.1f} s"}
 
 
+def bench_other(args):
+    """The other two workloads of the method, every form without the warm start (its
+    network is the 100-bus one): the 300-bus scenario tensor (complex64, built on the
+    device from its factors) and the 1,000-bus feeder over 200,000 minutes.  Prints one
+    JSON line."""
+    import torch
+
+    import paper_2403_04578_amd as tpf
+    from paper_2403_04578_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    tol, max_iter = 1e-6, 100
+    t0 = time.perf_counter()
+    if args.workload == "tensor300":
+        f = W.make_feeder(300)
+        loads = W.scenario_loads(f)
+        c = torch.from_numpy(loads.c.astype(np.float32)).to(dev)
+        L = torch.from_numpy(loads.L.astype(np.complex64)).to(dev)
+        PV = torch.from_numpy(loads.PV.astype(np.float32)).to(dev)
+        S = (c[:, None, None] * L[None] - PV[None]).contiguous().reshape(-1, f.n_bus - 1)
+        del c, L, PV
+        desc = "300-bus radial feeder (299 PQ), 1,000 scenarios x 8,760 hours, complex64 S"
+        sample = lambda k: loads.element(np.arange(k) // 8760, np.arange(k) % 8760, np.complex128)
+    else:
+        f = W.make_feeder(1000)
+        S_host = W.profile_minute_year(f, steps=200_000)
+        S = torch.from_numpy(S_host).to(dev)
+        desc = "1,000-bus radial feeder (999 PQ), 200,000 one-minute steps, complex128 S"
+        sample = lambda k: S_host[:k]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    T, n = S.shape
+    net = tpf.Network.from_feeder(f)
+    stream = torch.cuda.current_stream(dev)
+    esz = S.element_size()
+    forms = {}
+    for mode in ("fp64", "fp32", "mixed_bf16", "mixed_fp16"):
+        out = tpf.alloc_outputs(net, S, mode, mismatch=True)
+        kout = (out[0], out[1], out[2], None, out[4])  # same buffers, no mismatch pass
+        for _ in range(args.warmup):
+            tpf.solve_timeseries(net, S, tol, max_iter, mode, mismatch=True, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            tpf.solve_timeseries(net, S, tol, max_iter, mode, mismatch=True, out=out)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / args.steps
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        tpf.solve_timeseries(net, S, tol, max_iter, mode, out=kout)
+        b.record(stream)
+        torch.cuda.synchronize()
+        tpf.solve_timeseries(net, S, tol, max_iter, mode, mismatch=True, out=out)  # outputs of a full step
+        it = out[1].double()
+        sweeps = float(it.sum())
+        k_ms = a.elapsed_time(b)
+        flops = 8.0 * n * n * sweeps
+        forms[mode] = {"ms_per_step": 1e3 * wall, "solve_ms": k_ms, "power_flows_per_s": T / wall,
+                       "sweeps_mean": sweeps / T, "converged": int((out[2] == tpf.ST_CONVERGED).sum()),
+                       "max_mismatch_pu": float(out[3].max()),
+                       "solve_tflops": flops / (k_ms * 1e-3) / 1e12,
+                       "solve_hbm_gbs": 2.0 * esz * n * T / (k_ms * 1e-3) / 1e9}
+        del out, kout
+        torch.cuda.empty_cache()
+    base = forms["fp64"]
+    for r in forms.values():
+        r["speedup_vs_fp64"] = base["ms_per_step"] / r["ms_per_step"]
+    head = min(("mixed_fp16", "mixed_bf16"), key=lambda m: forms[m]["ms_per_step"])
+    rec = {"metric": f"power flows/s to 1e-6 pu, {args.workload}", "value": forms[head]["power_flows_per_s"],
+           "unit": "power flows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": forms[head]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f16" if head == "mixed_fp16" else "bf16", "data": "synthetic",
+           "config": {"workload": desc + ", tol 1e-6 pu, max 100 sweeps, + FP64 mismatch", "form": head,
+                      "n_pq": n, "power_flows": T},
+           "forms": forms, "setup_s": setup_s}
+    if not args.no_cpu_baseline:
+        import oracle
+        onet = oracle.build_network(f.n_bus, f.frm, f.to, f.r, f.x, 0, f.vs)
+        k = 200 if n > 500 else 2000
+        Sk = sample(k)
+        t0 = time.perf_counter()
+        oracle.fpi(onet, Sk, tol, max_iter)
+        dt = time.perf_counter() - t0
+        rec["cpu_baseline"] = {"value": k / dt, "unit": "power flows/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"first {k} columns of the workload, {dt:.1f} s"}
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,6 +273,10 @@ def main():
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
                          "--calib-copy into profiles/hbm_traffic.json and exit")
+    ap.add_argument("--workload", default="year100", choices=["year100", "tensor300", "feeder1000"],
+                    help="year100 (default, headline): 100-bus feeder, 525,600 minutes; tensor300: 300-bus "
+                         "feeder, 1,000 scenarios x 8,760 hours, complex64; feeder1000: 1,000-bus feeder, "
+                         "200,000 minutes")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT_TXT", "COMMAND"),
                     help="write a short text summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
@@ -198,6 +290,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+
+    if args.workload != "year100":
+        bench_other(args)
+        return
 
     import torch
 

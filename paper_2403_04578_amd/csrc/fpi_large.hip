@@ -121,8 +121,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T *__restrict__ A, int 
     const int c0 = blockIdx.x * 64;
     if (c0 >= nact) return;
     const int r0 = blockIdx.y * 64;
-    __shared__ T As[64][17];
-    __shared__ T Bs[64][17];
+    __shared__ T As[2][64][17];  // two buffers: the next k-slab lands while this one is used
+    __shared__ T Bs[2][64][17];
     __shared__ double red[2][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
@@ -130,29 +130,41 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T *__restrict__ A, int 
     v4 acc[2][2];
     for (int a = 0; a < 2; ++a)
         for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+    const int rr = tid >> 2, kk = (tid & 3) * 4;
+    const T *Ap = A + (size_t)(r0 + rr) * KP + kk, *Bp = B + (size_t)(c0 + rr) * KP + kk;
+    // the next k-slab is fetched into registers while the current one is multiplied
+    T pa0 = Ap[0], pa1 = Ap[1], pa2 = Ap[2], pa3 = Ap[3];
+    T pb0 = Bp[0], pb1 = Bp[1], pb2 = Bp[2], pb3 = Bp[3];
+    As[0][rr][kk] = pa0, As[0][rr][kk + 1] = pa1, As[0][rr][kk + 2] = pa2, As[0][rr][kk + 3] = pa3;
+    Bs[0][rr][kk] = pb0, Bs[0][rr][kk + 1] = pb1, Bs[0][rr][kk + 2] = pb2, Bs[0][rr][kk + 3] = pb3;
+    __syncthreads();
+    int buf = 0;
     for (int k0 = 0; k0 < KP; k0 += 16) {
-        {
-            const int rr = tid >> 2, kk = (tid & 3) * 4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                As[rr][kk + e] = A[(size_t)(r0 + rr) * KP + k0 + kk + e];
-                Bs[rr][kk + e] = B[(size_t)(c0 + rr) * KP + k0 + kk + e];
-            }
+        const bool more = k0 + 16 < KP;
+        if (more) {
+            const int o = k0 + 16;
+            pa0 = Ap[o], pa1 = Ap[o + 1], pa2 = Ap[o + 2], pa3 = Ap[o + 3];
+            pb0 = Bp[o], pb1 = Bp[o + 1], pb2 = Bp[o + 2], pb3 = Bp[o + 3];
         }
-        __syncthreads();
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             T af[2], bf[2];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) af[a] = As[wr + 16 * a + j][4 * ks + g];
+            for (int a = 0; a < 2; ++a) af[a] = As[buf][wr + 16 * a + j][4 * ks + g];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bf[b] = Bs[wc + 16 * b + j][4 * ks + g];
+            for (int b = 0; b < 2; ++b) bf[b] = Bs[buf][wc + 16 * b + j][4 * ks + g];
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) acc[a][b] = Ops::mma(af[a], bf[b], acc[a][b]);
         }
+        if (more) {  // the other buffer: its last readers passed the previous barrier
+            T *as = &As[buf ^ 1][rr][kk], *bs = &Bs[buf ^ 1][rr][kk];
+            as[0] = pa0, as[1] = pa1, as[2] = pa2, as[3] = pa3;
+            bs[0] = pb0, bs[1] = pb1, bs[2] = pb2, bs[3] = pb3;
+        }
         __syncthreads();
+        buf ^= 1;
     }
     // epilogue: each lane holds both parts of two buses (FP64 layout) or of two buses
     // (FP32 interleaved layout: rows 4g..4g+3 = Re/Im of two buses) of column j
@@ -400,8 +412,8 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
     const int c0 = blockIdx.x * 128;
     if (c0 >= nact) return;
     const int r0 = blockIdx.y * 128;
-    __shared__ uint4 As[128][5];  // 32 K values per row + one pad quad against bank conflicts
-    __shared__ uint4 Bs[128][5];
+    __shared__ uint4 As[2][128][5];  // 32 K values per row + one pad quad against bank conflicts;
+    __shared__ uint4 Bs[2][128][5];  // two buffers: the next k-slab lands while this one is used
     __shared__ float redd[2][128], redu[2][128];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
@@ -411,24 +423,45 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 4; ++b) acc[a][b] = f4x{0.f, 0.f, 0.f, 0.f};
+    // thread tid moves quads (row tid / 4, q) and (row 64 + tid / 4, q) of both operands
+    const int lrow = tid >> 2, lq = tid & 3;
+    const uint4 *Ap = reinterpret_cast<const uint4 *>(A + (size_t)(r0 + lrow) * KP16 + 8 * lq);
+    const uint4 *Bp = reinterpret_cast<const uint4 *>(B + (size_t)(c0 + lrow) * KP16 + 8 * lq);
+    const size_t half = (size_t)64 * KP16 / 8;  // 64 rows further, in quads
+    // the next k-slab is fetched into registers while the current one is multiplied
+    uint4 pa0 = Ap[0], pa1 = Ap[half], pb0 = Bp[0], pb1 = Bp[half];
+    As[0][lrow][lq] = pa0;
+    As[0][64 + lrow][lq] = pa1;
+    Bs[0][lrow][lq] = pb0;
+    Bs[0][64 + lrow][lq] = pb1;
+    __syncthreads();
+    int buf = 0;
     for (int k0 = 0; k0 < KP16; k0 += 32) {
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int idx = tid + 256 * h, row = idx >> 2, q = idx & 3;
-            As[row][q] = *reinterpret_cast<const uint4 *>(A + (size_t)(r0 + row) * KP16 + k0 + 8 * q);
-            Bs[row][q] = *reinterpret_cast<const uint4 *>(B + (size_t)(c0 + row) * KP16 + k0 + 8 * q);
+        const bool more = k0 + 32 < KP16;
+        if (more) {
+            const int o = (k0 + 32) / 8;
+            pa0 = Ap[o];
+            pa1 = Ap[half + o];
+            pb0 = Bp[o];
+            pb1 = Bp[half + o];
         }
-        __syncthreads();
         uint4 af[4], bf[4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) af[a] = As[wr + 16 * a + j][g];
+        for (int a = 0; a < 4; ++a) af[a] = As[buf][wr + 16 * a + j][g];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bf[b] = Bs[wc + 16 * b + j][g];
+        for (int b = 0; b < 4; ++b) bf[b] = Bs[buf][wc + 16 * b + j][g];
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = Low16<MODE>::mma(af[a], bf[b], acc[a][b]);
+        if (more) {  // the other buffer: its last readers passed the previous barrier
+            As[buf ^ 1][lrow][lq] = pa0;
+            As[buf ^ 1][64 + lrow][lq] = pa1;
+            Bs[buf ^ 1][lrow][lq] = pb0;
+            Bs[buf ^ 1][64 + lrow][lq] = pb1;
+        }
         __syncthreads();
+        buf ^= 1;
     }
     // lane group g holds rows 4g..4g+3 of each 16-row tile: Re/Im of two buses
 #pragma unroll

@@ -135,3 +135,21 @@ def test_nonfinite_parameters_fall_back_to_flat_start(data):
     Vw, iw, sw = tpf.solve_timeseries(net, Sv, 1e-8, 100, V0=V0)
     Vf, i_f, sf = tpf.solve_timeseries(net, Sv, 1e-8, 100)
     assert torch.equal(Vw, Vf) and torch.equal(iw, i_f)
+
+
+@pytest.mark.parametrize("rows", [1, 63, 64, 65, 1000])
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_fused_prediction_ragged_rows_and_dtypes(data, rows, dtype):
+    """The inference kernel works on 64-row tiles: partial last tiles, both complex
+    dtypes, and rows far apart in the year (calendar features) all match the reference."""
+    f, net, onet, S, t, Sd, td, V = data
+    sizes = W.mlp_sizes(99)
+    p0 = W.mlp_init_params(sizes, seed=21)
+    mlp = tpf.WarmStart(99, params=p0)
+    Sx = Sd[-rows:].to(dtype).contiguous()
+    V0 = mlp.predict(Sx, td[-rows:].contiguous())
+    assert V0.dtype == dtype and V0.shape == Sx.shape
+    Sh = Sx.cpu().numpy().astype(np.complex128)
+    y, _ = M.forward(_ref_params(p0, sizes), sizes, bf16_round(M.features(Sh, t[-rows:])))
+    err = np.abs(V0.cpu().numpy().astype(np.complex128) - M.to_voltage(y)).max()
+    assert err < 5e-3 * max(1.0, np.abs(y).max() / 20) + (1e-7 if dtype == torch.complex64 else 0.0), err
