@@ -166,7 +166,19 @@ def cpu_baseline(net_args, S, tol, max_iter, budget_s=12.0):
     oracle.fpi(onet, S[:n], tol, max_iter)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "power flows/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {n} of {len(S)} one-minute steps of the year, tol {tol:g} pu, FP64, {dt:.1f} s"}
+            "sample": f"first {n} of {len(S)} one-minute steps of the year, tol {tol:g} pu, FP64, {dt:.1f} s, "
+                      f"host CPU: {_cpu_model()}, {os.cpu_count()} logical CPUs visible"}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def bench_other(args):

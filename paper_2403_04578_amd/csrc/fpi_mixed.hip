@@ -101,7 +101,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const float *__restrict__ A32,
     const uint16_t *__restrict__ Alow, const uint16_t *__restrict__ Alo, const double *__restrict__ wv, int n,
-    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue) {
+    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue, int use_pf) {
     using L = LowOps<MODE>;
     typedef typename L::frag frag;
     typedef typename L::quad quad;
@@ -126,6 +126,8 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     ColState *cs = reinterpret_cast<ColState *>(rok + NC);                            // [2][NC]
     unsigned long long *qb = reinterpret_cast<unsigned long long *>(cs + 2 * NC);
     double *wl = reinterpret_cast<double *>(qb + 2);                                  // [2][8 MT] w
+    // S of the next batch, copied from HBM into LDS (no registers) while this batch sweeps
+    IO *Spf = reinterpret_cast<IO *>(wl + 16 * MT);                                   // [NC][n][2]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -220,16 +222,31 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
         }
     };
 
+    // Starts copying the S rows of batch `nb` (NC consecutive columns, contiguous in HBM)
+    // into Spf: each wavefront moves 1 KB per instruction straight into LDS.
+    auto prefetch = [&](unsigned long long nb) {
+        if (nb >= (unsigned long long)tau) return;
+        const long long cols = (long long)tau - (long long)nb < NC ? (long long)tau - (long long)nb : NC;
+        const long long bytes = cols * n * 2 * (long long)sizeof(IO);
+        const char *src = reinterpret_cast<const char *>(S + 2 * (long long)nb * n);
+        char *dst = reinterpret_cast<char *>(Spf);
+        for (long long off = (long long)wave * 1024; off < bytes; off += (long long)NW * 1024) {
+            if (off + 16 * lane < bytes)
+                __builtin_amdgcn_global_load_lds(src + off + 16 * lane,
+                                                 (__attribute__((address_space(3))) void *)(dst + off), 16, 0, 0);
+        }
+    };
+    bool from_pf = false;  // this refill's S is already in Spf
     auto refill = [&]() -> bool {
         if (tid < NC) {
             rsm[tid] = 0.0f;
             rok[tid] = 0;
         }
-        if (tid == 0) *qb = exhausted ? (unsigned long long)tau : atomicAdd(queue, (unsigned long long)NC);
+        if (tid == 0 && !from_pf) qb[0] = atomicAdd(queue, (unsigned long long)NC);
+        if (from_pf) __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wavefront's copies landed
         __syncthreads();
-        const unsigned long long base = *qb;
+        const unsigned long long base = from_pf ? qb[1] : qb[0];
         if (base >= (unsigned long long)tau) return false;
-        if (base + NC >= (unsigned long long)tau) exhausted = true;
 #pragma unroll
         for (int c = 0; c < CG; ++c) {
             const long long cc = (long long)base + 16 * c + j;
@@ -244,7 +261,10 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         if (b0 + h < n) {
-                            ldc(S + 2 * (col[c] * n + b0 + h), s[2 * h], s[2 * h + 1]);
+                            if (from_pf)
+                                ldc(Spf + 2 * ((16 * c + j) * n + b0 + h), s[2 * h], s[2 * h + 1]);
+                            else
+                                ldc(S + 2 * (col[c] * n + b0 + h), s[2 * h], s[2 * h + 1]);
                             if (V0) {
                                 ldc(V0 + 2 * (col[c] * n + b0 + h), v[2 * h], v[2 * h + 1]);
                                 const double m2 = v[2 * h] * v[2 * h] + v[2 * h + 1] * v[2 * h + 1];
@@ -270,7 +290,14 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                 if (bad | sbad) atomicOr(rok + 16 * c + j, bad | (sbad << 1));
             }
         }
-        __syncthreads();
+        if (kSplit && use_pf && tid == 0)  // the batch after this one, whose S is copied meanwhile
+            qb[1] = base + NC >= (unsigned long long)tau ? (unsigned long long)tau
+                                                         : atomicAdd(queue, (unsigned long long)NC);
+        __syncthreads();  // column reductions complete; every wavefront is done with Spf
+        if (kSplit && use_pf) {
+            prefetch(qb[1]);
+            from_pf = true;
+        }
 #pragma unroll
         for (int c = 0; c < CG; ++c) {
             if (V0 && (rok[16 * c + j] & 1)) {  // guard failed somewhere in the column: flat start
@@ -521,8 +548,13 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     constexpr bool mixed = MODE != TPF_MODE_FP32, split = MODE == TPF_MODE_MIXED_FP16;
     const size_t NC = 16 * CG, NT = NW * 64;
     const size_t KPL = 32 * KTL + 8, KP32 = 16 * MT + 4;
-    const size_t lds = NC * KP32 * 4 + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) + (size_t)CG * TPW * NT * 16 +
-                       NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 16 + 64 + (size_t)16 * MT * 8;
+    const size_t lds0 = NC * KP32 * 4 + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) + (size_t)CG * TPW * NT * 16 +
+                        NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 16 + 64 + (size_t)16 * MT * 8;
+    // the next batch's S is prefetched into LDS when it fits beside the rest
+    const size_t spf = ((size_t)NC * net.n * 2 * sizeof(IO) + 1023) / 1024 * 1024;
+    // (measured: it pays in the FP16 form, not in the BF16 one, whose registers it raises)
+    const int use_pf = split && lds0 + spf <= (size_t)160 * 1024 ? 1 : 0;
+    const size_t lds = lds0 + (use_pf ? spf : 0);
     auto kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, IO>;
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
@@ -535,7 +567,7 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     const long long blocks = std::min<long long>((long long)cus * per_cu, (tau + (long long)NC - 1) / (long long)NC);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.A32, MODE == TPF_MODE_MIXED_BF16 ? dn.Abf : dn.Ah, dn.Al,
-                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue);
+                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue, use_pf);
     return TPF_OK;
 }
 
