@@ -191,7 +191,7 @@ int tpf_mlp_train_step(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t 
 
 /* Warm start V0 (device [rows][n], same dtype as S) for the loads S at minute indices t_index.
  * When every padded layer width is <= 256 (the 99-bus network's 202 -> 256 x 3 -> 198), one
- * fused kernel per 64-row tile computes it with the activations in LDS and erf from
+ * fused kernel per 128-row tile computes it with the activations in LDS and erf from
  * Abramowitz-Stegun 7.1.26 (|error| < 1.5e-7, below the BF16 rounding of the activations);
  * the workspace is then unused but still checked.  Wider networks run layer by layer. */
 int tpf_mlp_predict(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t *t_index, int64_t rows, void *V0_out,

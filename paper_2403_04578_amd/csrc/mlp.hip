@@ -211,16 +211,16 @@ __global__ void sync_kernel(const float *__restrict__ p, int64_t woff, int in, i
 
 // ---- fused inference (every padded layer width <= 256)
 //
-// One workgroup of 4 waves carries a 64-row tile from the loads to the start voltages:
-// features into LDS, every layer as BF16 MFMA products whose activations stay in LDS
-// ([64][264] BF16, two buffers), and the voltage write.  Wave w owns output neurons
-// 64 w .. 64 w + 63 (4 x 4 tiles of 16x16x32) and reads its weight fragments straight
-// from global memory, one k-step ahead; the 0.47 MB of BF16 weights stay in L2.  The
-// output layer goes to LDS as FP32 so that the voltages leave as contiguous complex
-// stores.  Nothing but S and V0 touches HBM.
-constexpr int kFusedWidth = 256, kFusedRows = 64, kHStride = 264, kYStride = 257;
-constexpr size_t kFusedLds = (size_t)2 * kFusedRows * kHStride * 2;  // >= 64 x 257 FP32 (aliased)
-static_assert(kFusedRows * 4 == 256, "one (row, calendar phase) pair per thread");
+// One workgroup of 4 waves carries a tile of 16 RT rows from the loads to the start
+// voltages: features into LDS, every layer as BF16 MFMA products whose activations stay in
+// LDS ([rows][264] BF16, updated in place between two barriers: the layer's outputs wait
+// in the accumulators until every wave has read its inputs), and the voltage write.  Wave
+// w owns output neurons 64 w .. 64 w + 63 of all rows (RT x 4 tiles of 16x16x32) and
+// streams its weight fragments from L2 two k-steps ahead; with RT = 8 each fragment feeds
+// 32 products, halving the weight traffic per row against 64-row tiles.  The output layer
+// goes through LDS as FP32, 64 rows at a time, so that the voltages leave as contiguous
+// complex stores.  Nothing but S and V0 touches HBM.
+constexpr int kFusedWidth = 256, kHStride = 264, kYStride = 257;
 
 // Complex pairs as clang vectors, so that the streamed loads and stores can carry the
 // nontemporal hint (S and V0 pass once; the weights should stay in L2).
@@ -247,44 +247,51 @@ __device__ __forceinline__ float gelu_as(float z) {
     return 0.5f * z * (1.0f + copysignf(e, z));
 }
 
-template <typename IO>
+template <int RT>
+constexpr size_t fused_lds() {
+    return (size_t)16 * RT * kHStride * 2 > (size_t)64 * kYStride * 4 ? (size_t)16 * RT * kHStride * 2
+                                                                       : (size_t)64 * kYStride * 4;
+}
+
+template <typename IO, int RT>
 __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict__ S,
                                                             const int64_t *__restrict__ t_index, int64_t rows,
                                                             const MlpView mv, double vs_re, double vs_im,
                                                             IO *__restrict__ V0) {
+    constexpr int R = 16 * RT;  // rows per workgroup
+    typedef typename Pair<IO>::T P2;
     extern __shared__ __align__(16) unsigned char smem[];
-    __bf16 *H0 = reinterpret_cast<__bf16 *>(smem);
-    __bf16 *H1 = H0 + kFusedRows * kHStride;
-    float *Yf = reinterpret_cast<float *>(smem);  // [64][257], written once H0/H1 are consumed
+    __bf16 *H = reinterpret_cast<__bf16 *>(smem);  // [R][264]
+    float *Yf = reinterpret_cast<float *>(smem);   // [64][257], once the last product has read H
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, j = lane & 15;
     const int n = mv.n, dp0 = mv.dp[0];
-    const int64_t r0 = (int64_t)blockIdx.x * kFusedRows;
+    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const int64_t valid_rows = rows - r0 < R ? rows - r0 : R;
     // features: 50 P, 50 Q, then the calendar phases; zero padding and zero rows past the
-    // end.  The tile's loads are one contiguous block of 64 n complex values: each thread
-    // issues 8 independent loads before converting any, so HBM latency is paid per chunk.
-    // Element e = 256 i + tid of the block is (row e / n, bus e % n), tracked incrementally.
+    // end.  The tile's loads are one contiguous block of R n complex values; each thread
+    // issues 16 independent loads before converting any.  Element e = 256 i + tid is
+    // (row e / n, bus e % n), tracked incrementally.
     {
-        typedef typename Pair<IO>::T P2;
-        const int total = kFusedRows * n;
-        const int64_t valid = (rows - r0) * (int64_t)n;
+        const int total = R * n;
+        const int64_t valid = valid_rows * (int64_t)n;
         const P2 *src = reinterpret_cast<const P2 *>(S) + r0 * n;
-        int r = tid / n, b = tid - (tid / n) * n;  // position of element tid
-        const int dr = 256 / n, db = 256 - dr * n;   // step of 256 elements
-        for (int e0 = tid; e0 < total; e0 += 256 * 8) {
-            P2 v[8];
+        int r = tid / n, b = tid - (tid / n) * n;
+        const int dr = 256 / n, db = 256 - dr * n;
+        for (int e0 = tid; e0 < total; e0 += 256 * 16) {
+            P2 v[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 const int e = e0 + 256 * u;
                 v[u] = P2{0, 0};
                 if (e < total && e < valid) v[u] = __builtin_nontemporal_load(src + e);
             }
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
+            for (int u = 0; u < 16; ++u) {
                 if (e0 + 256 * u < total) {
-                    H0[r * kHStride + b] = (__bf16)(kFeatScale * (float)v[u].x);
-                    H0[r * kHStride + n + b] = (__bf16)(kFeatScale * (float)v[u].y);
+                    H[r * kHStride + b] = (__bf16)(kFeatScale * (float)v[u].x);
+                    H[r * kHStride + n + b] = (__bf16)(kFeatScale * (float)v[u].y);
                 }
                 r += dr;
                 b += db;
@@ -294,36 +301,35 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
                 }
             }
         }
-    }
-    // calendar phases (one (row, phase) pair per thread) and zero padding up to dp0
-    {
-        const int r = tid >> 2, f = 2 * n + (tid & 3);
-        float v = 0.0f;
-        if (r0 + r < rows) {
-            const int64_t t = t_index[r0 + r];
-            const double mod = (double)(t % 1440) / 1440.0;
-            const double day = (double)((t / 1440) % 365) / 365.0;
-            const double ang = 2.0 * M_PI * (f < 2 * n + 2 ? mod : day);
-            v = (float)(((f - 2 * n) & 1) ? cos(ang) : sin(ang));
+        // calendar phases (one (row, phase) pair per thread per pass) and zero padding
+        for (int p = tid; p < 4 * R; p += 256) {
+            const int rr = p >> 2, f = 2 * n + (p & 3);
+            float v = 0.0f;
+            if (rr < valid_rows) {
+                const int64_t t = t_index[r0 + rr];
+                const double mod = (double)(t % 1440) / 1440.0;
+                const double day = (double)((t / 1440) % 365) / 365.0;
+                const double ang = 2.0 * M_PI * (f < 2 * n + 2 ? mod : day);
+                v = (float)(((f - 2 * n) & 1) ? cos(ang) : sin(ang));
+            }
+            H[rr * kHStride + f] = (__bf16)v;
         }
-        H0[r * kHStride + f] = (__bf16)v;
         for (int c = 2 * n + 4 + (tid & 63); c < dp0; c += 64)
-            for (int rr = tid >> 6; rr < kFusedRows; rr += 4) H0[rr * kHStride + c] = (__bf16)0.0f;
+            for (int rr = tid >> 6; rr < R; rr += 4) H[rr * kHStride + c] = (__bf16)0.0f;
     }
     __syncthreads();
-    __bf16 *hin = H0, *hout = H1;
     for (int l = 0; l <= mv.L; ++l) {
         const int K = mv.dp[l], N = mv.dp[l + 1];
         const int n0 = 64 * wave;
         const bool mine = n0 < N;
         const bool last = l == mv.L;
-        f4 acc[4][4];
+        f4 acc[RT][4];
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < RT; ++a)
 #pragma unroll
             for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
         if (mine) {
-            // weight fragments stream from L2 through a ring of four register sets, three
+            // weight fragments stream from L2 through a ring of three register sets, two
             // k-steps ahead of the products that use them (K <= 256: at most 8 k-steps)
             const __bf16 *Wl = mv.W[l] + (int64_t)(n0 + j) * K + 8 * g;
             const int ks = K / 32;
@@ -331,69 +337,76 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
 #pragma unroll
                 for (int b = 0; b < 4; ++b) w[b] = *reinterpret_cast<const b8 *>(Wl + (int64_t)16 * b * K + k0);
             };
-            b8 w[4][4];
+            b8 w[3][4];
 #pragma unroll
-            for (int st = 0; st < 3; ++st)
+            for (int st = 0; st < 2; ++st)
                 if (st < ks) ldw(w[st], 32 * st);
 #pragma unroll
             for (int st = 0; st < kFusedWidth / 32; ++st) {
                 if (st < ks) {
-                    if (st + 3 < ks) ldw(w[(st + 3) & 3], 32 * (st + 3));
-                    b8 af[4];
+                    if (st + 2 < ks) ldw(w[(st + 2) % 3], 32 * (st + 2));
 #pragma unroll
-                    for (int a = 0; a < 4; ++a)
-                        af[a] = *reinterpret_cast<const b8 *>(hin + (16 * a + j) * kHStride + 32 * st + 8 * g);
-#pragma unroll
-                    for (int a = 0; a < 4; ++a)
+                    for (int a = 0; a < RT; ++a) {
+                        const b8 af = *reinterpret_cast<const b8 *>(H + (16 * a + j) * kHStride + 32 * st + 8 * g);
 #pragma unroll
                         for (int b = 0; b < 4; ++b)
-                            acc[a][b] =
-                                __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[a], w[st & 3][b], acc[a][b], 0, 0, 0);
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w[st % 3][b], acc[a][b], 0, 0, 0);
+                    }
                 }
             }
         }
-        if (last) __syncthreads();  // every wave is done with hin: the FP32 staging overwrites it
-        if (mine) {
-            const float *bias = mv.b[l];
+        __syncthreads();  // every wave has read this layer's inputs
+        const float *bias = mv.b[l];
+        if (!last) {
+            if (mine) {
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int col = n0 + 16 * b + j;
-                const float bc = bias[col];
+                for (int b = 0; b < 4; ++b) {
+                    const int col = n0 + 16 * b + j;
+                    const float bc = bias[col];
 #pragma unroll
-                for (int a = 0; a < 4; ++a)
+                    for (int a = 0; a < RT; ++a)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = 16 * a + 4 * g + r;
-                        const float v = acc[a][b][r] + bc;
-                        if (last)
-                            Yf[row * kYStride + col] = v;
-                        else
-                            hout[row * kHStride + col] = (__bf16)gelu_as(v);  // padding: W, b = 0 -> 0
-                    }
+                        for (int r = 0; r < 4; ++r)  // padding: W, b = 0 -> gelu(0) = 0
+                            H[(16 * a + 4 * g + r) * kHStride + col] = (__bf16)gelu_as(acc[a][b][r] + bc);
+                }
             }
+            __syncthreads();
+            continue;
         }
-        __syncthreads();
-        __bf16 *tmp = hin;
-        hin = hout;
-        hout = tmp;
-    }
-    {
-        typedef typename Pair<IO>::T P2;
+        // output layer: 64 rows at a time through the FP32 staging, then contiguous stores
         P2 *dst = reinterpret_cast<P2 *>(V0) + r0 * n;
-        const int64_t valid = (rows - r0) * (int64_t)n;
         const double inv_scale = 1.0 / kOutScale;
-        int r = tid / n, b = tid - (tid / n) * n;
-        const int dr = 256 / n, db = 256 - dr * n;
-        for (int e = tid; e < kFusedRows * n && e < valid; e += 256) {
-            const P2 o = P2{(IO)(vs_re + (double)Yf[r * kYStride + b] * inv_scale),
-                            (IO)(vs_im + (double)Yf[r * kYStride + n + b] * inv_scale)};
-            __builtin_nontemporal_store(o, dst + e);
-            r += dr;
-            b += db;
-            if (b >= n) {
-                b -= n;
-                r += 1;
+#pragma unroll
+        for (int half = 0; half < RT / 4; ++half) {
+            if (mine) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int col = n0 + 16 * b + j;
+                    const float bc = bias[col];
+#pragma unroll
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            Yf[(16 * a + 4 * g + r) * kYStride + col] = acc[4 * half + a][b][r] + bc;
+                }
             }
+            __syncthreads();
+            const int64_t rows_here = valid_rows - 64 * half;
+            const int64_t valid = (rows_here < 64 ? rows_here : 64) * (int64_t)n;
+            int r = tid / n, b = tid - (tid / n) * n;
+            const int dr = 256 / n, db = 256 - dr * n;
+            for (int e = tid; e < 64 * n && e < valid; e += 256) {
+                const P2 o = P2{(IO)(vs_re + (double)Yf[r * kYStride + b] * inv_scale),
+                                (IO)(vs_im + (double)Yf[r * kYStride + n + b] * inv_scale)};
+                __builtin_nontemporal_store(o, dst + (int64_t)64 * half * n + e);
+                r += dr;
+                b += db;
+                if (b >= n) {
+                    b -= n;
+                    r += 1;
+                }
+            }
+            __syncthreads();  // the staging is reused by the next 64 rows
         }
     }
 }
@@ -743,21 +756,23 @@ extern "C" int tpf_mlp_predict(tpf_mlp M, const void *S, int32_t dtype, const in
         for (int l = 0; l < M->layers + 2; ++l) mv.dp[l] = M->dp[l];
         mv.L = M->layers;
         mv.n = M->n;
-        const unsigned blocks = (unsigned)((rows + kFusedRows - 1) / kFusedRows);
+        constexpr int RT = 8;
+        constexpr size_t lds = fused_lds<RT>();
+        const unsigned blocks = (unsigned)((rows + 16 * RT - 1) / (16 * RT));
         if (dtype == TPF_C128) {
-            auto k = predict_fused_kernel<double>;
-            if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds) !=
+            auto k = predict_fused_kernel<double, RT>;
+            if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
                 hipSuccess)
                 return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
-            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), kFusedLds, st, (const double *)S, t_index, rows, mv,
-                               M->vs_re, M->vs_im, (double *)V0_out);
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, (const double *)S, t_index, rows, mv, M->vs_re,
+                               M->vs_im, (double *)V0_out);
         } else {
-            auto k = predict_fused_kernel<float>;
-            if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kFusedLds) !=
+            auto k = predict_fused_kernel<float, RT>;
+            if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
                 hipSuccess)
                 return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
-            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), kFusedLds, st, (const float *)S, t_index, rows, mv,
-                               M->vs_re, M->vs_im, (float *)V0_out);
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, (const float *)S, t_index, rows, mv, M->vs_re,
+                               M->vs_im, (float *)V0_out);
         }
         return last_launch("MLP fused predict");
     }
