@@ -96,12 +96,14 @@ struct ColState {
     int it, ph, want, wait;
 };
 
-template <int TPW, int NW, int KTL, int MODE, int CG, typename IO>
+// PF (FP16 form only): 1 = the rows of S of each batch are staged in LDS, the next batch's
+// copied while the current one sweeps; 2 = the rows of V0 as well.
+template <int TPW, int NW, int KTL, int MODE, int CG, int PF, typename IO>
 __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const float *__restrict__ A32,
     const uint16_t *__restrict__ Alow, const uint16_t *__restrict__ Alo, const double *__restrict__ wv, int n,
-    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue, int use_pf) {
+    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue) {
     using L = LowOps<MODE>;
     typedef typename L::frag frag;
     typedef typename L::quad quad;
@@ -110,24 +112,27 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     constexpr bool kF32Refine = !kSplit;
     constexpr bool kScaled = MODE == TPF_MODE_MIXED_FP16;  // FP16 operands need a power-of-two scale
     constexpr int NC = 16 * CG;
+    constexpr bool kPfS = kSplit && PF >= 1, kPfV = kSplit && PF >= 2;
     constexpr int NT = NW * 64;
     constexpr int KPL = 32 * KTL + 8;
     const int KP32 = 16 * MT + 4;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    float *B32 = reinterpret_cast<float *>(smem);                                     // [NC][KP32]
-    uint16_t *Bh = reinterpret_cast<uint16_t *>(B32 + NC * KP32);                       // [NC][KPL]
+    float *B32 = reinterpret_cast<float *>(smem);                                     // [NC][KP32] (FP32 refine)
+    uint16_t *Bh = reinterpret_cast<uint16_t *>(B32 + (kF32Refine ? NC * KP32 : 0));  // [NC][KPL]
     uint16_t *Bl = Bh + (kMixed ? NC * KPL : 0);                                      // [NC][KPL]
-    f4 *Sx = reinterpret_cast<f4 *>(Bl + (kSplit ? NC * KPL : 0));                    // [CG*TPW][NT]
-    float *rmax = reinterpret_cast<float *>(Sx + CG * TPW * NT);                      // [2][2][NC]
+    f4 *Sx = reinterpret_cast<f4 *>(Bl + (kSplit ? NC * KPL : 0));                    // [CG][MT][64]
+    float *rmax = reinterpret_cast<float *>(Sx + CG * MT * 64);                       // [2][2][NC]
     int *rbad = reinterpret_cast<int *>(rmax + 4 * NC);                               // [2][NC]
     float *rsm = reinterpret_cast<float *>(rbad + 2 * NC);                            // [NC] max |S|
     int *rok = reinterpret_cast<int *>(rsm + NC);                                     // [NC] guard
     ColState *cs = reinterpret_cast<ColState *>(rok + NC);                            // [2][NC]
-    unsigned long long *qb = reinterpret_cast<unsigned long long *>(cs + 2 * NC);
-    double *wl = reinterpret_cast<double *>(qb + 2);                                  // [2][8 MT] w
-    // S of the next batch, copied from HBM into LDS (no registers) while this batch sweeps
+    unsigned long long *qb = reinterpret_cast<unsigned long long *>(cs + 2 * NC);     // [3] batch claims
+    double *wl = reinterpret_cast<double *>(qb + 4);                                  // [2][8 MT] w
+    // S (and V0) of the next batch, copied from HBM into LDS (no registers) while this
+    // batch sweeps
     IO *Spf = reinterpret_cast<IO *>(wl + 16 * MT);                                   // [NC][n][2]
+    IO *Vpf = Spf + (size_t)NC * n * 2;                                               // [NC][n][2]
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -136,7 +141,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     const int tw = (wave + blockIdx.x) % NW;
     const int nv = (MT - tw + NW - 1) / NW;
 
-    for (int e = tid; e < NC * KP32; e += NT) B32[e] = 0.0f;
+    for (int e = tid; e < (kF32Refine ? NC * KP32 : 0); e += NT) B32[e] = 0.0f;
     for (int e = tid; e < (kMixed ? NC * KPL * (kSplit ? 2 : 1) : 0); e += NT) Bh[e] = 0;
     for (int e = tid; e < 4 * NC; e += NT) rmax[e] = 0.0f;
     for (int e = tid; e < 2 * NC; e += NT) rbad[e] = 0;
@@ -191,7 +196,8 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
         for (int c = 0; c < CG; ++c) {
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
-                const f4 In = inject(Sx[(c * TPW + q) * NT + tid], Wq[q], U[c][q], ks[c]);
+                const f4 In = inject(q < nv ? Sx[(c * MT + tw + NW * q) * 64 + lane] : f4{0, 0, 0, 0}, Wq[q],
+                                     U[c][q], ks[c]);
                 if (q < nv) {
                     const f4 bv = dif[c] ? In - Ip[c][q] : In;
                     const int t = tw + NW * q;
@@ -223,20 +229,26 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     };
 
     // Starts copying the S rows of batch `nb` (NC consecutive columns, contiguous in HBM)
-    // into Spf: each wavefront moves 1 KB per instruction straight into LDS.
+    // into Spf, and its V0 rows into Vpf when kPfV: each wavefront moves 1 KB per
+    // instruction straight into LDS.  Only whole batches are copied (a multiple of 16
+    // bytes); a partial last batch reads HBM directly.
     auto prefetch = [&](unsigned long long nb) {
-        if (nb >= (unsigned long long)tau) return;
-        const long long cols = (long long)tau - (long long)nb < NC ? (long long)tau - (long long)nb : NC;
-        const long long bytes = cols * n * 2 * (long long)sizeof(IO);
-        const char *src = reinterpret_cast<const char *>(S + 2 * (long long)nb * n);
-        char *dst = reinterpret_cast<char *>(Spf);
-        for (long long off = (long long)wave * 1024; off < bytes; off += (long long)NW * 1024) {
-            if (off + 16 * lane < bytes)
-                __builtin_amdgcn_global_load_lds(src + off + 16 * lane,
-                                                 (__attribute__((address_space(3))) void *)(dst + off), 16, 0, 0);
+        if (nb + NC > (unsigned long long)tau) return;
+        const long long bytes = (long long)NC * n * 2 * (long long)sizeof(IO);
+#pragma unroll
+        for (int arr = 0; arr < 2; ++arr) {
+            if (arr == 1 && !kPfV) break;
+            const char *src = reinterpret_cast<const char *>((arr ? V0 : S) + 2 * (long long)nb * n);
+            char *dst = reinterpret_cast<char *>(arr ? Vpf : Spf);
+            for (long long off = (long long)wave * 1024; off < bytes; off += (long long)NW * 1024) {
+                if (off + 16 * lane < bytes)
+                    __builtin_amdgcn_global_load_lds(src + off + 16 * lane,
+                                                     (__attribute__((address_space(3))) void *)(dst + off), 16, 0, 0);
+            }
         }
     };
-    bool from_pf = false;  // this refill's S is already in Spf
+    bool from_pf = false;  // this refill's batch was claimed ahead and its rows copied
+    int slot = 1;          // qb[slot]: the batch whose rows are being copied
     auto refill = [&]() -> bool {
         if (tid < NC) {
             rsm[tid] = 0.0f;
@@ -245,8 +257,28 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
         if (tid == 0 && !from_pf) qb[0] = atomicAdd(queue, (unsigned long long)NC);
         if (from_pf) __builtin_amdgcn_s_waitcnt(0x0f70);  // vmcnt(0): this wavefront's copies landed
         __syncthreads();
-        const unsigned long long base = from_pf ? qb[1] : qb[0];
+        const unsigned long long base = from_pf ? qb[slot] : qb[0];
         if (base >= (unsigned long long)tau) return false;
+        if constexpr (kPfS) {
+            if (!(from_pf && base + NC <= (unsigned long long)tau)) {
+                // the first batch and a partial last one were not copied ahead: copy their
+                // rows now (8-byte units, coalesced), so that every batch reads LDS below
+                const long long cols = (long long)tau - (long long)base < NC ? (long long)tau - (long long)base : NC;
+                const long long units = cols * n * 2 * (long long)sizeof(IO) / 8;
+#pragma unroll
+                for (int arr = 0; arr < (kPfV ? 2 : 1); ++arr) {
+                    const unsigned long long *src =
+                        reinterpret_cast<const unsigned long long *>((arr ? V0 : S) + 2 * (long long)base * n);
+                    unsigned long long *dst = reinterpret_cast<unsigned long long *>(arr ? Vpf : Spf);
+                    for (long long e = tid; e < units; e += NT) dst[e] = src[e];
+                }
+                __syncthreads();
+            }
+        }
+        // claim the batch after this one now; the atomic's latency overlaps the loads below
+        unsigned long long next = (unsigned long long)tau;
+        if (kPfS && tid == 0 && base + NC < (unsigned long long)tau)
+            next = atomicAdd(queue, (unsigned long long)NC);
 #pragma unroll
         for (int c = 0; c < CG; ++c) {
             const long long cc = (long long)base + 16 * c + j;
@@ -261,12 +293,15 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
                         if (b0 + h < n) {
-                            if (from_pf)
+                            if constexpr (kPfS)
                                 ldc(Spf + 2 * ((16 * c + j) * n + b0 + h), s[2 * h], s[2 * h + 1]);
                             else
                                 ldc(S + 2 * (col[c] * n + b0 + h), s[2 * h], s[2 * h + 1]);
                             if (V0) {
-                                ldc(V0 + 2 * (col[c] * n + b0 + h), v[2 * h], v[2 * h + 1]);
+                                if constexpr (kPfV)
+                                    ldc(Vpf + 2 * ((16 * c + j) * n + b0 + h), v[2 * h], v[2 * h + 1]);
+                                else
+                                    ldc(V0 + 2 * (col[c] * n + b0 + h), v[2 * h], v[2 * h + 1]);
                                 const double m2 = v[2 * h] * v[2 * h] + v[2 * h + 1] * v[2 * h + 1];
                                 bad |= (m2 >= 0.25 && m2 <= 2.25) ? 0 : 1;
                             }
@@ -275,7 +310,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                 }
                 const f4 sv = f4{(float)s[0], (float)s[1], (float)s[2], (float)s[3]};
                 sbad |= !(fabs(s[0]) + fabs(s[1]) + fabs(s[2]) + fabs(s[3]) < HUGE_VAL);
-                Sx[(c * TPW + q) * NT + tid] = sv;
+                if (q < nv) Sx[(c * MT + tw + NW * q) * 64 + lane] = sv;
                 sm = fmaxf(sm, amax4(sv));
                 U[c][q] = f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]} - Wq[q];
             }
@@ -290,12 +325,13 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                 if (bad | sbad) atomicOr(rok + 16 * c + j, bad | (sbad << 1));
             }
         }
-        if (kSplit && use_pf && tid == 0)  // the batch after this one, whose S is copied meanwhile
-            qb[1] = base + NC >= (unsigned long long)tau ? (unsigned long long)tau
-                                                         : atomicAdd(queue, (unsigned long long)NC);
-        __syncthreads();  // column reductions complete; every wavefront is done with Spf
-        if (kSplit && use_pf) {
-            prefetch(qb[1]);
+        // The other slot: qb[slot] may still be read by a wavefront that has not passed the
+        // barrier above; the slot written here is next read after two more barriers.
+        if (kPfS && tid == 0) qb[3 - slot] = next;
+        __syncthreads();  // column reductions complete; every wavefront is done with Spf and Vpf
+        if (kPfS) {
+            slot = 3 - slot;
+            prefetch(qb[slot]);
             from_pf = true;
         }
 #pragma unroll
@@ -520,7 +556,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                                 o[1] = (IO)(wl[8 * MT + b] + (double)U[c][q][2 * h + 1]);
                             }
                         }
-                        Sx[(c * TPW + q) * NT + tid] = f4{0, 0, 0, 0};  // idle slot: zero injection
+                        Sx[(c * MT + tw + NW * q) * 64 + lane] = f4{0, 0, 0, 0};  // idle slot: zero injection
                     }
                 }
             }
@@ -548,14 +584,22 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     constexpr bool mixed = MODE != TPF_MODE_FP32, split = MODE == TPF_MODE_MIXED_FP16;
     const size_t NC = 16 * CG, NT = NW * 64;
     const size_t KPL = 32 * KTL + 8, KP32 = 16 * MT + 4;
-    const size_t lds0 = NC * KP32 * 4 + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) + (size_t)CG * TPW * NT * 16 +
-                        NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 16 + 64 + (size_t)16 * MT * 8;
-    // the next batch's S is prefetched into LDS when it fits beside the rest
-    const size_t spf = ((size_t)NC * net.n * 2 * sizeof(IO) + 1023) / 1024 * 1024;
+    const size_t lds0 = (split ? 0 : NC * KP32 * 4) + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) +
+                        (size_t)CG * MT * 64 * 16 + NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 32 + 64 +
+                        (size_t)16 * MT * 8;
+    // The next batch's S is prefetched into LDS when it fits beside the rest, and its V0
+    // too when that also fits (the copies write exactly the rows' bytes).
     // (measured: it pays in the FP16 form, not in the BF16 one, whose registers it raises)
-    const int use_pf = split && lds0 + spf <= (size_t)160 * 1024 ? 1 : 0;
-    const size_t lds = lds0 + (use_pf ? spf : 0);
-    auto kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, IO>;
+    const size_t spf = (size_t)NC * net.n * 2 * sizeof(IO);
+    const size_t cap = (size_t)160 * 1024;
+    int pf = split && lds0 + spf <= cap ? 1 : 0;
+    if (pf && V0 && lds0 + 2 * spf <= cap) pf = 2;
+    const size_t lds = lds0 + (size_t)pf * spf;
+    auto kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 0, IO>;
+    if constexpr (split) {
+        if (pf == 1) kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 1, IO>;
+        if (pf == 2) kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 2, IO>;
+    }
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
     int per_cu = 0;
@@ -567,7 +611,7 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     const long long blocks = std::min<long long>((long long)cus * per_cu, (tau + (long long)NC - 1) / (long long)NC);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.A32, MODE == TPF_MODE_MIXED_BF16 ? dn.Abf : dn.Ah, dn.Al,
-                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue, use_pf);
+                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue);
     return TPF_OK;
 }
 

@@ -103,18 +103,30 @@ def test_fast_forms_edge_columns(gpu, mode):
     assert np.abs(V.cpu().numpy()[[0, 3]] - ref.V).max() < 2e-6  # k = 0.61: bound k/(1-k) tol
 
 
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
 @pytest.mark.parametrize("mode", MODES)
-def test_fast_forms_warm_start(gpu, feeder100, mode):
+def test_fast_forms_warm_start(gpu, feeder100, mode, dtype):
+    """Guarded warm starts in the first batch of a workgroup (read from HBM), in later
+    batches (copied into LDS ahead of time in the FP16 form) and in the partial last one."""
     f, net, onet = feeder100
     S = W.profile_minute_year(f, steps=700, t0=5)
+    if dtype == torch.complex64:
+        S = S.astype(np.complex64).astype(np.complex128)
     ref = oracle.fpi(onet, S, 1e-10, 200)
     rng = np.random.default_rng(2)
     V0 = ref.V + 3e-5 * (rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape))
-    V0[10, 3] = np.nan  # guarded: this column starts flat
-    Vw, iw, sw = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode=mode, V0=_dev(V0, gpu))
-    _check(onet, S, Vw, iw, sw, ref=ref)
-    Vf, i_f, sf = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode=mode)
-    assert float(iw.float().mean()) < float(i_f.float().mean())
+    V0[10, 3] = np.nan  # guarded: these columns start flat
+    V0[333, 50] = 3.0
+    V0[690, 98] = 0.1
+    Vw, iw, sw = tpf.solve_timeseries(net, _dev(S, gpu, dtype), tol=1e-6, max_iter=100, mode=mode,
+                                      V0=_dev(V0, gpu, dtype))
+    _check(onet, S, Vw, iw, sw, bound=FAST_BOUND + (1e-7 if dtype == torch.complex64 else 0.0), ref=ref)
+    Vf, i_f, sf = tpf.solve_timeseries(net, _dev(S, gpu, dtype), tol=1e-6, max_iter=100, mode=mode)
+    iw, i_f = iw.cpu().numpy(), i_f.cpu().numpy()
+    assert iw.mean() < i_f.mean()
+    if mode == "fp32":  # a guarded column runs exactly as from the flat start
+        for c in (10, 333, 690):
+            assert iw[c] == i_f[c], c
 
 
 @pytest.mark.parametrize("mode", MODES)
