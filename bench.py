@@ -105,7 +105,7 @@ def ingest_pmc(fetch_dir: str, write_dir: str):
     out = {"calibration": {"kernel": calib_f, "fetch_kib": fetch[calib_f], "write_kib": write[calib_w],
                            "fetch_scale": cf, "write_scale": cw}}
 
-    def mixed(mode):  # fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, IO>
+    def mixed(mode):  # fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, PF, IO>
         return lambda k: (targs(k, "fpi_mixed_kernel") or [""] * 4)[3] == mode
     for key, match in (("fp64/year100", lambda k: "fpi_f64_kernel<" in k),
                        ("mixed_fp16+warm/year100", mixed("3")),
