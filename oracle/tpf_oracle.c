@@ -21,6 +21,14 @@
  *                    stop when max_i |V'_i - V_i| < tol or after max_iter sweeps.
  *   oracle_mismatch  Power balance of Eq. (1): m = S + V .* conj(Y_ds v_s + Y_dd V),
  *                    reported as max_i |m_i| per column.
+ *   oracle_fpi_zip   Eq. (2) with a ZIP load model whose constant-impedance share is
+ *                    zero: per column A = diag(alpha_P .* s*), B = Y_dd,
+ *                    c = Y_ds v_s + alpha_I .* s*, F = -B^-1 A, w = -B^-1 c, then
+ *                    Algorithm 1 with v <- F conj(v)^-1 + w.
+ *   oracle_mismatch_zip  The power balance of the same loads: a load draws
+ *                    v .* conj(i) with i = alpha_I .* s* + alpha_P .* s* ./ conj(v),
+ *                    i.e. s .* (alpha_P + alpha_I .* v), so
+ *                    m = S .* (alpha_P + alpha_I .* V) + V .* conj(Y_ds v_s + Y_dd V).
  *
  * Readings where the paper is silent or garbled (listed in the design notes):
  *   - the stopping measure is the complex modulus of the voltage step,
@@ -194,6 +202,94 @@ void oracle_mismatch(int n, const double complex *Ydd, const double complex *Yds
             double complex acc = Yds[i] * vs;
             for (int j = 0; j < n; ++j) acc += Ydd[(size_t)i * n + j] * v[j];
             double complex m = S[col * n + i] + v[i] * conj(acc);
+            double a = cabs(m);
+            if (!(a <= worst)) worst = a; /* NaN propagates */
+        }
+        mmax[col] = worst;
+    }
+}
+
+/* Eq. (2) for ZIP loads with alpha_Z = 0, one column at a time.  Z = -Y_dd^-1 is
+ * -B^-1 (B = Y_dd when alpha_Z = 0); each column forms its own F = Z diag(alpha_P .* s*)
+ * and w = Z (Y_ds v_s + alpha_I .* s*) and iterates v <- F conj(v)^-1 + w with the same
+ * start, stopping rule and outputs as oracle_fpi.  alpha_i, alpha_p: [n] per PQ bus. */
+void oracle_fpi_zip(int n, const double complex *Z, const double complex *Yds, double vs_re,
+                    double vs_im, const double *alpha_i, const double *alpha_p, int64_t tau,
+                    const double complex *S, double tol, int max_iter,
+                    const double complex *V0, double complex *V, int32_t *iters,
+                    int8_t *status, double *dlast)
+{
+    double complex vs = vs_re + I * vs_im;
+#pragma omp parallel
+    {
+        double complex *F = malloc(sizeof(double complex) * (size_t)n * n);
+        double complex *wc = malloc(sizeof(double complex) * n);
+        double complex *cc = malloc(sizeof(double complex) * n);
+        double complex *cur = malloc(sizeof(double complex) * n);
+        double complex *nxt = malloc(sizeof(double complex) * n);
+        double complex *rec = malloc(sizeof(double complex) * n);
+#pragma omp for schedule(static)
+        for (int64_t col = 0; col < tau; ++col) {
+            const double complex *s = S + col * n;
+            /* F = -B^-1 A = Z diag(alpha_P .* s*) */
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j)
+                    F[(size_t)i * n + j] = Z[(size_t)i * n + j] * (alpha_p[j] * conj(s[j]));
+            /* c = Y_ds v_s + alpha_I .* s*,  w = -B^-1 c = Z c */
+            for (int i = 0; i < n; ++i) cc[i] = Yds[i] * vs + alpha_i[i] * conj(s[i]);
+            for (int i = 0; i < n; ++i) {
+                double complex acc = 0.0;
+                for (int j = 0; j < n; ++j) acc += Z[(size_t)i * n + j] * cc[j];
+                wc[i] = acc;
+            }
+            for (int i = 0; i < n; ++i) cur[i] = V0 ? V0[col * n + i] : 1.0;
+            double d = INFINITY;
+            int k = 0, bad = 0;
+            while (d >= tol && k < max_iter) {
+                /* conj(v)^-1, element-wise */
+                for (int i = 0; i < n; ++i) rec[i] = 1.0 / conj(cur[i]);
+                /* v' = F conj(v)^-1 + w */
+                for (int i = 0; i < n; ++i) {
+                    double complex acc = 0.0;
+                    for (int j = 0; j < n; ++j) acc += F[(size_t)i * n + j] * rec[j];
+                    nxt[i] = acc + wc[i];
+                }
+                d = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    if (!isfinite(creal(nxt[i])) || !isfinite(cimag(nxt[i]))) bad = 1;
+                    double e = cabs(nxt[i] - cur[i]);
+                    if (e > d) d = e;
+                }
+                memcpy(cur, nxt, sizeof(double complex) * n);
+                ++k;
+                if (bad) break;
+            }
+            memcpy(V + col * n, cur, sizeof(double complex) * n);
+            iters[col] = k;
+            status[col] = bad ? ST_NONFINITE : (d < tol ? ST_CONVERGED : ST_MAX_ITER);
+            if (dlast) dlast[col] = bad ? NAN : d;
+        }
+        free(F); free(wc); free(cc); free(cur); free(nxt); free(rec);
+    }
+}
+
+/* Power balance of ZIP loads (alpha_Z = 0): m = S .* (alpha_P + alpha_I .* V)
+ * + V .* conj(Y_ds v_s + Y_dd V); max_i |m_i| per column. */
+void oracle_mismatch_zip(int n, const double complex *Ydd, const double complex *Yds,
+                         double vs_re, double vs_im, const double *alpha_i,
+                         const double *alpha_p, int64_t tau, const double complex *S,
+                         const double complex *V, double *mmax)
+{
+    double complex vs = vs_re + I * vs_im;
+#pragma omp parallel for schedule(static)
+    for (int64_t col = 0; col < tau; ++col) {
+        const double complex *v = V + col * n;
+        double worst = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double complex acc = Yds[i] * vs;
+            for (int j = 0; j < n; ++j) acc += Ydd[(size_t)i * n + j] * v[j];
+            double complex load = S[col * n + i] * (alpha_p[i] + alpha_i[i] * v[i]);
+            double complex m = load + v[i] * conj(acc);
             double a = cabs(m);
             if (!(a <= worst)) worst = a; /* NaN propagates */
         }

@@ -323,3 +323,74 @@ def test_singular_and_invalid_networks():
     with pytest.raises(oracle.OracleError) as e:
         oracle.build_network(3, [0, 1], [1, 2], [0.01, 0.0], [0.01, 0.0])
     assert e.value.code == -1
+
+
+# ----------------------------------------------------------------------------- Eq. (2), ZIP loads
+
+def _zip_numpy_balance(net, S, V, ai, ap):
+    """Power balance of ZIP loads written independently of the oracle: a load draws
+    s (alpha_P + alpha_I v), the network delivers -v conj(Y_ds v_s + Y_dd v)."""
+    inj = net.Yds[None, :] * net.vs + V @ net.Ydd.T
+    return np.abs(S * (ap + ai * V) + V * np.conj(inj)).max(axis=1)
+
+
+def test_zip_constant_power_reduces_to_algorithm1():
+    f = W.make_feeder(30)
+    net = oracle.build_feeder(f)
+    S = W.profile_daily96(f)
+    a = oracle.fpi(net, S, 1e-12, 100)
+    b = oracle.fpi_zip(net, S, 0.0, 1.0, 1e-12, 100)
+    assert np.array_equal(a.iters, b.iters) and np.array_equal(a.status, b.status)
+    assert np.abs(a.V - b.V).max() < 1e-13
+
+
+def test_zip_constant_current_is_one_linear_solve():
+    """alpha_P = 0: F = 0, the map is constant, so the first sweep lands on
+    v = -Y_dd^-1 (Y_ds v_s + alpha_I s*) (a library solve, not the oracle's inverse)
+    and the second sweep does not move."""
+    f = W.make_feeder(40)
+    net = oracle.build_feeder(f)
+    S = W.profile_daily96(f, steps=8)
+    res = oracle.fpi_zip(net, S, 1.0, 0.0, 1e-12, 10)
+    assert np.all(res.iters == 2) and np.all(res.status == oracle.ST_CONVERGED)
+    rhs = -(net.Yds[None, :] * net.vs + np.conj(S))
+    Vs = np.linalg.solve(net.Ydd, rhs.T).T
+    assert np.abs(res.V - Vs).max() < 1e-12
+    assert _zip_numpy_balance(net, S, res.V, 1.0, 0.0).max() < 1e-11
+
+
+def test_zip_twobus_closed_form():
+    """One PQ bus behind z: v = v_s - z (alpha_P s*/v* + alpha_I s*).  Multiplying by v*
+    gives the constant-power two-bus problem with source u = v_s - z alpha_I s* and load
+    alpha_P s, whose high root is closed-form."""
+    z, vs = 0.05 + 0.08j, 1.02 + 0.01j
+    net = _twobus_net(z, vs)
+    for s, ai, ap in [(0.9 + 0.4j, 0.3, 0.7), (1.5 + 0.2j, 0.8, 0.2), (0.6 - 0.3j, 0.5, 0.5)]:
+        res = oracle.fpi_zip(net, np.array([[s]]), ai, ap, 1e-14, 500)
+        assert res.status[0] == oracle.ST_CONVERGED
+        u = vs - z * ai * np.conj(s)
+        vh, _ = twobus_roots(z, u, ap * s)
+        assert abs(res.V[0, 0] - vh) < 1e-12, (s, ai, ap)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_zip_mixed_shares_satisfy_power_balance(seed):
+    f = W.make_feeder(60, load_scale=3.0)
+    net = oracle.build_feeder(f)
+    S = W.profile_daily96(f, steps=12)
+    rng = np.random.default_rng(seed)
+    ai = rng.uniform(0.0, 1.0, net.n)
+    ap = 1.0 - ai
+    res = oracle.fpi_zip(net, S, ai, ap, 1e-13, 200)
+    assert np.all(res.status == oracle.ST_CONVERGED)
+    bal = _zip_numpy_balance(net, S, res.V, ai, ap)
+    assert bal.max() < 1e-11
+    assert oracle.mismatch_zip(net, S, res.V, ai, ap).max() < 1e-11
+    # away from the solution the two formulas agree to rounding
+    Vp = res.V + 1e-3 * (rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape))
+    assert np.allclose(oracle.mismatch_zip(net, S, Vp, ai, ap), _zip_numpy_balance(net, S, Vp, ai, ap),
+                       rtol=1e-10, atol=1e-13)
+    # the constant-current share moves the solution, and the constant-power mismatch sees it
+    cp = oracle.fpi(net, S, 1e-13, 200)
+    assert np.abs(cp.V - res.V).max() > 1e-5
+    assert oracle.mismatch(net, S, res.V).max() > 1e-6
