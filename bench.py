@@ -182,10 +182,11 @@ def _cpu_model() -> str:
 
 
 def bench_other(args):
-    """The other two workloads of the method, every form without the warm start (its
+    """The other workloads of the method, every form without the warm start (its
     network is the 100-bus one): the 300-bus scenario tensor (complex64, built on the
-    device from its factors) and the 1,000-bus feeder over 200,000 minutes.  Prints one
-    JSON line."""
+    device from its factors), the 1,000-bus feeder over 200,000 minutes, and the 100-bus
+    year with ZIP loads (Eq. (2), FP64 form, beside the same year with constant-power
+    loads).  Prints one JSON line."""
     import torch
 
     import paper_2403_04578_amd as tpf
@@ -204,6 +205,14 @@ def bench_other(args):
         del c, L, PV
         desc = "300-bus radial feeder (299 PQ), 1,000 scenarios x 8,760 hours, complex64 S"
         sample = lambda k: loads.element(np.arange(k) // 8760, np.arange(k) % 8760, np.complex128)
+    elif args.workload == "zip100":
+        f = W.make_feeder(100)
+        S_host = W.profile_minute_year(f)
+        S = torch.from_numpy(S_host).to(dev)
+        ai, ap = W.zip_shares(f.n_bus - 1)
+        desc = ("100-bus radial feeder (99 PQ), ZIP loads (per bus constant-current share U(0, 0.6), the rest "
+                "constant power), 525,600 one-minute steps, complex128 S")
+        sample = lambda k: S_host[:k]
     else:
         f = W.make_feeder(1000)
         S_host = W.profile_minute_year(f, steps=200_000)
@@ -213,11 +222,14 @@ def bench_other(args):
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     T, n = S.shape
-    net = tpf.Network.from_feeder(f)
+    zip_loads = args.workload == "zip100"
+    net = tpf.Network.from_feeder(f, alpha_i=ai, alpha_p=ap) if zip_loads else tpf.Network.from_feeder(f)
     stream = torch.cuda.current_stream(dev)
     esz = S.element_size()
     forms = {}
-    for mode in ("fp64", "fp32", "mixed_bf16", "mixed_fp16"):
+    runs = [("fp64", "fp64", net), ("fp64_constant_power", "fp64", tpf.Network.from_feeder(f))] if zip_loads else \
+        [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16")]
+    for key, mode, net in runs:
         out = tpf.alloc_outputs(net, S, mode, mismatch=True)
         kout = (out[0], out[1], out[2], None, out[4])  # same buffers, no mismatch pass
         for _ in range(args.warmup):
@@ -238,7 +250,7 @@ def bench_other(args):
         sweeps = float(it.sum())
         k_ms = a.elapsed_time(b)
         flops = 8.0 * n * n * sweeps
-        forms[mode] = {"ms_per_step": 1e3 * wall, "solve_ms": k_ms, "power_flows_per_s": T / wall,
+        forms[key] = {"ms_per_step": 1e3 * wall, "solve_ms": k_ms, "power_flows_per_s": T / wall,
                        "sweeps_mean": sweeps / T, "converged": int((out[2] == tpf.ST_CONVERGED).sum()),
                        "max_mismatch_pu": float(out[3].max()),
                        "solve_tflops": flops / (k_ms * 1e-3) / 1e12,
@@ -248,21 +260,25 @@ def bench_other(args):
     base = forms["fp64"]
     for r in forms.values():
         r["speedup_vs_fp64"] = base["ms_per_step"] / r["ms_per_step"]
-    head = min(("mixed_fp16", "mixed_bf16"), key=lambda m: forms[m]["ms_per_step"])
+    head = "fp64" if zip_loads else min(("mixed_fp16", "mixed_bf16"), key=lambda m: forms[m]["ms_per_step"])
     rec = {"metric": f"power flows/s to 1e-6 pu, {args.workload}", "value": forms[head]["power_flows_per_s"],
            "unit": "power flows/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": forms[head]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f16" if head == "mixed_fp16" else "bf16", "data": "synthetic",
+           "vs_baseline": None, "dtype": {"mixed_fp16": "f16", "mixed_bf16": "bf16"}.get(head, "f64"),
+           "data": "synthetic",
            "config": {"workload": desc + ", tol 1e-6 pu, max 100 sweeps, + FP64 mismatch", "form": head,
                       "n_pq": n, "power_flows": T},
            "forms": forms, "setup_s": setup_s}
     if not args.no_cpu_baseline:
         import oracle
         onet = oracle.build_network(f.n_bus, f.frm, f.to, f.r, f.x, 0, f.vs)
-        k = 200 if n > 500 else 2000
+        k = 200 if n > 500 else (100_000 if zip_loads else 2000)
         Sk = sample(k)
         t0 = time.perf_counter()
-        oracle.fpi(onet, Sk, tol, max_iter)
+        if zip_loads:
+            oracle.fpi_zip(onet, Sk, ai, ap, tol, max_iter)
+        else:
+            oracle.fpi(onet, Sk, tol, max_iter)
         dt = time.perf_counter() - t0
         rec["cpu_baseline"] = {"value": k / dt, "unit": "power flows/s", "cores": oracle.num_threads(),
                                "kind": "oracle", "sample": f"first {k} columns of the workload, {dt:.1f} s"}
@@ -285,10 +301,10 @@ def main():
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
                          "--calib-copy into profiles/hbm_traffic.json and exit")
-    ap.add_argument("--workload", default="year100", choices=["year100", "tensor300", "feeder1000"],
+    ap.add_argument("--workload", default="year100", choices=["year100", "tensor300", "feeder1000", "zip100"],
                     help="year100 (default, headline): 100-bus feeder, 525,600 minutes; tensor300: 300-bus "
                          "feeder, 1,000 scenarios x 8,760 hours, complex64; feeder1000: 1,000-bus feeder, "
-                         "200,000 minutes")
+                         "200,000 minutes; zip100: the 100-bus year with ZIP loads, FP64 form")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT_TXT", "COMMAND"),
                     help="write a short text summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()

@@ -101,6 +101,25 @@ int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, cons
                       const double *r, const double *x, int32_t slack_bus, double vs_re,
                       double vs_im, tpf_network *out);
 
+/* Sec. II Eq. (2) with a ZIP load model: the same network whose loads draw, at bus q,
+ * the current alpha_I[q] s* + alpha_P[q] s* / conj(v) (constant-current and constant-power
+ * shares of the nominal power s), i.e. the power s (alpha_P + alpha_I v).  Eq. (2) then
+ * has A = diag(alpha_P s*), B = Y_dd, c = Y_ds v_s + alpha_I s*, and the sweeps compute
+ * V <- Z (alpha_P conj(S./V) + alpha_I conj(S)) + w.
+ *   alpha_z          host float64 [n] or NULL: constant-impedance shares; must be 0
+ *                    (a nonzero share makes B, hence F and w, differ per power flow:
+ *                    TPF_ERR_UNSUPPORTED)
+ *   alpha_i, alpha_p host float64 [n] per PQ bus (PQ order), finite; any values
+ *                    (they need not sum to 1)
+ * Other arguments and errors as tpf_build_network; TPF_ERR_INVALID_ARG for a NULL or
+ * non-finite share.  A ZIP network solves in TPF_MODE_FP64 (other modes return
+ * TPF_ERR_UNSUPPORTED), and its mismatch (options.mismatch_out, tpf_mismatch) is the
+ * balance of these loads: S (alpha_P + alpha_I V) + V conj(Y_ds v_s + Y_dd V). */
+int tpf_build_network_zip(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                          const double *r, const double *x, int32_t slack_bus, double vs_re, double vs_im,
+                          const double *alpha_z, const double *alpha_i, const double *alpha_p,
+                          tpf_network *out);
+
 void tpf_free_network(tpf_network net);
 
 /* Number of PQ (demand) buses n = n_bus - 1. */
@@ -140,7 +159,8 @@ int tpf_solve_tensor(tpf_network net, const void *S, int32_t dtype, int64_t n_sc
                      size_t workspace_bytes, void *stream);
 
 /* FP64 power-balance mismatch of given voltages (Eq. (1)):
- * out[c] = max_i |S_ci + V_ci conj((Y_ds v_s)_i + (Y_dd V_c)_i)|.
+ * out[c] = max_i |S_ci + V_ci conj((Y_ds v_s)_i + (Y_dd V_c)_i)|
+ * (for a ZIP network the load term S_ci is S_ci (alpha_P,i + alpha_I,i V_ci)).
  *   S, V   device [tau][n], dtype TPF_C64 or TPF_C128;  out  device float64 [tau]. */
 int tpf_mismatch(tpf_network net, const void *S, const void *V, int32_t dtype, int64_t tau,
                  double *out, void *stream);

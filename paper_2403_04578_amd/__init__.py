@@ -58,6 +58,7 @@ def load_library() -> ctypes.CDLL:
     P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     sig = {
         "tpf_build_network": (ctypes.c_int, [I32, I32, P, P, P, P, I32, D, D, ctypes.POINTER(P)]),
+        "tpf_build_network_zip": (ctypes.c_int, [I32, I32, P, P, P, P, I32, D, D, P, P, P, ctypes.POINTER(P)]),
         "tpf_free_network": (None, [P]),
         "tpf_network_n_pq": (ctypes.c_int, [P]),
         "tpf_network_get_zw": (ctypes.c_int, [P, P, P]),
@@ -93,9 +94,13 @@ def _check(rc: int):
 
 
 class Network:
-    """A feeder prepared for the sweeps: Z = -Y_dd^-1 and w (Sec. II Eqs. (1)-(2))."""
+    """A feeder prepared for the sweeps: Z = -Y_dd^-1 and w (Sec. II Eqs. (1)-(2)).
 
-    def __init__(self, n_bus: int, frm, to, r, x, slack: int = 0, vs: complex = 1.0 + 0.0j):
+    With alpha_i / alpha_p (per PQ bus, or scalars) the loads follow Eq. (2)'s ZIP model
+    with constant-current and constant-power shares (alpha_z must be zero or None)."""
+
+    def __init__(self, n_bus: int, frm, to, r, x, slack: int = 0, vs: complex = 1.0 + 0.0j,
+                 alpha_i=None, alpha_p=None, alpha_z=None):
         lib = load_library()
         self._keep = [np.ascontiguousarray(frm, np.int32), np.ascontiguousarray(to, np.int32),
                       np.ascontiguousarray(r, np.float64), np.ascontiguousarray(x, np.float64)]
@@ -103,17 +108,28 @@ class Network:
         f, t, rr, xx = self._keep
         if not (len(f) == len(t) == len(rr) == len(xx)):
             raise ValueError("branch arrays must have equal lengths")
-        rc = lib.tpf_build_network(int(n_bus), len(f), f.ctypes.data, t.ctypes.data, rr.ctypes.data,
-                                   xx.ctypes.data, int(slack), float(np.real(vs)), float(np.imag(vs)),
-                                   ctypes.byref(h))
+        self.zip = alpha_i is not None or alpha_p is not None or alpha_z is not None
+        if self.zip:
+            n = int(n_bus) - 1
+            shares = [np.ascontiguousarray(np.broadcast_to(np.asarray(a if a is not None else d, np.float64), (n,)))
+                      for a, d in ((alpha_z, 0.0), (alpha_i, 0.0), (alpha_p, 1.0))]
+            self._keep += shares
+            rc = lib.tpf_build_network_zip(int(n_bus), len(f), f.ctypes.data, t.ctypes.data, rr.ctypes.data,
+                                           xx.ctypes.data, int(slack), float(np.real(vs)), float(np.imag(vs)),
+                                           shares[0].ctypes.data, shares[1].ctypes.data, shares[2].ctypes.data,
+                                           ctypes.byref(h))
+        else:
+            rc = lib.tpf_build_network(int(n_bus), len(f), f.ctypes.data, t.ctypes.data, rr.ctypes.data,
+                                       xx.ctypes.data, int(slack), float(np.real(vs)), float(np.imag(vs)),
+                                       ctypes.byref(h))
         _check(rc)
         self._h = h
         self.n_bus = int(n_bus)
         self.n = lib.tpf_network_n_pq(h)
 
     @classmethod
-    def from_feeder(cls, feeder) -> "Network":
-        return cls(feeder.n_bus, feeder.frm, feeder.to, feeder.r, feeder.x, 0, feeder.vs)
+    def from_feeder(cls, feeder, alpha_i=None, alpha_p=None, alpha_z=None) -> "Network":
+        return cls(feeder.n_bus, feeder.frm, feeder.to, feeder.r, feeder.x, 0, feeder.vs, alpha_i, alpha_p, alpha_z)
 
     @property
     def handle(self):

@@ -84,10 +84,11 @@ __global__ void init_kernel(const IO *__restrict__ V0, const double *__restrict_
     }
 }
 
+// I = conj(S./V), or alpha_P conj(S./V) + alpha_I conj(S) for ZIP loads (aP, aI non-NULL).
 template <typename T, typename IO>
 __global__ void inject_kernel(const IO *__restrict__ S, const T *__restrict__ x, const double *__restrict__ w, int n,
                               int KP, const long long *__restrict__ act, const int *__restrict__ na, int rows,
-                              T *__restrict__ B) {
+                              const double *__restrict__ aP, const double *__restrict__ aI, T *__restrict__ B) {
     const long long total = (long long)rows * KP;
     const int nact = *na;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total / 2;
@@ -101,8 +102,14 @@ __global__ void inject_kernel(const IO *__restrict__ S, const T *__restrict__ x,
             double vr = (double)x[2 * (c * n + b)], vi = (double)x[2 * (c * n + b) + 1];
             if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
             const double inv = 1.0 / (vr * vr + vi * vi);
-            ir = (T)((sr * vr + si * vi) * inv);
-            ii = (T)((sr * vi - si * vr) * inv);
+            double jr = (sr * vr + si * vi) * inv, ji = (sr * vi - si * vr) * inv;
+            if (aP) {
+                const double ap = aP[b], ai = aI[b];
+                jr = ap * jr + ai * sr;
+                ji = ap * ji - ai * si;
+            }
+            ir = (T)jr;
+            ii = (T)ji;
         }
         B[a * KP + 2 * b] = ir;
         B[a * KP + 2 * b + 1] = ii;
@@ -631,7 +638,8 @@ static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *
     for (int sweep = 0; sweep < max_iter && na > 0; ++sweep) {
         const long long arows = (na + 63) / 64 * 64;
         hipLaunchKernelGGL((inject_kernel<T, IO>), dim3((unsigned)std::min<long long>(65536, (arows * KP / 2 + 255) / 256)),
-                           dim3(256), 0, st, (const IO *)S, x, w, n, KP, act[cur], cnt + cur, (int)arows, B);
+                           dim3(256), 0, st, (const IO *)S, x, w, n, KP, act[cur], cnt + cur, (int)arows, dn.aP,
+                           dn.aI, B);
         hipLaunchKernelGGL((gemm_kernel<T>), dim3((unsigned)(arows / 64), (unsigned)(MP / 64)), dim3(256), 0, st, A, KP,
                            B, act[cur], cnt + cur, w, n, x, dmax, badf);
         hipLaunchKernelGGL((finish_kernel<T, IO>), dim3((unsigned)((na + 3) / 4)), dim3(256), 0, st, act[cur],

@@ -1,4 +1,4 @@
-// Persistent FP64 sweep kernel for networks with up to 128 PQ buses.
+// Persistent FP64 sweep kernel for networks with up to 320 PQ buses.
 //
 // Algorithm 1 (Sec. IV-A) evaluates V <- Z conj(S ./ V) + w for every power flow
 // (column) of the reshaped load matrix until the voltage step of that column
@@ -50,13 +50,26 @@ struct SlotState {
     d4 v[TPW], s[TPW];
 };
 
-__device__ __forceinline__ void put_injection(double *Ib, int t, int lane, const d4 &vv, const d4 &ss) {
+// Writes the injection conj(S./V) of the lane's two buses 8t+g and 8t+g+4; for ZIP loads
+// (Eq. (2), alpha_Z = 0) alpha_P conj(S./V) + alpha_I conj(S), with the shares staged in
+// LDS as zl[2][8 MT] (alpha_P, then alpha_I).
+template <bool ZIP>
+__device__ __forceinline__ void put_injection(double *Ib, int t, int lane, const d4 &vv, const d4 &ss,
+                                              const double *zl, int MT) {
+    const int g = lane >> 4;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const double vr = vv[h], vi = vv[h + 2], sr = ss[h], si = ss[h + 2];
         const double inv = 1.0 / (vr * vr + vi * vi);
-        Ib[256 * t + 64 * h + lane] = (sr * vr + si * vi) * inv;        // Re conj(S/V), row 16t+g+4h
-        Ib[256 * t + 64 * (h + 2) + lane] = (sr * vi - si * vr) * inv;  // Im conj(S/V), row 16t+g+8+4h
+        double ir = (sr * vr + si * vi) * inv, ii = (sr * vi - si * vr) * inv;  // conj(S/V)
+        if constexpr (ZIP) {
+            const int b = 8 * t + g + 4 * h;
+            const double ap = zl[b], ai = zl[8 * MT + b];
+            ir = ap * ir + ai * sr;
+            ii = ap * ii - ai * si;
+        }
+        Ib[256 * t + 64 * h + lane] = ir;        // Re, row 16t+g+4h
+        Ib[256 * t + 64 * (h + 2) + lane] = ii;  // Im, row 16t+g+8+4h
     }
 }
 
@@ -113,18 +126,19 @@ __device__ __forceinline__ void sweep_product(d4 (&acc)[TPW], const double *__re
     }
 }
 
-template <int TPW, int NW, typename IO>
+template <int TPW, int NW, bool ZIP, typename IO>
 __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const double *__restrict__ A,
     const double *__restrict__ wv, int n, int MT, long long tau, double tol, int max_iter,
-    unsigned long long *__restrict__ queue) {
+    unsigned long long *__restrict__ queue, const double *__restrict__ aP, const double *__restrict__ aI) {
     extern __shared__ double lds[];
     double *Ib = lds;                                 // [16*MT][16]
     double *part = lds + 256 * MT;                    // [NW][16] partial max |dV|^2
     int *flag = reinterpret_cast<int *>(part + NW * 16);  // [NW][16] partial non-finite / guard flags
     unsigned long long *qb = reinterpret_cast<unsigned long long *>(flag + NW * 16);
     double *wl = reinterpret_cast<double *>(qb + 2);   // [2][8*MT] w staged once
+    double *zl = wl + 16 * MT;                         // [2][8*MT] ZIP shares (ZIP only)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -184,11 +198,17 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
             it = 0;
 #pragma unroll
             for (int q = 0; q < TPW; ++q)
-                if (q < nv) put_injection(Ib, tw + NW * q, lane, st.v[q], st.s[q]);
+                if (q < nv) put_injection<ZIP>(Ib, tw + NW * q, lane, st.v[q], st.s[q], zl, MT);
         }
     };
 
     for (int e = threadIdx.x; e < 16 * MT; e += NW * 64) wl[e] = wv[e];
+    if constexpr (ZIP) {  // padding buses: no load, share 0
+        for (int e = threadIdx.x; e < 8 * MT; e += NW * 64) {
+            zl[e] = e < n ? aP[e] : 0.0;
+            zl[8 * MT + e] = e < n ? aI[e] : 0.0;
+        }
+    }
     // Initial fill: 16 consecutive queue entries per workgroup.
     if (threadIdx.x == 0) *qb = atomicAdd(queue, 16ull);
     __syncthreads();
@@ -232,7 +252,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
                 dmax = e0 > dmax ? e0 : dmax;
                 dmax = e1 > dmax ? e1 : dmax;
                 st.v[q] = d4{n0r, n1r, n0i, n1i};
-                put_injection(Ib, t, lane, st.v[q], st.s[q]);
+                put_injection<ZIP>(Ib, t, lane, st.v[q], st.s[q], zl, MT);
             }
         }
         dmax = fmax(dmax, __shfl_xor(dmax, 16));
@@ -324,25 +344,33 @@ static int num_cus() {
     return cached[dev];
 }
 
+template <int TPW, int NW, bool ZIP, typename IO>
+static int launch_rows_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
+                          int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
+                          unsigned long long *queue, hipStream_t stream) {
+    const int MT = dn.MT;
+    const size_t lds = (size_t)256 * MT * sizeof(double) + (size_t)NW * 16 * (sizeof(double) + sizeof(int)) + 16 +
+                       (size_t)(ZIP ? 32 : 16) * MT * sizeof(double);
+    auto kern = fpi_f64_kernel<TPW, NW, ZIP, IO>;
+    if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NW * 64, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    const long long blocks = std::min<long long>((long long)num_cus() * per_cu, (tau + 15) / 16);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, (const IO *)S, (IO *)V, iters,
+                       status, (const IO *)V0, dn.A64, dn.w64, net.n, MT, (long long)tau, tol, max_iter, queue,
+                       (const double *)dn.aP, (const double *)dn.aI);
+    return TPF_OK;
+}
+
 template <int TPW, int NW, typename IO>
 static int launch_rows(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
                        int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
                        unsigned long long *queue, hipStream_t stream) {
-    const int MT = dn.MT;
-    const size_t lds = (size_t)256 * MT * sizeof(double) + (size_t)NW * 16 * (sizeof(double) + sizeof(int)) + 16 +
-                       (size_t)16 * MT * sizeof(double);
-    if (hipFuncSetAttribute((const void *)fpi_f64_kernel<TPW, NW, IO>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds) != hipSuccess)
-        return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fpi_f64_kernel<TPW, NW, IO>, NW * 64, lds) !=
-            hipSuccess || per_cu < 1)
-        per_cu = 1;
-    const long long blocks = std::min<long long>((long long)num_cus() * per_cu, (tau + 15) / 16);
-    hipLaunchKernelGGL((fpi_f64_kernel<TPW, NW, IO>), dim3((unsigned)blocks), dim3(NW * 64), lds, stream,
-                       (const IO *)S, (IO *)V, iters, status, (const IO *)V0, dn.A64, dn.w64, net.n, MT,
-                       (long long)tau, tol, max_iter, queue);
-    return TPF_OK;
+    if (dn.aP)
+        return launch_rows_as<TPW, NW, true, IO>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);
+    return launch_rows_as<TPW, NW, false, IO>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, queue, stream);
 }
 
 template <typename IO>

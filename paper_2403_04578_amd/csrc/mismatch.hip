@@ -3,7 +3,8 @@
 // Eq. (1) of the paper gives -i_d = Y_ds v_s + Y_dd v for the demand nodes, so a
 // load drawing S must satisfy S = v .* conj(i_d), i.e.
 //     m = S + V .* conj(Y_ds v_s + Y_dd V) = 0,
-// reported per column as max_i |m_i| (NaN if any term is NaN).
+// reported per column as max_i |m_i| (NaN if any term is NaN).  ZIP loads of Eq. (2)
+// (alpha_Z = 0) draw S (alpha_P + alpha_I V) in place of S.
 //
 // Tiled kernel: a workgroup takes CB columns at a time (their V are contiguous),
 // copies their V into LDS with coalesced loads, and then TPC = 256 / CB consecutive
@@ -23,8 +24,21 @@ struct MismatchArgs {
     const int32_t *colidx;
     const double *yval;  // [nnz][2]
     const double *cval;  // [n][2]
+    const double *aI, *aP;  // ZIP shares [n], or NULL for constant-power loads
     double *out;         // [tau]
 };
+
+// The power a load draws: S for constant power, S (alpha_P + alpha_I V) for ZIP loads.
+__device__ __forceinline__ void load_power(const MismatchArgs &mm, int b, double sr, double si, double vr, double vi,
+                                           double &lr, double &li) {
+    lr = sr;
+    li = si;
+    if (mm.aP) {
+        const double ap = mm.aP[b], ai = mm.aI[b];
+        lr = sr * ap + ai * (sr * vr - si * vi);
+        li = si * ap + ai * (sr * vi + si * vr);
+    }
+}
 
 __device__ __forceinline__ double nanmax(double a, double b) { return (a > b || a != a) ? a : b; }
 
@@ -40,8 +54,10 @@ __device__ __forceinline__ double bus_mismatch(const MismatchArgs &mm, int b, do
         ar += yr * xr - yi * xi;
         ai += yr * xi + yi * xr;
     }
-    const double mr = sr + vr * ar + vi * ai;
-    const double mi = si + vi * ar - vr * ai;
+    double lr, li;
+    load_power(mm, b, sr, si, vr, vi, lr, li);
+    const double mr = lr + vr * ar + vi * ai;
+    const double mi = li + vi * ar - vr * ai;
     return sqrt(mr * mr + mi * mi);
 }
 
@@ -125,8 +141,10 @@ __global__ __launch_bounds__(256) void mismatch_tile_kernel(const IO *__restrict
                             ai += yr * xi + yi * xr;
                         }
                         const double vr = vc[2 * b], vi = vc[2 * b + 1];
-                        const double mr = (double)s[u].x + vr * ar + vi * ai;
-                        const double mi = (double)s[u].y + vi * ar - vr * ai;
+                        double lr, li;
+                        load_power(mm, b, (double)s[u].x, (double)s[u].y, vr, vi, lr, li);
+                        const double mr = lr + vr * ar + vi * ai;
+                        const double mi = li + vi * ar - vr * ai;
                         worst = nanmax(worst, sqrt(mr * mr + mi * mi));
                     }
                 }
@@ -198,7 +216,7 @@ int launch_io(const MismatchArgs &mm, int nnz, const void *S, const void *V, int
 
 int launch_mismatch_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, const void *V, int dtype,
                         int64_t tau, double *out, hipStream_t stream) {
-    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, out};
+    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, dn.aI, dn.aP, out};
     const int nnz = (int)net.colidx.size();
     if (dtype == TPF_C128) return launch_io<double>(mm, nnz, S, V, net.n, tau, stream);
     return launch_io<float>(mm, nnz, S, V, net.n, tau, stream);

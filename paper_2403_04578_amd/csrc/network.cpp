@@ -256,6 +256,13 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
             !h2d(dn.yval, yv.data(), nnz * 16) || !h2d(dn.cval, cv.data(), n * 16))
             return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
     }
+    // ---- ZIP shares
+    if (net.zip) {
+        if (!dalloc((void **)&dn.aI, n * 8) || !dalloc((void **)&dn.aP, n * 8))
+            return fail(TPF_ERR_OOM, "device allocation failed (ZIP shares)");
+        if (!h2d(dn.aI, net.alpha_i.data(), n * 8) || !h2d(dn.aP, net.alpha_p.data(), n * 8))
+            return fail(TPF_ERR_DEVICE, "host-to-device copy failed (ZIP shares)");
+    }
     return TPF_OK;
 }
 
@@ -410,3 +417,36 @@ extern "C" int tpf_network_get_zw(tpf_network net, double *Z_out, double *w_out)
 }
 
 extern "C" const char *tpf_last_error(void) { return tpf::g_err.c_str(); }
+
+extern "C" int tpf_build_network_zip(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                                     const double *r, const double *x, int32_t slack_bus, double vs_re,
+                                     double vs_im, const double *alpha_z, const double *alpha_i,
+                                     const double *alpha_p, tpf_network *out) {
+    clear_error();
+    if (!out) return fail(TPF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_bus < 2) return fail(TPF_ERR_INVALID_ARG, "n_bus must be >= 2");
+    if (!alpha_i || !alpha_p) return fail(TPF_ERR_INVALID_ARG, "alpha_i and alpha_p must not be NULL");
+    const int n = n_bus - 1;
+    for (int q = 0; q < n; ++q) {
+        if (!std::isfinite(alpha_i[q]) || !std::isfinite(alpha_p[q]) || (alpha_z && !std::isfinite(alpha_z[q])))
+            return fail(TPF_ERR_INVALID_ARG, "ZIP share of PQ bus " + std::to_string(q) + " not finite");
+        if (alpha_z && alpha_z[q] != 0.0)
+            return fail(TPF_ERR_UNSUPPORTED,
+                        "a constant-impedance share makes B = diag(alpha_Z s*) + Y_dd, hence F and w, differ per "
+                        "power flow; only alpha_z = 0 is supported");
+    }
+    tpf_network net = nullptr;
+    const int rc = tpf_build_network(n_bus, n_branch, from, to, r, x, slack_bus, vs_re, vs_im, &net);
+    if (rc != TPF_OK) return rc;
+    try {
+        net->alpha_i.assign(alpha_i, alpha_i + n);
+        net->alpha_p.assign(alpha_p, alpha_p + n);
+    } catch (...) {
+        tpf_free_network(net);
+        return fail(TPF_ERR_OOM, "host allocation failed");
+    }
+    net->zip = true;
+    *out = net;
+    return TPF_OK;
+}

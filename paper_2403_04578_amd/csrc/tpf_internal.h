@@ -59,6 +59,8 @@ struct DeviceNet {
     int32_t *colidx = nullptr;   // [nnz]
     double *yval = nullptr;      // [nnz][2]
     double *cval = nullptr;      // [n][2]
+    // ZIP load shares per PQ bus (Eq. (2), alpha_Z = 0); NULL for constant-power loads.
+    double *aI = nullptr, *aP = nullptr;  // [n] each
     std::vector<void *> owned;   // every allocation above, freed with the network
 };
 
@@ -77,6 +79,10 @@ struct tpf_network_s {
     std::vector<int32_t> rowptr, colidx;
     std::vector<tpf::cd> yval;
     std::vector<tpf::cd> c;
+    // ZIP loads (Eq. (2)) with alpha_Z = 0: shares of constant current and constant power
+    // per PQ bus; empty for constant-power loads.
+    bool zip = false;
+    std::vector<double> alpha_i, alpha_p;
     std::mutex mu;
     std::vector<tpf::DeviceNet *> dev;  // indexed by HIP device id
 };

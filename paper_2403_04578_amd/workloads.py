@@ -27,6 +27,7 @@ SEED_FEEDER = 1
 SEED_LOAD = 2
 SEED_TRAIN = 3
 SEED_PV = 4
+SEED_ZIP = 5
 
 MINUTES_PER_YEAR = 525_600
 HOURS_PER_YEAR = 8_760
@@ -210,6 +211,14 @@ def scenario_loads(feeder: Feeder, n_scen: int = 1000, hours: int = HOURS_PER_YE
     bell = np.where((hday >= 6) & (hday <= 18), np.maximum(0.0, np.sin(math.pi * (hday - 6.0) / 12.0)), 0.0)
     PV = bell[:, None] * cap[None, :]
     return ScenarioLoads(c, L, PV)
+
+
+def zip_shares(n_pq: int, seed: int = SEED_ZIP, max_current: float = 0.6):
+    """Seeded ZIP shares per PQ bus for Eq. (2)'s load model: constant-current share
+    alpha_I ~ U(0, max_current), constant-power share alpha_P = 1 - alpha_I, no
+    constant-impedance share."""
+    ai = np.random.default_rng(seed).uniform(0.0, max_current, n_pq)
+    return ai, 1.0 - ai
 
 
 def mlp_sizes(n_pq: int, hidden: int = 256, layers: int = 3):

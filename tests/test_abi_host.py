@@ -127,3 +127,31 @@ def test_workspace_sizes_by_path():
     assert lib.tpf_workspace_bytes(mid.handle, 1000, ctypes.byref(o)) == 256
     o.mode = tpf.MODE_FP32
     assert lib.tpf_workspace_bytes(mid.handle, 1000, ctypes.byref(o)) > 1000 * 2 * 199 * 4
+
+
+def test_zip_network_build_and_errors():
+    """Eq. (2) ZIP loads: Z and w do not depend on the shares; a constant-impedance share
+    is refused (it makes F and w differ per power flow); shares must be finite."""
+    f = W.make_feeder(20, seed=3)
+    n = f.n_bus - 1
+    plain = tpf.Network.from_feeder(f)
+    z = tpf.Network.from_feeder(f, alpha_i=np.linspace(0, 1, n), alpha_p=np.linspace(1, 0, n))
+    assert z.zip and not plain.zip and z.n == n
+    Z0, w0 = plain.zw()
+    Z1, w1 = z.zw()
+    assert np.array_equal(Z0, Z1) and np.array_equal(w0, w1)
+    tpf.Network.from_feeder(f, alpha_i=0.2, alpha_p=0.8, alpha_z=0.0)  # an all-zero alpha_z is accepted
+    for kw, code in [(dict(alpha_i=0.2, alpha_p=0.7, alpha_z=0.1), tpf.TPF_ERR_UNSUPPORTED),
+                     (dict(alpha_i=np.nan, alpha_p=1.0), tpf.TPF_ERR_INVALID_ARG),
+                     (dict(alpha_i=0.0, alpha_p=np.inf), tpf.TPF_ERR_INVALID_ARG)]:
+        with pytest.raises(tpf.TpfError) as e:
+            tpf.Network.from_feeder(f, **kw)
+        assert e.value.code == code, kw
+    lib = tpf.load_library()
+    h = ctypes.c_void_p()
+    fr, to = np.ascontiguousarray(f.frm, np.int32), np.ascontiguousarray(f.to, np.int32)
+    r, x = np.ascontiguousarray(f.r), np.ascontiguousarray(f.x)
+    ap = np.ones(n)
+    rc = lib.tpf_build_network_zip(f.n_bus, len(fr), fr.ctypes.data, to.ctypes.data, r.ctypes.data, x.ctypes.data,
+                                   0, 1.0, 0.0, None, None, ap.ctypes.data, ctypes.byref(h))
+    assert rc == tpf.TPF_ERR_INVALID_ARG and not h.value
