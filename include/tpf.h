@@ -120,9 +120,25 @@ int tpf_build_network_zip(int32_t n_bus, int32_t n_branch, const int32_t *from, 
                           const double *alpha_z, const double *alpha_i, const double *alpha_p,
                           tpf_network *out);
 
+/* Sec. II Eq. (1) for a three-phase (unbalanced) network: Eq. (1) is written per node,
+ * and here every bus has three phase nodes, node 3 b + p for phase p in (a, b, c).
+ *   zabc     host float64 [n_branch][3][3][2]: the series impedance matrix of each
+ *            branch (self terms on the diagonal, mutual coupling off it), invertible
+ *   vs_abc   host float64 [3][2]: slack phase voltages (a balanced source is
+ *            1, e^{-j 2 pi/3}, e^{+j 2 pi/3})
+ * Each branch stamps Y_b = zabc^-1 as a 3x3 block (Y_ff += Y_b, Y_tt += Y_b,
+ * Y_ft -= Y_b, Y_tf -= Y_b); the three slack nodes form the slack block of the partition,
+ * and the network has n = 3 (n_bus - 1) demand nodes: column q of S and V is phase
+ * q % 3 of the (q / 3)-th non-slack bus.  Everything downstream (modes, solve calls,
+ * mismatch) is the same as for a single-phase network with n demand nodes.  Other
+ * arguments and errors as tpf_build_network; TPF_ERR_INVALID_ARG for a non-finite or
+ * singular zabc block. */
+int tpf_build_network_3ph(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                          const double *zabc, int32_t slack_bus, const double *vs_abc, tpf_network *out);
+
 void tpf_free_network(tpf_network net);
 
-/* Number of PQ (demand) buses n = n_bus - 1. */
+/* Number of demand nodes n: n_bus - 1 (single phase), 3 (n_bus - 1) (three phase). */
 int tpf_network_n_pq(tpf_network net);
 
 /* Copies Z = -Y_dd^-1 (host float64 [n][n][2]) and w (host float64 [n][2]) out of the

@@ -54,6 +54,8 @@ def _load():
         lib.oracle_mismatch.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double,
                                         ctypes.c_int64, P, P, P]
         lib.oracle_mismatch.restype = None
+        lib.oracle_build_3ph.argtypes = [ctypes.c_int, ctypes.c_int, P, P, P, ctypes.c_int, P, P, P, P, P]
+        lib.oracle_build_3ph.restype = ctypes.c_int
         lib.oracle_fpi_zip.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double, P, P, ctypes.c_int64,
                                        P, ctypes.c_double, ctypes.c_int, P, P, P, P, P]
         lib.oracle_fpi_zip.restype = None
@@ -102,6 +104,33 @@ def build_network(n_bus, frm, to, r, x, slack=0, vs=1.0 + 0.0j) -> OracleNetwork
     if rc != 0:
         raise OracleError(rc)
     return OracleNetwork(n, Ydd, Yds, Z, w, complex(vs))
+
+
+def build_network_3ph(n_bus, frm, to, zabc, slack=0, vs_abc=None) -> OracleNetwork:
+    """Sec. II Eq. (1) per phase node of a three-phase network (zabc [n_branch, 3, 3]).
+    The returned network holds Yds = Y_ds v_s (the slack block times the slack phase
+    voltages) and vs = 1, so every function below applies unchanged."""
+    lib = _load()
+    n = 3 * (n_bus - 1)
+    frm = np.ascontiguousarray(frm, np.int32)
+    to = np.ascontiguousarray(to, np.int32)
+    z = np.ascontiguousarray(np.asarray(zabc, np.complex128).reshape(len(frm), 3, 3))
+    if vs_abc is None:
+        vs_abc = np.exp(-2j * np.pi / 3 * np.arange(3))
+    v = np.ascontiguousarray(np.asarray(vs_abc, np.complex128).reshape(3))
+    Ydd = np.zeros((n, n), np.complex128)
+    c = np.zeros(n, np.complex128)
+    Z = np.zeros((n, n), np.complex128)
+    w = np.zeros(n, np.complex128)
+    rc = lib.oracle_build_3ph(n_bus, len(frm), _ptr(frm), _ptr(to), _ptr(z), slack, _ptr(v), _ptr(Ydd), _ptr(c),
+                              _ptr(Z), _ptr(w))
+    if rc != 0:
+        raise OracleError(rc)
+    return OracleNetwork(n, Ydd, c, Z, w, 1.0 + 0.0j)
+
+
+def build_feeder_3ph(feeder) -> OracleNetwork:
+    return build_network_3ph(feeder.n_bus, feeder.frm, feeder.to, feeder.zabc, 0, feeder.vs_abc)
 
 
 def build_feeder(feeder) -> OracleNetwork:

@@ -21,6 +21,9 @@
  *                    stop when max_i |V'_i - V_i| < tol or after max_iter sweeps.
  *   oracle_mismatch  Power balance of Eq. (1): m = S + V .* conj(Y_ds v_s + Y_dd V),
  *                    reported as max_i |m_i| per column.
+ *   oracle_build_3ph Sec. II Eq. (1) written per phase node for a three-phase network:
+ *                    each branch's 3x3 series impedance matrix is inverted and stamped
+ *                    as a block; the slack bus's three nodes form the slack block.
  *   oracle_fpi_zip   Eq. (2) with a ZIP load model whose constant-impedance share is
  *                    zero: per column A = diag(alpha_P .* s*), B = Y_dd,
  *                    c = Y_ds v_s + alpha_I .* s*, F = -B^-1 A, w = -B^-1 c, then
@@ -135,6 +138,99 @@ int oracle_build(int n_bus, int n_branch, const int32_t *frm, const int32_t *to,
     }
 done:
     free(Y); free(M); free(pq);
+    return rc;
+}
+
+/* Inverse of an m x m complex matrix by Gauss-Jordan elimination with partial pivoting
+ * on [A | 1]; work holds m * 2m entries.  Returns 0, or OR_ERR_SINGULAR. */
+static int gj_inverse(const double complex *A, int m, double complex *Ainv, double complex *work)
+{
+    for (int i = 0; i < m; ++i) {
+        for (int j = 0; j < 2 * m; ++j) work[(size_t)i * 2 * m + j] = 0.0;
+        for (int j = 0; j < m; ++j) work[(size_t)i * 2 * m + j] = A[(size_t)i * m + j];
+        work[(size_t)i * 2 * m + m + i] = 1.0;
+    }
+    double scale = 0.0;
+    for (size_t e = 0; e < (size_t)m * m; ++e) scale = fmax(scale, cabs(A[e]));
+    for (int c = 0; c < m; ++c) {
+        int p = c;
+        double best = cabs(work[(size_t)c * 2 * m + c]);
+        for (int i = c + 1; i < m; ++i) {
+            double v = cabs(work[(size_t)i * 2 * m + c]);
+            if (v > best) { best = v; p = i; }
+        }
+        if (!(best > 1e-13 * scale)) return OR_ERR_SINGULAR;
+        if (p != c)
+            for (int j = 0; j < 2 * m; ++j) {
+                double complex tmp = work[(size_t)c * 2 * m + j];
+                work[(size_t)c * 2 * m + j] = work[(size_t)p * 2 * m + j];
+                work[(size_t)p * 2 * m + j] = tmp;
+            }
+        double complex piv = work[(size_t)c * 2 * m + c];
+        for (int j = 0; j < 2 * m; ++j) work[(size_t)c * 2 * m + j] /= piv;
+        for (int i = 0; i < m; ++i) {
+            if (i == c) continue;
+            double complex f = work[(size_t)i * 2 * m + c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 2 * m; ++j) work[(size_t)i * 2 * m + j] -= f * work[(size_t)c * 2 * m + j];
+        }
+    }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) Ainv[(size_t)i * m + j] = work[(size_t)i * 2 * m + m + j];
+    return OR_OK;
+}
+
+/* Sec. II Eq. (1) per phase node (three phases).  Node 3 b + p is phase p of bus b.
+ * Each branch stamps Y_b = zabc_k^-1 (zabc: [n_branch][3][3]) as a 3x3 block; the slack
+ * bus's nodes are the slack block with voltages vs[3].  Outputs: Ydd [n*n], c [n] =
+ * Y_ds v_s (the product of the n x 3 slack block and vs), Z [n*n] = -Y_dd^-1, w [n] =
+ * Z c, with n = 3 (n_bus - 1) demand nodes in ascending node order. */
+int oracle_build_3ph(int n_bus, int n_branch, const int32_t *frm, const int32_t *to,
+                     const double complex *zabc, int slack, const double complex *vs,
+                     double complex *Ydd, double complex *c, double complex *Z, double complex *w)
+{
+    if (n_bus < 2 || n_branch < 1 || slack < 0 || slack >= n_bus)
+        return OR_ERR_INVALID;
+    const int N = 3 * n_bus, n = 3 * (n_bus - 1);
+    double complex *Y = calloc((size_t)N * N, sizeof(double complex));
+    double complex *work = malloc(sizeof(double complex) * (size_t)n * 2 * n + 64);
+    double complex *Yinv = malloc(sizeof(double complex) * (size_t)n * n);
+    int *dn = malloc(sizeof(int) * n);
+    if (!Y || !work || !Yinv || !dn) {
+        free(Y); free(work); free(Yinv); free(dn);
+        return OR_ERR_OOM;
+    }
+    int rc = OR_OK;
+    for (int k = 0; k < n_branch; ++k) {
+        int f = frm[k], t = to[k];
+        if (f < 0 || f >= n_bus || t < 0 || t >= n_bus || f == t) { rc = OR_ERR_INVALID; goto done; }
+        double complex yb[9];
+        if (gj_inverse(zabc + 9 * (size_t)k, 3, yb, work) != OR_OK) { rc = OR_ERR_INVALID; goto done; }
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                Y[(size_t)(3 * f + i) * N + 3 * f + j] += yb[3 * i + j];
+                Y[(size_t)(3 * t + i) * N + 3 * t + j] += yb[3 * i + j];
+                Y[(size_t)(3 * f + i) * N + 3 * t + j] -= yb[3 * i + j];
+                Y[(size_t)(3 * t + i) * N + 3 * f + j] -= yb[3 * i + j];
+            }
+    }
+    for (int b = 0, i = 0; b < n_bus; ++b)
+        if (b != slack)
+            for (int p = 0; p < 3; ++p) dn[i++] = 3 * b + p;
+    for (int i = 0; i < n; ++i) {
+        c[i] = 0.0;
+        for (int p = 0; p < 3; ++p) c[i] += Y[(size_t)dn[i] * N + 3 * slack + p] * vs[p];
+        for (int j = 0; j < n; ++j) Ydd[(size_t)i * n + j] = Y[(size_t)dn[i] * N + dn[j]];
+    }
+    if (gj_inverse(Ydd, n, Yinv, work) != OR_OK) { rc = OR_ERR_SINGULAR; goto done; }
+    for (size_t e = 0; e < (size_t)n * n; ++e) Z[e] = -Yinv[e];
+    for (int i = 0; i < n; ++i) {
+        double complex acc = 0.0;
+        for (int j = 0; j < n; ++j) acc += Z[(size_t)i * n + j] * c[j];
+        w[i] = acc;
+    }
+done:
+    free(Y); free(work); free(Yinv); free(dn);
     return rc;
 }
 

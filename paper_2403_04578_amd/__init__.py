@@ -59,6 +59,7 @@ def load_library() -> ctypes.CDLL:
     sig = {
         "tpf_build_network": (ctypes.c_int, [I32, I32, P, P, P, P, I32, D, D, ctypes.POINTER(P)]),
         "tpf_build_network_zip": (ctypes.c_int, [I32, I32, P, P, P, P, I32, D, D, P, P, P, ctypes.POINTER(P)]),
+        "tpf_build_network_3ph": (ctypes.c_int, [I32, I32, P, P, P, I32, P, ctypes.POINTER(P)]),
         "tpf_free_network": (None, [P]),
         "tpf_network_n_pq": (ctypes.c_int, [P]),
         "tpf_network_get_zw": (ctypes.c_int, [P, P, P]),
@@ -126,6 +127,34 @@ class Network:
         self._h = h
         self.n_bus = int(n_bus)
         self.n = lib.tpf_network_n_pq(h)
+
+    @classmethod
+    def three_phase(cls, n_bus: int, frm, to, zabc, slack: int = 0, vs_abc=None) -> "Network":
+        """Three-phase network (Eq. (1) per phase node): zabc [n_branch, 3, 3] complex
+        series impedance matrices, vs_abc the slack phase voltages (balanced by default).
+        Demand node 3 k + p is phase p of the k-th non-slack bus."""
+        lib = load_library()
+        self = cls.__new__(cls)
+        f, t = np.ascontiguousarray(frm, np.int32), np.ascontiguousarray(to, np.int32)
+        z = np.ascontiguousarray(np.asarray(zabc, np.complex128).reshape(len(f), 3, 3))
+        if vs_abc is None:
+            vs_abc = np.exp(-2j * np.pi / 3 * np.arange(3))
+        v = np.ascontiguousarray(np.asarray(vs_abc, np.complex128).reshape(3))
+        if len(f) != len(t):
+            raise ValueError("branch arrays must have equal lengths")
+        self._keep = [f, t, z, v]
+        h = ctypes.c_void_p()
+        _check(lib.tpf_build_network_3ph(int(n_bus), len(f), f.ctypes.data, t.ctypes.data, z.ctypes.data,
+                                         int(slack), v.ctypes.data, ctypes.byref(h)))
+        self._h = h
+        self.zip = False
+        self.n_bus = int(n_bus)
+        self.n = lib.tpf_network_n_pq(h)
+        return self
+
+    @classmethod
+    def from_feeder_3ph(cls, feeder) -> "Network":
+        return cls.three_phase(feeder.n_bus, feeder.frm, feeder.to, feeder.zabc, 0, feeder.vs_abc)
 
     @classmethod
     def from_feeder(cls, feeder, alpha_i=None, alpha_p=None, alpha_z=None) -> "Network":

@@ -291,69 +291,60 @@ int device_net(tpf_network net, DeviceNet **out) {
 
 using namespace tpf;
 
-extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
-                                 const double *r, const double *x, int32_t slack_bus, double vs_re,
-                                 double vs_im, tpf_network *out) {
-    clear_error();
-    if (!out) return fail(TPF_ERR_INVALID_ARG, "out is NULL");
-    *out = nullptr;
+// Checks of the bus-level topology shared by the builders: indices, self loops, and that
+// every bus reaches the slack (else Y_dd is singular).
+static int check_topology(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                          int32_t slack_bus) {
     if (n_bus < 2) return fail(TPF_ERR_INVALID_ARG, "n_bus must be >= 2");
     if (n_branch < 1) return fail(TPF_ERR_INVALID_ARG, "n_branch must be >= 1");
-    if (!from || !to || !r || !x) return fail(TPF_ERR_INVALID_ARG, "branch arrays must not be NULL");
+    if (!from || !to) return fail(TPF_ERR_INVALID_ARG, "branch arrays must not be NULL");
     if (slack_bus < 0 || slack_bus >= n_bus) return fail(TPF_ERR_INVALID_ARG, "slack_bus out of range");
-    if (!std::isfinite(vs_re) || !std::isfinite(vs_im)) return fail(TPF_ERR_INVALID_ARG, "slack voltage not finite");
     for (int k = 0; k < n_branch; ++k) {
         if (from[k] < 0 || from[k] >= n_bus || to[k] < 0 || to[k] >= n_bus)
             return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": bus index out of range");
         if (from[k] == to[k]) return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": from == to");
-        if (!std::isfinite(r[k]) || !std::isfinite(x[k]))
-            return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": impedance not finite");
-        if (r[k] == 0.0 && x[k] == 0.0)
-            return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": zero impedance");
     }
-    const int N = n_bus, n = n_bus - 1;
-    // Connectivity: every bus must be reachable from the slack, else Y_dd is singular.
-    {
-        std::vector<std::vector<int>> adj(N);
-        for (int k = 0; k < n_branch; ++k) adj[from[k]].push_back(to[k]), adj[to[k]].push_back(from[k]);
-        std::vector<char> seen(N, 0);
-        std::queue<int> q;
-        q.push(slack_bus);
-        seen[slack_bus] = 1;
-        int cnt = 1;
-        while (!q.empty()) {
-            int u = q.front();
-            q.pop();
-            for (int v : adj[u])
-                if (!seen[v]) seen[v] = 1, ++cnt, q.push(v);
-        }
-        if (cnt != N) return fail(TPF_ERR_SINGULAR, "network is not connected: some bus cannot reach the slack");
+    std::vector<std::vector<int>> adj(n_bus);
+    for (int k = 0; k < n_branch; ++k) adj[from[k]].push_back(to[k]), adj[to[k]].push_back(from[k]);
+    std::vector<char> seen(n_bus, 0);
+    std::queue<int> q;
+    q.push(slack_bus);
+    seen[slack_bus] = 1;
+    int cnt = 1;
+    while (!q.empty()) {
+        int u = q.front();
+        q.pop();
+        for (int v : adj[u])
+            if (!seen[v]) seen[v] = 1, ++cnt, q.push(v);
     }
+    if (cnt != n_bus) return fail(TPF_ERR_SINGULAR, "network is not connected: some bus cannot reach the slack");
+    return TPF_OK;
+}
+
+// Sec. II Eqs. (1)-(2) from a node-level admittance matrix Y [Nn][Nn]: the slack nodes
+// (with their voltages) against the demand nodes in ascending node order; CSR of Y_dd,
+// c = Y_ds v_s, Z = -Y_dd^-1 (LU with partial pivoting), w = Z c.
+static int finish_network(const std::vector<cd> &Y, int Nn, const std::vector<int> &slack_nodes,
+                          const std::vector<cd> &vs_nodes, int n_bus, int slack_bus, tpf_network *out) {
     auto *net = new (std::nothrow) tpf_network_s();
     if (!net) return fail(TPF_ERR_OOM, "host allocation failed");
     try {
-        net->n_bus = N;
+        const int n = Nn - (int)slack_nodes.size();
+        net->n_bus = n_bus;
         net->n = n;
         net->slack = slack_bus;
-        net->vs = cd(vs_re, vs_im);
-        // Eq. (1): branch admittances stamped into Y.
-        std::vector<cd> Y((size_t)N * N, 0.0);
-        for (int k = 0; k < n_branch; ++k) {
-            const cd y = 1.0 / cd(r[k], x[k]);
-            const int f = from[k], t = to[k];
-            Y[(size_t)f * N + f] += y;
-            Y[(size_t)t * N + t] += y;
-            Y[(size_t)f * N + t] -= y;
-            Y[(size_t)t * N + f] -= y;
-        }
+        net->vs = vs_nodes[0];
+        std::vector<char> is_slack(Nn, 0);
+        for (int sn : slack_nodes) is_slack[sn] = 1;
         std::vector<int> pq;
-        for (int b = 0; b < N; ++b)
-            if (b != slack_bus) pq.push_back(b);
+        for (int b = 0; b < Nn; ++b)
+            if (!is_slack[b]) pq.push_back(b);
         std::vector<cd> Ydd((size_t)n * n);
-        std::vector<cd> Yds(n);
+        net->c.assign(n, 0.0);
         for (int i = 0; i < n; ++i) {
-            Yds[i] = Y[(size_t)pq[i] * N + slack_bus];
-            for (int j = 0; j < n; ++j) Ydd[(size_t)i * n + j] = Y[(size_t)pq[i] * N + pq[j]];
+            for (size_t p = 0; p < slack_nodes.size(); ++p)
+                net->c[i] += Y[(size_t)pq[i] * Nn + slack_nodes[p]] * vs_nodes[p];
+            for (int j = 0; j < n; ++j) Ydd[(size_t)i * n + j] = Y[(size_t)pq[i] * Nn + pq[j]];
         }
         net->rowptr.assign(1, 0);
         for (int i = 0; i < n; ++i) {
@@ -361,8 +352,6 @@ extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t 
                 if (Ydd[(size_t)i * n + j] != 0.0) net->colidx.push_back(j), net->yval.push_back(Ydd[(size_t)i * n + j]);
             net->rowptr.push_back((int32_t)net->colidx.size());
         }
-        net->c.resize(n);
-        for (int i = 0; i < n; ++i) net->c[i] = Yds[i] * net->vs;
         // Eq. (2): Z = -Y_dd^-1 (column by column from the LU factors), w = Z (Y_ds v_s).
         std::vector<int> piv;
         std::vector<cd> lu = Ydd;
@@ -390,6 +379,94 @@ extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t 
     }
     *out = net;
     return TPF_OK;
+}
+
+extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                                 const double *r, const double *x, int32_t slack_bus, double vs_re,
+                                 double vs_im, tpf_network *out) {
+    clear_error();
+    if (!out) return fail(TPF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_topology(n_bus, n_branch, from, to, slack_bus);
+    if (rc != TPF_OK) return rc;
+    if (!r || !x) return fail(TPF_ERR_INVALID_ARG, "branch arrays must not be NULL");
+    if (!std::isfinite(vs_re) || !std::isfinite(vs_im)) return fail(TPF_ERR_INVALID_ARG, "slack voltage not finite");
+    for (int k = 0; k < n_branch; ++k) {
+        if (!std::isfinite(r[k]) || !std::isfinite(x[k]))
+            return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": impedance not finite");
+        if (r[k] == 0.0 && x[k] == 0.0)
+            return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": zero impedance");
+    }
+    const int N = n_bus;
+    std::vector<cd> Y;
+    try {
+        // Eq. (1): branch admittances stamped into Y.
+        Y.assign((size_t)N * N, 0.0);
+        for (int k = 0; k < n_branch; ++k) {
+            const cd y = 1.0 / cd(r[k], x[k]);
+            const int f = from[k], t = to[k];
+            Y[(size_t)f * N + f] += y;
+            Y[(size_t)t * N + t] += y;
+            Y[(size_t)f * N + t] -= y;
+            Y[(size_t)t * N + f] -= y;
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(TPF_ERR_OOM, "host allocation failed");
+    }
+    return finish_network(Y, N, {slack_bus}, {cd(vs_re, vs_im)}, n_bus, slack_bus, out);
+}
+
+extern "C" int tpf_build_network_3ph(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                                     const double *zabc, int32_t slack_bus, const double *vs_abc,
+                                     tpf_network *out) {
+    clear_error();
+    if (!out) return fail(TPF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int rc = check_topology(n_bus, n_branch, from, to, slack_bus);
+    if (rc != TPF_OK) return rc;
+    if (!zabc || !vs_abc) return fail(TPF_ERR_INVALID_ARG, "zabc and vs_abc must not be NULL");
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(vs_abc[i])) return fail(TPF_ERR_INVALID_ARG, "slack voltage not finite");
+    const int Nn = 3 * n_bus;
+    std::vector<cd> Y;
+    try {
+        Y.assign((size_t)Nn * Nn, 0.0);
+        std::vector<cd> zb(9), yb(9), col(3);
+        std::vector<int> piv;
+        for (int k = 0; k < n_branch; ++k) {
+            for (int e = 0; e < 9; ++e) {
+                zb[e] = cd(zabc[18 * (size_t)k + 2 * e], zabc[18 * (size_t)k + 2 * e + 1]);
+                if (!std::isfinite(zb[e].real()) || !std::isfinite(zb[e].imag()))
+                    return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": impedance not finite");
+            }
+            // branch admittance matrix Y_b = Z_abc^-1
+            if (!lu_factor(zb, piv, 3))
+                return fail(TPF_ERR_INVALID_ARG, "branch " + std::to_string(k) + ": singular impedance matrix");
+            for (int j = 0; j < 3; ++j) {
+                col = {0.0, 0.0, 0.0};
+                col[j] = 1.0;
+                lu_solve(zb, piv, 3, col.data());
+                for (int i = 0; i < 3; ++i) yb[3 * i + j] = col[i];
+            }
+            // Eq. (1) with 3x3 blocks: node 3 b + p is phase p of bus b
+            const int f = 3 * from[k], t = 3 * to[k];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    const cd y = yb[3 * i + j];
+                    Y[(size_t)(f + i) * Nn + f + j] += y;
+                    Y[(size_t)(t + i) * Nn + t + j] += y;
+                    Y[(size_t)(f + i) * Nn + t + j] -= y;
+                    Y[(size_t)(t + i) * Nn + f + j] -= y;
+                }
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(TPF_ERR_OOM, "host allocation failed");
+    }
+    const std::vector<int> sn = {3 * slack_bus, 3 * slack_bus + 1, 3 * slack_bus + 2};
+    const std::vector<cd> vs = {cd(vs_abc[0], vs_abc[1]), cd(vs_abc[2], vs_abc[3]), cd(vs_abc[4], vs_abc[5])};
+    rc = finish_network(Y, Nn, sn, vs, n_bus, slack_bus, out);
+    if (rc == TPF_OK) (*out)->phases = 3;
+    return rc;
 }
 
 extern "C" void tpf_free_network(tpf_network net) {

@@ -70,7 +70,8 @@ struct DeviceNet {
 
 struct tpf_network_s {
     int n_bus = 0;
-    int n = 0;  // PQ buses
+    int phases = 1;  // 3 for tpf_build_network_3ph: demand node 3 k + p is phase p of PQ bus k
+    int n = 0;  // demand nodes (PQ buses x phases)
     int slack = 0;
     tpf::cd vs;
     std::vector<tpf::cd> Z;  // [n][n], Z = -Y_dd^-1

@@ -112,6 +112,54 @@ def make_chain_feeder(z: np.ndarray, vs: complex = 1.0 + 0.0j) -> Feeder:
                   z.real.copy(), z.imag.copy(), np.zeros(n), np.zeros(n), vs)
 
 
+@dataclass
+class Feeder3ph:
+    """A three-phase radial feeder: the bus tree of :func:`make_feeder` with a 3x3 series
+    impedance matrix per branch and per-phase base loads.  Demand node 3 k + p is phase p
+    of PQ bus k + 1; ``s_base`` and ``n_pq`` count demand nodes, so the profile
+    generators below apply unchanged."""
+
+    n_bus: int
+    frm: np.ndarray  # int32 [n_branch]
+    to: np.ndarray  # int32 [n_branch]
+    zabc: np.ndarray  # complex128 [n_branch, 3, 3]
+    s_base: np.ndarray  # complex128 [3 (n_bus - 1)]
+    vs_abc: np.ndarray  # complex128 [3]
+
+    @property
+    def n_pq(self) -> int:
+        return 3 * (self.n_bus - 1)
+
+
+def balanced_slack() -> np.ndarray:
+    """Phase voltages 1, e^{-j 2 pi/3}, e^{+j 2 pi/3} (phase sequence a, b, c)."""
+    return np.exp(-2j * math.pi / 3.0 * np.arange(3))
+
+
+def make_feeder_3ph(n_bus: int, seed: int = SEED_FEEDER, load_scale: float = 1.0) -> Feeder3ph:
+    """Three-phase version of :func:`make_feeder` (same tree and self impedances).
+
+    Per branch the self impedance z = r + jx of each phase is scaled by U(0.9, 1.1), and
+    every phase pair couples with a mutual impedance z U(0.3, 0.45) (a symmetric, not
+    transposed, matrix).  Each phase of a bus carries a third of the single-phase base
+    load times an imbalance factor U(0.6, 1.4).
+    """
+    f = make_feeder(n_bus, seed, load_scale)
+    rng = np.random.Generator(np.random.PCG64(seed + 1000))
+    nb = len(f.frm)
+    z = f.r + 1j * f.x
+    zabc = np.zeros((nb, 3, 3), np.complex128)
+    for p in range(3):
+        zabc[:, p, p] = z * rng.uniform(0.9, 1.1, nb)
+    for p, q in ((0, 1), (0, 2), (1, 2)):
+        m = z * rng.uniform(0.3, 0.45, nb)
+        zabc[:, p, q] = m
+        zabc[:, q, p] = m
+    imb = rng.uniform(0.6, 1.4, (n_bus - 1, 3))
+    s_base = (f.s_base[:, None] / 3.0 * imb).reshape(-1)
+    return Feeder3ph(n_bus, f.frm, f.to, zabc, s_base, balanced_slack())
+
+
 # ----------------------------------------------------------------------------- profiles
 
 def profile_daily96(feeder: Feeder, seed: int = SEED_LOAD, steps: int = 96) -> np.ndarray:

@@ -155,3 +155,31 @@ def test_zip_network_build_and_errors():
     rc = lib.tpf_build_network_zip(f.n_bus, len(fr), fr.ctypes.data, to.ctypes.data, r.ctypes.data, x.ctypes.data,
                                    0, 1.0, 0.0, None, None, ap.ctypes.data, ctypes.byref(h))
     assert rc == tpf.TPF_ERR_INVALID_ARG and not h.value
+
+
+@pytest.mark.parametrize("n_bus", [2, 20, 100])
+def test_three_phase_network_build_matches_oracle(n_bus):
+    f = W.make_feeder_3ph(n_bus, seed=3)
+    net = tpf.Network.from_feeder_3ph(f)
+    on = oracle.build_feeder_3ph(f)
+    assert net.n == 3 * (n_bus - 1) == on.n
+    Z, w = net.zw()
+    assert np.abs(Z - on.Z).max() <= 1e-12 * np.abs(on.Z).max()
+    assert np.abs(w - on.w).max() <= 1e-12
+
+
+def test_three_phase_build_errors():
+    f = W.make_feeder_3ph(5, seed=3)
+    z = f.zabc.copy()
+    z[1] = np.ones((3, 3))  # rank one: no branch admittance matrix
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.Network.three_phase(f.n_bus, f.frm, f.to, z)
+    assert e.value.code == tpf.TPF_ERR_INVALID_ARG
+    z = f.zabc.copy()
+    z[0, 1, 2] = np.nan
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.Network.three_phase(f.n_bus, f.frm, f.to, z)
+    assert e.value.code == tpf.TPF_ERR_INVALID_ARG
+    with pytest.raises(tpf.TpfError) as e:  # island
+        tpf.Network.three_phase(4, [0, 2], [1, 3], f.zabc[:2])
+    assert e.value.code == tpf.TPF_ERR_SINGULAR

@@ -394,3 +394,72 @@ def test_zip_mixed_shares_satisfy_power_balance(seed):
     cp = oracle.fpi(net, S, 1e-13, 200)
     assert np.abs(cp.V - res.V).max() > 1e-5
     assert oracle.mismatch(net, S, res.V).max() > 1e-6
+
+
+# ----------------------------------------------------------------------------- three phases
+
+def _a2():
+    return np.exp(-2j * math.pi / 3.0)
+
+
+def test_3ph_zbus_is_path_impedance_blocks():
+    """Radial three-phase feeder: block (i, j) of Y_dd^-1 is the sum of the branch
+    impedance matrices shared by the slack->i and slack->j paths; w = v_s per phase."""
+    f = W.make_feeder_3ph(30, seed=7)
+    net = oracle.build_feeder_3ph(f)
+    paths = _paths(f)
+    n = f.n_bus - 1
+    expect = np.zeros((3 * n, 3 * n), complex)
+    for i in range(n):
+        for j in range(n):
+            for k in paths[i + 1] & paths[j + 1]:
+                expect[3 * i:3 * i + 3, 3 * j:3 * j + 3] += f.zabc[k]
+    assert np.abs(-net.Z - expect).max() <= 1e-13 * np.abs(expect).max()
+    assert np.abs(net.w - np.tile(f.vs_abc, n)).max() < 1e-13
+
+
+def test_3ph_uncoupled_phases_are_three_single_phase_feeders():
+    f1 = W.make_feeder(40, seed=2)
+    z = f1.r + 1j * f1.x
+    scale = (1.0, 1.3, 0.7)
+    zabc = np.zeros((len(z), 3, 3), complex)
+    for p in range(3):
+        zabc[:, p, p] = z * scale[p]
+    vs = W.balanced_slack() * 1.01
+    net = oracle.build_network_3ph(f1.n_bus, f1.frm, f1.to, zabc, 0, vs)
+    S1 = W.profile_daily96(f1, steps=20)
+    S = np.stack([S1 * (0.8 + 0.2 * p) for p in range(3)], axis=2).reshape(20, -1)
+    res = oracle.fpi(net, S, 1e-13, 200)
+    for p in range(3):
+        zp = z * scale[p]
+        single = oracle.build_network(f1.n_bus, f1.frm, f1.to, zp.real, zp.imag, 0, vs[p])
+        assert np.abs(net.Z[p::3, p::3] - single.Z).max() < 1e-14
+        other = [q for q in range(3) if q != p]
+        assert np.abs(net.Z[p::3][:, other[0]::3]).max() == 0.0
+        r1 = oracle.fpi(single, S1 * (0.8 + 0.2 * p), 1e-13, 200)
+        assert np.abs(res.V[:, p::3] - r1.V).max() < 1e-12
+
+
+def test_3ph_balanced_transposed_line_is_its_positive_sequence():
+    """Equal self and equal mutual impedances, a balanced source and balanced loads: the
+    solution is a positive-sequence set whose phase a solves the single-phase feeder
+    with z1 = z_self - z_mutual (I_a + I_b + I_c = 0 cancels the coupling)."""
+    f1 = W.make_feeder(35, seed=4, load_scale=4.0)
+    zs = f1.r + 1j * f1.x
+    zm = 0.4 * zs
+    zabc = zm[:, None, None] * np.ones((3, 3)) + (zs - zm)[:, None, None] * np.eye(3)
+    net = oracle.build_network_3ph(f1.n_bus, f1.frm, f1.to, zabc)
+    S1 = W.profile_daily96(f1, steps=16)
+    S = np.repeat(S1, 3, axis=1)
+    res = oracle.fpi(net, S, 1e-13, 200)
+    z1 = zs - zm
+    single = oracle.build_network(f1.n_bus, f1.frm, f1.to, z1.real, z1.imag)
+    r1 = oracle.fpi(single, S1, 1e-13, 200)
+    assert np.all(res.status == oracle.ST_CONVERGED)
+    a2 = _a2()
+    assert np.abs(res.V[:, 0::3] - r1.V).max() < 1e-12
+    assert np.abs(res.V[:, 1::3] - a2 * r1.V).max() < 1e-12
+    assert np.abs(res.V[:, 2::3] - np.conj(a2) * r1.V).max() < 1e-12
+    # the coupling matters: the same loads on uncoupled phases with z_self land elsewhere
+    loose = oracle.build_network(f1.n_bus, f1.frm, f1.to, zs.real, zs.imag)
+    assert np.abs(oracle.fpi(loose, S1, 1e-13, 200).V - r1.V).max() > 1e-4
