@@ -205,6 +205,13 @@ def bench_other(args):
         del c, L, PV
         desc = "300-bus radial feeder (299 PQ), 1,000 scenarios x 8,760 hours, complex64 S"
         sample = lambda k: loads.element(np.arange(k) // 8760, np.arange(k) % 8760, np.complex128)
+    elif args.workload == "year100_3ph":
+        f = W.make_feeder_3ph(100)
+        S_host = W.profile_minute_year(f)
+        S = torch.from_numpy(S_host).to(dev)
+        desc = ("100-bus three-phase radial feeder (297 demand nodes, coupled phases, unbalanced loads), "
+                "525,600 one-minute steps, complex128 S")
+        sample = lambda k: S_host[:k]
     elif args.workload == "zip100":
         f = W.make_feeder(100)
         S_host = W.profile_minute_year(f)
@@ -223,7 +230,11 @@ def bench_other(args):
     setup_s = time.perf_counter() - t0
     T, n = S.shape
     zip_loads = args.workload == "zip100"
-    net = tpf.Network.from_feeder(f, alpha_i=ai, alpha_p=ap) if zip_loads else tpf.Network.from_feeder(f)
+    three = args.workload == "year100_3ph"
+    if three:
+        net = tpf.Network.from_feeder_3ph(f)
+    else:
+        net = tpf.Network.from_feeder(f, alpha_i=ai, alpha_p=ap) if zip_loads else tpf.Network.from_feeder(f)
     stream = torch.cuda.current_stream(dev)
     esz = S.element_size()
     forms = {}
@@ -271,7 +282,7 @@ def bench_other(args):
            "forms": forms, "setup_s": setup_s}
     if not args.no_cpu_baseline:
         import oracle
-        onet = oracle.build_network(f.n_bus, f.frm, f.to, f.r, f.x, 0, f.vs)
+        onet = oracle.build_feeder_3ph(f) if three else oracle.build_network(f.n_bus, f.frm, f.to, f.r, f.x, 0, f.vs)
         k = 200 if n > 500 else (100_000 if zip_loads else 2000)
         Sk = sample(k)
         t0 = time.perf_counter()
@@ -301,10 +312,11 @@ def main():
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="turn two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of this script with "
                          "--calib-copy into profiles/hbm_traffic.json and exit")
-    ap.add_argument("--workload", default="year100", choices=["year100", "tensor300", "feeder1000", "zip100"],
+    ap.add_argument("--workload", default="year100", choices=["year100", "tensor300", "feeder1000", "zip100", "year100_3ph"],
                     help="year100 (default, headline): 100-bus feeder, 525,600 minutes; tensor300: 300-bus "
                          "feeder, 1,000 scenarios x 8,760 hours, complex64; feeder1000: 1,000-bus feeder, "
-                         "200,000 minutes; zip100: the 100-bus year with ZIP loads, FP64 form")
+                         "200,000 minutes; zip100: the 100-bus year with ZIP loads, FP64 form; year100_3ph: the "
+                         "100-bus three-phase feeder over the year")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT_TXT", "COMMAND"),
                     help="write a short text summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
