@@ -296,6 +296,57 @@ def bench_other(args):
     print(json.dumps(rec), flush=True)
 
 
+def bench_scaling(args):
+    """Solve time of the kernels alone against network size (demand nodes 9 .. 1,999 at
+    500 columns) and against the number of columns (10 .. 525,600 at 499 nodes), FP64
+    and mixed FP16 forms, tol 1e-6: the shapes of the paper's size and batch scaling
+    figures on synthetic feeders.  Median of 3 timed solves after one warm-up.  Prints
+    one JSON line."""
+    import torch
+
+    import paper_2403_04578_amd as tpf
+    from paper_2403_04578_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    tol, max_iter = 1e-6, 100
+
+    def point(n_bus, tau):
+        f = W.make_feeder(n_bus)
+        t0 = time.perf_counter()
+        net = tpf.Network.from_feeder(f)
+        build_s = time.perf_counter() - t0
+        S = torch.from_numpy(W.profile_minute_year(f, steps=tau)).to(dev)
+        rec = {"n_nodes": n_bus - 1, "tau": tau, "build_s": build_s}
+        for mode in ("fp64", "mixed_fp16"):
+            out = tpf.alloc_outputs(net, S, mode, mismatch=False)
+            tpf.solve_timeseries(net, S, tol, max_iter, mode, out=out)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                tpf.solve_timeseries(net, S, tol, max_iter, mode, out=out)
+                b.record(stream)
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            ms = float(np.median(ts))
+            sweeps = float(out[1].double().sum())
+            rec[mode] = {"ms": ms, "power_flows_per_s": tau / (ms * 1e-3), "sweeps_mean": sweeps / tau,
+                         "tflops": 8.0 * (n_bus - 1) ** 2 * sweeps / (ms * 1e-3) / 1e12,
+                         "converged": int((out[2] == tpf.ST_CONVERGED).sum())}
+            del out
+        del S
+        torch.cuda.empty_cache()
+        print(json.dumps(rec), file=sys.stderr, flush=True)
+        return rec
+
+    size_curve = [point(nb, 500) for nb in (10, 31, 100, 200, 300, 500, 1000, 2000)]
+    tau_curve = [point(500, t) for t in (10, 100, 1_000, 10_000, 100_000, 525_600)]
+    print(json.dumps({"metric": "solve time vs network size and batch", "size_curve_tau500": size_curve,
+                      "tau_curve_n499": tau_curve}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -317,6 +368,8 @@ def main():
                          "feeder, 1,000 scenarios x 8,760 hours, complex64; feeder1000: 1,000-bus feeder, "
                          "200,000 minutes; zip100: the 100-bus year with ZIP loads, FP64 form; year100_3ph: the "
                          "100-bus three-phase feeder over the year")
+    ap.add_argument("--scaling", action="store_true",
+                    help="time the FP64 and mixed FP16 solves over network sizes and batch sizes and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT_TXT", "COMMAND"),
                     help="write a short text summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
@@ -331,6 +384,9 @@ def main():
                           "n_gpus": args.gpus}))
         sys.exit(2)
 
+    if args.scaling:
+        bench_scaling(args)
+        return
     if args.workload != "year100":
         bench_other(args)
         return
