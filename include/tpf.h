@@ -112,9 +112,10 @@ int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, cons
  *   alpha_i, alpha_p host float64 [n] per PQ bus (PQ order), finite; any values
  *                    (they need not sum to 1)
  * Other arguments and errors as tpf_build_network; TPF_ERR_INVALID_ARG for a NULL or
- * non-finite share.  A ZIP network solves in TPF_MODE_FP64 (other modes return
- * TPF_ERR_UNSUPPORTED), and its mismatch (options.mismatch_out, tpf_mismatch) is the
- * balance of these loads: S (alpha_P + alpha_I V) + V conj(Y_ds v_s + Y_dd V). */
+ * non-finite share.  A ZIP network solves in every mode; the FP16 form widens its
+ * per-column scale by max_q |alpha_P[q]| + |alpha_I[q]| so that the larger injections stay
+ * in range.  Its mismatch (options.mismatch_out, tpf_mismatch) is the balance of these
+ * loads: S (alpha_P + alpha_I V) + V conj(Y_ds v_s + Y_dd V). */
 int tpf_build_network_zip(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
                           const double *r, const double *x, int32_t slack_bus, double vs_re, double vs_im,
                           const double *alpha_z, const double *alpha_i, const double *alpha_p,

@@ -37,8 +37,6 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
     if (max_iter < 0) return fail(TPF_ERR_INVALID_ARG, "max_iter must be >= 0");
     const int mode = opts ? opts->mode : TPF_MODE_FP64;
     if (mode < TPF_MODE_FP64 || mode > TPF_MODE_MIXED_FP16) return fail(TPF_ERR_INVALID_ARG, "unknown mode");
-    if (net->zip && mode != TPF_MODE_FP64)
-        return fail(TPF_ERR_UNSUPPORTED, "a ZIP-load network solves in TPF_MODE_FP64 only");
     if (mode != TPF_MODE_FP64 && tol < 5e-7)
         return fail(TPF_ERR_INVALID_ARG, "tol below the FP32 state floor (5e-7 pu) in a reduced-precision mode");
     if (T == 0) return TPF_OK;

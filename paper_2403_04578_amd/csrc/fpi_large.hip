@@ -306,9 +306,10 @@ struct Low16<TPF_MODE_MIXED_FP16> {
     }
 };
 
-// One wave per column: FP16 scale from max |S| and the initial schedule state.
+// One wave per column: FP16 scale from max |S| (times zscale = max |alpha_P| + |alpha_I|
+// for ZIP loads) and the initial schedule state.
 template <int MODE, typename IO>
-__global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, int sZ, MixState *ms,
+__global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, int sZ, float zscale, MixState *ms,
                                 unsigned *umax) {
     const long long c = blockIdx.x * 4LL + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
@@ -320,6 +321,7 @@ __global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, 
         sbad |= !(sr + si < HUGE_VAL);
         sm = fmaxf(sm, (float)fmax(sr, si));
     }
+    sm *= zscale;
     for (int off = 32; off > 0; off >>= 1) {
         sm = fmaxf(sm, __shfl_xor(sm, off));
         sbad |= __shfl_xor(sbad, off);
@@ -344,11 +346,20 @@ __global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, 
     }
 }
 
+// alpha_P conj(S./V) + alpha_I conj(S) for ZIP loads (aP, aI non-NULL), else conj(S./V).
+__device__ __forceinline__ float2 zip_injection(float ir, float ii, float sr, float si, const double *aP,
+                                                const double *aI, int b) {
+    if (!aP) return make_float2(ir, ii);
+    const float ap = (float)aP[b], ai = (float)aI[b];
+    return make_float2(ap * ir + ai * sr, ap * ii - ai * si);
+}
+
 // I = conj(S./V) in FP32 for the refine list: B32 [rows][KP] and I_prev.
 template <typename IO>
 __global__ void inject_refine_kernel(const IO *__restrict__ S, const float *__restrict__ U,
                                      const double *__restrict__ w, float *__restrict__ Ip, int n, int KP,
                                      const long long *__restrict__ act, const int *__restrict__ na, int rows,
+                                     const double *__restrict__ aP, const double *__restrict__ aI,
                                      float *__restrict__ B) {
     const int nact = *na;
     const int half = KP / 2;
@@ -362,7 +373,7 @@ __global__ void inject_refine_kernel(const IO *__restrict__ S, const float *__re
             const float sr = (float)S[o], si = (float)S[o + 1];
             const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
             const float r = 1.0f / (vr * vr + vi * vi);
-            out = make_float2((sr * vr + si * vi) * r, (sr * vi - si * vr) * r);
+            out = zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, aP, aI, b);
             *reinterpret_cast<float2 *>(Ip + o) = out;
         }
         *reinterpret_cast<float2 *>(B + a * KP + 2 * b) = out;
@@ -376,6 +387,7 @@ __global__ void inject_low_kernel(const IO *__restrict__ S, const float *__restr
                                   const double *__restrict__ w, float *__restrict__ Ip,
                                   const MixState *__restrict__ ms, int n, int KP16,
                                   const long long *__restrict__ act, const int *__restrict__ na, int rows,
+                                  const double *__restrict__ aP, const double *__restrict__ aI,
                                   uint32_t *__restrict__ B) {
     const int nact = *na;
     const int half = KP16 / 2;
@@ -391,7 +403,8 @@ __global__ void inject_low_kernel(const IO *__restrict__ S, const float *__restr
             const float sr = (float)S[o], si = (float)S[o + 1];
             const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
             const float r = 1.0f / (vr * vr + vi * vi);
-            const float ir = (sr * vr + si * vi) * r, ii = (sr * vi - si * vr) * r;
+            const float2 iz = zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, aP, aI, b);
+            const float ir = iz.x, ii = iz.y;
             float br = ir, bi = ii;
             float2 *ip = reinterpret_cast<float2 *>(Ip + o);
             if (ph) {
@@ -702,14 +715,15 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
     hipLaunchKernelGGL((init_kernel<float, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)V0, w,
                        n, (long long)tau, U, iters, actL[0], cnt, dmax);
     hipLaunchKernelGGL((init_mix_kernel<MODE, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)S,
-                       n, (long long)tau, dn.sZ, ms, umax);
+                       n, (long long)tau, dn.sZ, dn.aP ? dn.zscale : 1.0f, ms, umax);
     int nl = (int)tau, nr = 0, cur = 0;
     for (int sweep = 0; sweep < max_iter && nl + nr > 0; ++sweep) {
         int *cc = cnt + 2 * cur, *cn = cnt + 2 * (cur ^ 1);
         if (nr > 0) {
             const long long ar = (nr + 63) / 64 * 64;
             hipLaunchKernelGGL((inject_refine_kernel<IO>), dim3((unsigned)std::min<long long>(65536, (ar * KP / 2 + 255) / 256)),
-                               dim3(256), 0, st, (const IO *)S, U, w, Ip, n, KP, actR[cur], cc + 1, (int)ar, B32);
+                               dim3(256), 0, st, (const IO *)S, U, w, Ip, n, KP, actR[cur], cc + 1, (int)ar, dn.aP,
+                               dn.aI, B32);
             hipLaunchKernelGGL((gemm_kernel<float>), dim3((unsigned)(ar / 64), (unsigned)(MP / 64)), dim3(256), 0, st,
                                dn.AL32, KP, B32, actR[cur], cc + 1, w, n, U, dmax, badf);
         }
@@ -717,7 +731,7 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
             const long long ar = (nl + 127) / 128 * 128;
             hipLaunchKernelGGL((inject_low_kernel<MODE, IO>),
                                dim3((unsigned)std::min<long long>(65536, (ar * K16 / 2 + 255) / 256)), dim3(256), 0, st,
-                               (const IO *)S, U, w, Ip, ms, n, K16, actL[cur], cc, (int)ar,
+                               (const IO *)S, U, w, Ip, ms, n, K16, actL[cur], cc, (int)ar, dn.aP, dn.aI,
                                reinterpret_cast<uint32_t *>(B16));
             hipLaunchKernelGGL((gemm_low_kernel<MODE>), dim3((unsigned)(ar / 128), (unsigned)(MP / 128)), dim3(256), 0,
                                st, A16, K16, B16, actL[cur], cc, ms, n, U, dmax, umax, badf);

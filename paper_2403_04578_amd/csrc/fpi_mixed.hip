@@ -97,13 +97,16 @@ struct ColState {
 };
 
 // PF (FP16 form only): 1 = the rows of S of each batch are staged in LDS, the next batch's
-// copied while the current one sweeps; 2 = the rows of V0 as well.
-template <int TPW, int NW, int KTL, int MODE, int CG, int PF, typename IO>
+// copied while the current one sweeps; 2 = the rows of V0 as well.  ZIP: loads of Eq. (2)
+// with constant-current and constant-power shares (aP, aI per bus; zscale = max_b
+// |alpha_P| + |alpha_I| bounds the injection for the FP16 column scale).
+template <int TPW, int NW, int KTL, int MODE, int CG, int PF, bool ZIP, typename IO>
 __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const float *__restrict__ A32,
     const uint16_t *__restrict__ Alow, const uint16_t *__restrict__ Alo, const double *__restrict__ wv, int n,
-    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue) {
+    int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue,
+    const double *__restrict__ aP, const double *__restrict__ aI, float zscale) {
     using L = LowOps<MODE>;
     typedef typename L::frag frag;
     typedef typename L::quad quad;
@@ -133,6 +136,8 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     // batch sweeps
     IO *Spf = reinterpret_cast<IO *>(wl + 16 * MT);                                   // [NC][n][2]
     IO *Vpf = Spf + (size_t)NC * n * 2;                                               // [NC][n][2]
+    // ZIP shares [2][8 MT] (alpha_P, then alpha_I; padding buses 0), after the row copies
+    float *zl = reinterpret_cast<float *>(Spf + (size_t)NC * n * 2 * (kSplit ? PF : 0));
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -146,6 +151,12 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     for (int e = tid; e < 4 * NC; e += NT) rmax[e] = 0.0f;
     for (int e = tid; e < 2 * NC; e += NT) rbad[e] = 0;
     for (int e = tid; e < 16 * MT; e += NT) wl[e] = wv[e];
+    if constexpr (ZIP) {
+        for (int e = tid; e < 8 * MT; e += NT) {
+            zl[e] = e < n ? (float)aP[e] : 0.0f;
+            zl[8 * MT + e] = e < n ? (float)aI[e] : 0.0f;
+        }
+    }
 
     frag Af[TPW][KTL], Ag[kSplit ? TPW : 1][kSplit ? KTL : 1];
     f4 Wq[TPW];  // w of the lane's two buses per tile, FP32, (Re, Im, Re, Im)
@@ -191,13 +202,19 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
 
     // Forms the injections of every group from the current drops (Eq. (3), scaled by the
     // column's 2^sB), writes the B operand of the next sweep and rotates Ip.
-    auto prepare_b = [&]() {
+    auto prepare_b = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int c = 0; c < CG; ++c) {
 #pragma unroll
             for (int q = 0; q < TPW; ++q) {
-                const f4 In = inject(q < nv ? Sx[(c * MT + tw + NW * q) * 64 + lane] : f4{0, 0, 0, 0}, Wq[q],
-                                     U[c][q], ks[c]);
+                const f4 sv = q < nv ? Sx[(c * MT + tw + NW * q) * 64 + lane] : f4{0, 0, 0, 0};
+                f4 In = inject(sv, Wq[q], U[c][q], ks[c]);
+                if (ZIP && q < nv) {  // alpha_P conj(S./V) + alpha_I conj(S), both scaled
+                    const int b0 = 8 * (tw + NW * q) + 2 * g;
+                    const float p0 = zl[b0], p1 = zl[b0 + 1], i0 = zl[8 * MT + b0] * ks[c], i1 = zl[8 * MT + b0 + 1] * ks[c];
+                    In = f4{p0 * In[0] + i0 * sv[0], p0 * In[1] - i0 * sv[1], p1 * In[2] + i1 * sv[2],
+                            p1 * In[3] - i1 * sv[3]};
+                }
                 if (q < nv) {
                     const f4 bv = dif[c] ? In - Ip[c][q] : In;
                     const int t = tw + NW * q;
@@ -314,6 +331,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
                 sm = fmaxf(sm, amax4(sv));
                 U[c][q] = f4{(float)v[0], (float)v[1], (float)v[2], (float)v[3]} - Wq[q];
             }
+            if constexpr (ZIP) sm *= zscale;
             sm = fmaxf(sm, __shfl_xor(sm, 16));
             sm = fmaxf(sm, __shfl_xor(sm, 32));
             bad |= __shfl_xor(bad, 16);
@@ -584,9 +602,10 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     constexpr bool mixed = MODE != TPF_MODE_FP32, split = MODE == TPF_MODE_MIXED_FP16;
     const size_t NC = 16 * CG, NT = NW * 64;
     const size_t KPL = 32 * KTL + 8, KP32 = 16 * MT + 4;
+    const bool zip = dn.aP != nullptr;
     const size_t lds0 = (split ? 0 : NC * KP32 * 4) + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) +
-                        (size_t)CG * MT * 64 * 16 + NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 32 + 64 +
-                        (size_t)16 * MT * 8;
+                        (size_t)CG * MT * 64 * 16 + NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 32 +
+                        (size_t)16 * MT * 8 + (zip ? (size_t)16 * MT * 4 : 0);
     // The next batch's S is prefetched into LDS when it fits beside the rest, and its V0
     // too when that also fits (the copies write exactly the rows' bytes).
     // (measured: it pays in the FP16 form, not in the BF16 one, whose registers it raises)
@@ -595,10 +614,15 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     int pf = split && lds0 + spf <= cap ? 1 : 0;
     if (pf && V0 && lds0 + 2 * spf <= cap) pf = 2;
     const size_t lds = lds0 + (size_t)pf * spf;
-    auto kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 0, IO>;
+    auto kern = zip ? fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 0, true, IO>
+                    : fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 0, false, IO>;
     if constexpr (split) {
-        if (pf == 1) kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 1, IO>;
-        if (pf == 2) kern = fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 2, IO>;
+        if (pf == 1)
+            kern = zip ? fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 1, true, IO>
+                       : fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 1, false, IO>;
+        if (pf == 2)
+            kern = zip ? fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 2, true, IO>
+                       : fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, 2, false, IO>;
     }
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
@@ -611,7 +635,8 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     const long long blocks = std::min<long long>((long long)cus * per_cu, (tau + (long long)NC - 1) / (long long)NC);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.A32, MODE == TPF_MODE_MIXED_BF16 ? dn.Abf : dn.Ah, dn.Al,
-                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue);
+                       dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue, dn.aP, dn.aI,
+                       dn.zscale);
     return TPF_OK;
 }
 

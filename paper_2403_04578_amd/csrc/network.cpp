@@ -262,6 +262,9 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
             return fail(TPF_ERR_OOM, "device allocation failed (ZIP shares)");
         if (!h2d(dn.aI, net.alpha_i.data(), n * 8) || !h2d(dn.aP, net.alpha_p.data(), n * 8))
             return fail(TPF_ERR_DEVICE, "host-to-device copy failed (ZIP shares)");
+        double zs = 0.0;
+        for (int q = 0; q < n; ++q) zs = std::max(zs, std::fabs(net.alpha_p[q]) + std::fabs(net.alpha_i[q]));
+        dn.zscale = (float)zs;
     }
     return TPF_OK;
 }

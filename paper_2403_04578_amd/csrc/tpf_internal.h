@@ -61,6 +61,7 @@ struct DeviceNet {
     double *cval = nullptr;      // [n][2]
     // ZIP load shares per PQ bus (Eq. (2), alpha_Z = 0); NULL for constant-power loads.
     double *aI = nullptr, *aP = nullptr;  // [n] each
+    float zscale = 1.0f;                  // max_b |alpha_P| + |alpha_I| (bounds |I| / |S| with |V|)
     std::vector<void *> owned;   // every allocation above, freed with the network
 };
 

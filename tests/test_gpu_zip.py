@@ -1,7 +1,8 @@
-"""GPU parity of the ZIP load model of Eq. (2) (constant-impedance share zero) in the
-FP64 form against the oracle's per-column F and w: the register-resident kernel (99 and
-299 PQ buses) and the per-sweep path (399), complex128 and complex64 loads, the
-constant-power and constant-current limits, and the ZIP power-balance mismatch.
+"""GPU parity of the ZIP load model of Eq. (2) (constant-impedance share zero) against
+the oracle's per-column F and w: the FP64 register-resident kernel (99 and 299 PQ buses)
+and per-sweep path (399), the FP32 and mixed forms (register-resident at 99, per-sweep at
+299, with warm starts), complex128 and complex64 loads, the constant-power and
+constant-current limits, and the ZIP power-balance mismatch.
 
 Bounds: the FP64 contract, 1e-9 pu, on columns with the oracle's sweep count (a column
 whose last step sits on the tolerance may stop one sweep apart and is re-run on the
@@ -119,11 +120,42 @@ def test_zip_complex64_and_edges(gpu, n_bus):
     assert np.all(stn[good] == tpf.ST_CONVERGED)
 
 
-def test_zip_rejects_fast_forms(gpu):
+@pytest.mark.parametrize("mode", ["fp32", "mixed_bf16", "mixed_fp16"])
+@pytest.mark.parametrize("n_bus,dtype", [(100, torch.complex128), (100, torch.complex64), (300, torch.complex128)])
+def test_zip_fast_forms(gpu, mode, n_bus, dtype):
+    """The reduced-precision forms with ZIP loads: register-resident kernels at 99 PQ
+    buses, the per-sweep path at 299; warm starts at 99 (staged in LDS in the FP16 form).
+    Bound: the fast-form contract, 1e-6 pu against a tol-1e-10 oracle solution."""
+    f = W.make_feeder(n_bus)
+    ai, ap = _shares(n_bus - 1, 13)
+    net, onet = tpf.Network.from_feeder(f, alpha_i=ai, alpha_p=ap), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=600, t0=55)
+    if dtype == torch.complex64:
+        S = S.astype(np.complex64).astype(np.complex128)
+    ref = oracle.fpi_zip(onet, S, ai, ap, 1e-10, 200)
+    bound = 1e-6 + (1e-7 if dtype == torch.complex64 else 0.0)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu, dtype), tol=1e-6, max_iter=100, mode=mode)
+    assert int(st.max()) == tpf.ST_CONVERGED
+    assert np.abs(V.cpu().numpy().astype(np.complex128) - ref.V).max() <= bound
+    if n_bus == 100:
+        rng = np.random.default_rng(3)
+        V0 = ref.V + 2e-4 * (rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape))
+        Vw, iw, sw = tpf.solve_timeseries(net, _dev(S, gpu, dtype), tol=1e-6, max_iter=100, mode=mode,
+                                          V0=_dev(V0, gpu, dtype))
+        assert int(sw.max()) == tpf.ST_CONVERGED
+        assert np.abs(Vw.cpu().numpy().astype(np.complex128) - ref.V).max() <= bound
+        assert float(iw.float().mean()) < float(it.float().mean())
+
+
+def test_zip_large_shares_keep_fp16_in_range(gpu):
+    """Shares far from a partition of unity (alpha_P = 3, alpha_I = 2) enlarge the
+    injection; the FP16 column scale accounts for them, so the form still converges to
+    the oracle's solution."""
     f = W.make_feeder(100)
-    net = tpf.Network.from_feeder(f, alpha_i=0.3, alpha_p=0.7)
-    Sd = _dev(W.profile_minute_year(f, steps=10), gpu)
-    for mode in ("fp32", "mixed_bf16", "mixed_fp16"):
-        with pytest.raises(tpf.TpfError) as e:
-            tpf.solve_timeseries(net, Sd, tol=1e-6, max_iter=10, mode=mode)
-        assert e.value.code == tpf.TPF_ERR_UNSUPPORTED
+    net, onet = tpf.Network.from_feeder(f, alpha_i=2.0, alpha_p=3.0), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=128, t0=600) * 0.2
+    ref = oracle.fpi_zip(onet, S, 2.0, 3.0, 1e-10, 200)
+    for mode in ("mixed_fp16", "mixed_bf16"):
+        V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode=mode)
+        assert int(st.max()) == tpf.ST_CONVERGED
+        assert np.abs(V.cpu().numpy() - ref.V).max() <= 1e-6
