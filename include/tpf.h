@@ -68,7 +68,15 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
  * per-sweep kernel sequence (dense Z no longer fits one workgroup's registers) whose
  * host loop waits for the device once per sweep; smaller networks run one persistent
  * kernel per solve. */
-enum { TPF_MODE_FP64 = 0, TPF_MODE_FP32 = 1, TPF_MODE_MIXED_BF16 = 2, TPF_MODE_MIXED_FP16 = 3 };
+/* TREE_FP64   the FP64 iteration with Z I evaluated by two passes over the feeder's
+ *             tree instead of the dense product: on a radial network without shunts,
+ *             -Z is the path-impedance matrix, so Z I = -D with branch currents
+ *             J_b = I_b + sum over b's children of J (leaves to slack) and drops
+ *             D_b = D_parent + z_b J_b (slack to leaves).  Same iterates up to rounding,
+ *             O(n) instead of 8 n^2 flops per column and sweep.  Needs a single-phase
+ *             network with n_bus - 1 branches (a tree) and n <= 1024; returns
+ *             TPF_ERR_UNSUPPORTED otherwise. */
+enum { TPF_MODE_FP64 = 0, TPF_MODE_FP32 = 1, TPF_MODE_MIXED_BF16 = 2, TPF_MODE_MIXED_FP16 = 3, TPF_MODE_TREE_FP64 = 4 };
 
 /* Per-column outcome written to status_out. */
 enum { TPF_ST_CONVERGED = 0, TPF_ST_MAX_ITER = 1, TPF_ST_NONFINITE = 2 };

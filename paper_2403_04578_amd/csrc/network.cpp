@@ -256,6 +256,29 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
             !h2d(dn.yval, yv.data(), nnz * 16) || !h2d(dn.cval, cv.data(), n * 16))
             return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
     }
+    // ---- breadth-first tree (radial single-phase networks)
+    if (!net.tree_pq.empty()) {
+        const int levels = (int)net.tree_level_start.size() - 2;
+        std::vector<int32_t> ti(4 * (n + 1) + levels + 2);
+        std::vector<double> tz(4 * (n + 1));
+        for (int p = 0; p <= n; ++p) {
+            ti[4 * p] = net.tree_pq[p];
+            ti[4 * p + 1] = net.tree_parent[p];
+            ti[4 * p + 2] = net.tree_c0[p];
+            ti[4 * p + 3] = net.tree_c1[p];
+            tz[4 * p] = net.tree_z[p].real();
+            tz[4 * p + 1] = net.tree_z[p].imag();
+            const tpf::cd wq = p > 0 ? net.w[net.tree_pq[p]] : tpf::cd(0.0);
+            tz[4 * p + 2] = wq.real();
+            tz[4 * p + 3] = wq.imag();
+        }
+        for (int L = 0; L < levels + 2; ++L) ti[4 * (n + 1) + L] = net.tree_level_start[L];
+        if (!dalloc((void **)&dn.tree_i, ti.size() * 4) || !dalloc((void **)&dn.tree_z, tz.size() * 8))
+            return fail(TPF_ERR_OOM, "device allocation failed (tree)");
+        if (!h2d(dn.tree_i, ti.data(), ti.size() * 4) || !h2d(dn.tree_z, tz.data(), tz.size() * 8))
+            return fail(TPF_ERR_DEVICE, "host-to-device copy failed (tree)");
+        dn.tree_levels = levels;
+    }
     // ---- ZIP shares
     if (net.zip) {
         if (!dalloc((void **)&dn.aI, n * 8) || !dalloc((void **)&dn.aP, n * 8))
@@ -384,6 +407,48 @@ static int finish_network(const std::vector<cd> &Y, int Nn, const std::vector<in
     return TPF_OK;
 }
 
+// Breadth-first layout of a connected network with n_bus - 1 branches (a tree): the
+// positions, parents, children ranges, levels and branch impedances the tree operator
+// walks.  Host work once per network.
+static void build_tree(tpf_network_s &net, int32_t n_branch, const int32_t *from, const int32_t *to,
+                       const double *r, const double *x) {
+    const int N = net.n_bus, slack = net.slack;
+    std::vector<std::vector<std::pair<int, int>>> adj(N);  // (neighbour, branch)
+    for (int k = 0; k < n_branch; ++k) adj[from[k]].push_back({to[k], k}), adj[to[k]].push_back({from[k], k});
+    std::vector<int> pos(N, -1), order, lev;
+    std::vector<int32_t> par, c0, c1;
+    std::vector<cd> zb;
+    order.push_back(slack);
+    pos[slack] = 0;
+    par.push_back(-1);
+    lev.push_back(0);
+    zb.push_back(0.0);
+    for (size_t h = 0; h < order.size(); ++h) {
+        const int u = order[h];
+        c0.push_back((int32_t)order.size());
+        for (auto [v, k] : adj[u]) {
+            if (pos[v] >= 0) continue;
+            pos[v] = (int)order.size();
+            order.push_back(v);
+            par.push_back((int32_t)h);
+            lev.push_back(lev[h] + 1);
+            zb.push_back(cd(r[k], x[k]));
+        }
+        c1.push_back((int32_t)order.size());
+    }
+    const int n = net.n;
+    net.tree_pq.assign(n + 1, -1);
+    for (int p = 1; p <= n; ++p) net.tree_pq[p] = order[p] < slack ? order[p] : order[p] - 1;
+    net.tree_parent = par;
+    net.tree_c0 = c0;
+    net.tree_c1 = c1;
+    net.tree_z = zb;
+    net.tree_level_start.clear();
+    for (int p = 0; p <= n; ++p)
+        if (p == 0 || lev[p] != lev[p - 1]) net.tree_level_start.push_back(p);
+    net.tree_level_start.push_back(n + 1);
+}
+
 extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
                                  const double *r, const double *x, int32_t slack_bus, double vs_re,
                                  double vs_im, tpf_network *out) {
@@ -416,7 +481,9 @@ extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t 
     } catch (const std::bad_alloc &) {
         return fail(TPF_ERR_OOM, "host allocation failed");
     }
-    return finish_network(Y, N, {slack_bus}, {cd(vs_re, vs_im)}, n_bus, slack_bus, out);
+    rc = finish_network(Y, N, {slack_bus}, {cd(vs_re, vs_im)}, n_bus, slack_bus, out);
+    if (rc == TPF_OK && n_branch == n_bus - 1) build_tree(**out, n_branch, from, to, r, x);
+    return rc;
 }
 
 extern "C" int tpf_build_network_3ph(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,

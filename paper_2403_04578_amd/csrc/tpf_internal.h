@@ -60,6 +60,13 @@ struct DeviceNet {
     double *yval = nullptr;      // [nnz][2]
     double *cval = nullptr;      // [n][2]
     // ZIP load shares per PQ bus (Eq. (2), alpha_Z = 0); NULL for constant-power loads.
+    // Radial single-phase networks, tree operator (fpi_tree.hip): breadth-first positions
+    // 0..n (0 = slack).  tree_i = [pq index][parent][first child][end of children] per
+    // position (4 (n+1) int32) then the level starts (tree_levels + 2 int32);
+    // tree_z = [position][z re, z im, w re, w im] doubles.
+    int tree_levels = 0;
+    int32_t *tree_i = nullptr;
+    double *tree_z = nullptr;
     double *aI = nullptr, *aP = nullptr;  // [n] each
     float zscale = 1.0f;                  // max_b |alpha_P| + |alpha_I| (bounds |I| / |S| with |V|)
     std::vector<void *> owned;   // every allocation above, freed with the network
@@ -85,6 +92,12 @@ struct tpf_network_s {
     // per PQ bus; empty for constant-power loads.
     bool zip = false;
     std::vector<double> alpha_i, alpha_p;
+    // Breadth-first tree of a radial single-phase network (empty otherwise): per position
+    // p = 0..n (0 = slack) the PQ index, parent position, children range and the impedance
+    // of the branch from the parent; level starts.  Children of a position are
+    // contiguous, and each level is a contiguous range of positions.
+    std::vector<int32_t> tree_pq, tree_parent, tree_c0, tree_c1, tree_level_start;
+    std::vector<tpf::cd> tree_z;
     std::mutex mu;
     std::vector<tpf::DeviceNet *> dev;  // indexed by HIP device id
 };
@@ -102,6 +115,9 @@ int device_net(tpf_network net, DeviceNet **out);
 int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype,
                          int64_t tau, double tol, int max_iter, const void *V0, void *V,
                          int32_t *iters, int8_t *status, unsigned long long *queue, hipStream_t stream);
+int launch_fpi_tree(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype, int64_t tau,
+                    double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
+                    unsigned long long *queue, hipStream_t stream);
 int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype,
                      int64_t tau, double tol, int max_iter, const void *V0, void *V, int32_t *iters,
                      int8_t *status, unsigned long long *queue, hipStream_t stream);
