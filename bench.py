@@ -239,6 +239,8 @@ def bench_other(args):
     esz = S.element_size()
     forms = {}
     runs = [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16")]
+    if not three:  # the tree operator needs a radial single-phase network
+        runs.append(("tree_fp64", "tree_fp64", net))
     if zip_loads:
         runs.append(("fp64_constant_power", "fp64", tpf.Network.from_feeder(f)))
     for key, mode, net in runs:
@@ -460,7 +462,7 @@ def main():
 
     forms = {}
     forms["fp64"] = time_form("fp64")  # the reference form is always timed
-    for mode in ("fp32", "mixed_bf16", "mixed_fp16"):
+    for mode in ("fp32", "mixed_bf16", "mixed_fp16", "tree_fp64"):
         if want(mode):
             forms[mode] = time_form(mode)
 

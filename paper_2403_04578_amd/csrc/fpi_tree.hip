@@ -9,13 +9,14 @@
 // and Z I = -D.  This is O(n) work per column instead of the dense 8 n^2, with the same
 // iterates up to rounding.
 //
-// One wavefront per power flow: lane l owns the breadth-first positions 1 + l + 64 r
-// (r < B) and keeps their S and V in registers.  The passes run level by level over a
-// per-wavefront LDS array of n + 1 complex values (J, then D in place); within a level
-// the positions are spread over the lanes, and a wavefront's LDS accesses complete in
-// order, so no workgroup barrier is needed.  Columns are dealt to wavefronts round
-// robin.  Per sweep each column reads and writes only LDS and registers; S, V0 and the
-// result cross HBM once.
+// A wavefront carries CPW power flows (columns) side by side, 64 / CPW lanes each: lane
+// l of a column owns the breadth-first positions 1 + l + (64 / CPW) r (r < B) and keeps
+// their S and V in registers.  The passes run level by level over a per-column LDS array
+// of n + 1 complex values (J, then D in place); within a level the positions are spread
+// over the column's lanes, and a wavefront's LDS accesses complete in order, so no
+// workgroup barrier is needed.  Columns are dealt to the slots round robin.  Per sweep
+// each column reads and writes only LDS and registers; S, V0 and the result cross HBM
+// once.
 #include "tpf_internal.h"
 
 namespace tpf {
@@ -24,20 +25,22 @@ namespace {
 
 constexpr int kTreeWaves = 4;
 
-template <typename IO, int B, bool ZIP>
+template <typename IO, int CPW, int B, bool ZIP>
 __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const int32_t *__restrict__ tree_i,
     const double *__restrict__ tree_z, int n, int levels, long long tau, double tol, int max_iter,
     const double *__restrict__ aP, const double *__restrict__ aI) {
+    constexpr int LPC = 64 / CPW;  // lanes per column
     extern __shared__ double lds[];
     const int np = n + 1;
     double *tz = lds;                                        // [np][4]: z, w per position
     double *za = tz + 4 * np;                                // [np][2]: alpha_P, alpha_I (ZIP)
-    double *Jw = za + (ZIP ? 2 * np : 0);                    // [waves][np][2]
-    int32_t *ti = reinterpret_cast<int32_t *>(Jw + kTreeWaves * 2 * np);  // [np][4], level starts
+    double *Jw = za + (ZIP ? 2 * np : 0);                    // [waves][CPW][np][2]
+    int32_t *ti = reinterpret_cast<int32_t *>(Jw + kTreeWaves * CPW * 2 * np);  // [np][4], level starts
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
+    const int slot = lane / LPC, sl = lane % LPC;  // column slot of the wavefront, lane within it
     for (int e = threadIdx.x; e < 4 * np; e += kTreeWaves * 64) tz[e] = tree_z[e];
     for (int e = threadIdx.x; e < 4 * np + levels + 2; e += kTreeWaves * 64) ti[e] = tree_i[e];
     if constexpr (ZIP) {
@@ -48,20 +51,24 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
         }
     }
     __syncthreads();
-    double *J = Jw + wave * 2 * np;
+    double *J = Jw + (wave * CPW + slot) * 2 * np;
     const int32_t *ls = ti + 4 * np;  // level L = positions [ls[L], ls[L+1])
-    if (lane == 0) J[0] = J[1] = 0.0;  // the slack's drop
+    if (sl == 0) J[0] = J[1] = 0.0;   // the slack's drop
 
-    const long long nwaves = (long long)gridDim.x * kTreeWaves;
-    for (long long c = (long long)blockIdx.x * kTreeWaves + wave; c < tau; c += nwaves) {
-        double sr[B], si[B], vr[B], vi[B];
+    // Column slots take columns round robin; a slot that finishes a column loads its next
+    // one at once, so the slots of a wavefront may be at different sweeps.
+    const long long nslots = (long long)gridDim.x * kTreeWaves * CPW;
+    long long c = ((long long)blockIdx.x * kTreeWaves + wave) * CPW + slot;
+    double sr[B], si[B], vr[B], vi[B];
+    int it = 0;
+    auto load = [&]() __attribute__((always_inline)) {
         int ok = 1;
 #pragma unroll
         for (int r = 0; r < B; ++r) {
-            const int p = 1 + lane + 64 * r;
+            const int p = 1 + sl + LPC * r;
             sr[r] = si[r] = vi[r] = 0.0;
             vr[r] = 1.0;
-            if (p <= n) {
+            if (c < tau && p <= n) {
                 const long long o = 2 * (c * n + ti[4 * p]);
                 sr[r] = (double)S[o];
                 si[r] = (double)S[o + 1];
@@ -73,102 +80,111 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
                 }
             }
         }
-        if (V0 && __ballot(!ok)) {  // the guard failed somewhere in the column: flat start
+        if (V0) {  // the guard failed somewhere in the column: flat start
 #pragma unroll
-            for (int r = 0; r < B; ++r) vr[r] = 1.0, vi[r] = 0.0;
+            for (int off = LPC / 2; off > 0; off >>= 1) ok &= __shfl_xor(ok, off);
+            if (!ok) {
+#pragma unroll
+                for (int r = 0; r < B; ++r) vr[r] = 1.0, vi[r] = 0.0;
+            }
         }
-        int it = 0;
-        while (true) {
-            // injections conj(S./V) (ZIP: alpha_P conj(S./V) + alpha_I conj(S)) into J
+        it = 0;
+    };
+    load();
+    while (__ballot(c < tau)) {
+        const bool live = c < tau;
+        // injections conj(S./V) (ZIP: alpha_P conj(S./V) + alpha_I conj(S)) into J
 #pragma unroll
-            for (int r = 0; r < B; ++r) {
-                const int p = 1 + lane + 64 * r;
-                if (p <= n) {
-                    const double inv = 1.0 / (vr[r] * vr[r] + vi[r] * vi[r]);
-                    double ir = (sr[r] * vr[r] + si[r] * vi[r]) * inv, ii = (sr[r] * vi[r] - si[r] * vr[r]) * inv;
-                    if constexpr (ZIP) {
-                        const double ap = za[2 * p], ai = za[2 * p + 1];
-                        ir = ap * ir + ai * sr[r];
-                        ii = ap * ii - ai * si[r];
-                    }
-                    J[2 * p] = ir;
-                    J[2 * p + 1] = ii;
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            if (p <= n) {
+                const double inv = 1.0 / (vr[r] * vr[r] + vi[r] * vi[r]);
+                double ir = (sr[r] * vr[r] + si[r] * vi[r]) * inv, ii = (sr[r] * vi[r] - si[r] * vr[r]) * inv;
+                if constexpr (ZIP) {
+                    const double ap = za[2 * p], ai = za[2 * p + 1];
+                    ir = ap * ir + ai * sr[r];
+                    ii = ap * ii - ai * si[r];
                 }
+                J[2 * p] = ir;
+                J[2 * p + 1] = ii;
             }
-            __builtin_amdgcn_wave_barrier();
-            // backward pass, deepest level first: J_b += J of b's children
-            for (int L = levels; L >= 1; --L) {
-                for (int p = ls[L] + lane; p < ls[L + 1]; p += 64) {
-                    double jr = J[2 * p], ji = J[2 * p + 1];
-                    for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
-                        jr += J[2 * ch];
-                        ji += J[2 * ch + 1];
-                    }
-                    J[2 * p] = jr;
-                    J[2 * p + 1] = ji;
+        }
+        __builtin_amdgcn_wave_barrier();
+        // backward pass, deepest level first: J_b += J of b's children
+        for (int L = levels; L >= 1; --L) {
+            for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                double jr = J[2 * p], ji = J[2 * p + 1];
+                for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
+                    jr += J[2 * ch];
+                    ji += J[2 * ch + 1];
                 }
-                __builtin_amdgcn_wave_barrier();
-            }
-            // forward pass, level 1 first: D_b = D_parent + z_b J_b (in place of J_b)
-            for (int L = 1; L <= levels; ++L) {
-                for (int p = ls[L] + lane; p < ls[L + 1]; p += 64) {
-                    const int par = ti[4 * p + 1];
-                    const double zr = tz[4 * p], zi = tz[4 * p + 1], jr = J[2 * p], ji = J[2 * p + 1];
-                    J[2 * p] = J[2 * par] + zr * jr - zi * ji;
-                    J[2 * p + 1] = J[2 * par + 1] + zr * ji + zi * jr;
-                }
-                __builtin_amdgcn_wave_barrier();
-            }
-            // V' = w + Z I = w - D; step max |V' - V|
-            double dmax = 0.0;
-            int bad = 0;
-#pragma unroll
-            for (int r = 0; r < B; ++r) {
-                const int p = 1 + lane + 64 * r;
-                if (p <= n) {
-                    const double nr = tz[4 * p + 2] - J[2 * p], ni = tz[4 * p + 3] - J[2 * p + 1];
-                    const double er = nr - vr[r], ei = ni - vi[r];
-                    const double e = er * er + ei * ei;
-                    bad |= !(e < HUGE_VAL);
-                    dmax = e > dmax ? e : dmax;
-                    vr[r] = nr;
-                    vi[r] = ni;
-                }
-            }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off));
-            bad = __ballot(bad) != 0;
-            ++it;
-            const bool conv = !bad && sqrt(dmax) < tol;
-            if (bad || conv || it >= max_iter) {
-#pragma unroll
-                for (int r = 0; r < B; ++r) {
-                    const int p = 1 + lane + 64 * r;
-                    if (p <= n) {
-                        const long long o = 2 * (c * n + ti[4 * p]);
-                        Vout[o] = (IO)vr[r];
-                        Vout[o + 1] = (IO)vi[r];
-                    }
-                }
-                if (lane == 0) {
-                    iters_out[c] = it;
-                    status_out[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
-                }
-                break;
+                J[2 * p] = jr;
+                J[2 * p + 1] = ji;
             }
             __builtin_amdgcn_wave_barrier();
         }
+        // forward pass, level 1 first: D_b = D_parent + z_b J_b (in place of J_b)
+        for (int L = 1; L <= levels; ++L) {
+            for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                const int par = ti[4 * p + 1];
+                const double zr = tz[4 * p], zi = tz[4 * p + 1], jr = J[2 * p], ji = J[2 * p + 1];
+                J[2 * p] = J[2 * par] + zr * jr - zi * ji;
+                J[2 * p + 1] = J[2 * par + 1] + zr * ji + zi * jr;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        // V' = w + Z I = w - D; step max |V' - V| per column
+        double dmax = 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            if (p <= n) {
+                const double nr = tz[4 * p + 2] - J[2 * p], ni = tz[4 * p + 3] - J[2 * p + 1];
+                const double er = nr - vr[r], ei = ni - vi[r];
+                const double e = er * er + ei * ei;
+                bad |= !(e < HUGE_VAL);
+                dmax = e > dmax ? e : dmax;
+                vr[r] = nr;
+                vi[r] = ni;
+            }
+        }
+#pragma unroll
+        for (int off = LPC / 2; off > 0; off >>= 1) {
+            dmax = fmax(dmax, __shfl_xor(dmax, off));
+            bad |= __shfl_xor(bad, off);
+        }
+        ++it;
+        const bool conv = !bad && sqrt(dmax) < tol;
+        if (live && (bad || conv || it >= max_iter)) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const int p = 1 + sl + LPC * r;
+                if (p <= n) {
+                    const long long o = 2 * (c * n + ti[4 * p]);
+                    Vout[o] = (IO)vr[r];
+                    Vout[o + 1] = (IO)vi[r];
+                }
+            }
+            if (sl == 0) {
+                iters_out[c] = it;
+                status_out[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            }
+            c += nslots;
+            load();
+        }
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
-template <typename IO, int B, bool ZIP>
+template <typename IO, int CPW, int B, bool ZIP>
 int launch_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
               const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
     const int n = net.n, np = n + 1, levels = dn.tree_levels;
-    const size_t lds = (size_t)4 * np * 8 + (ZIP ? (size_t)2 * np * 8 : 0) + (size_t)kTreeWaves * 2 * np * 8 +
+    const size_t lds = (size_t)4 * np * 8 + (ZIP ? (size_t)2 * np * 8 : 0) + (size_t)kTreeWaves * CPW * 2 * np * 8 +
                        (size_t)(4 * np + levels + 2) * 4;
     if (lds > (size_t)160 * 1024) return fail(TPF_ERR_UNSUPPORTED, "tree operator: network too large for LDS");
-    auto k = fpi_tree_kernel<IO, B, ZIP>;
+    auto k = fpi_tree_kernel<IO, CPW, B, ZIP>;
     if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
     int per_cu = 0;
@@ -177,30 +193,32 @@ int launch_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int6
     int dev = 0, cus = 256;
     (void)hipGetDevice(&dev);
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const long long per_block = (long long)kTreeWaves * CPW;
     const long long blocks =
-        std::max<long long>(1, std::min<long long>((long long)cus * per_cu, (tau + kTreeWaves - 1) / kTreeWaves));
+        std::max<long long>(1, std::min<long long>((long long)cus * per_cu, (tau + per_block - 1) / per_block));
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTreeWaves * 64), lds, st, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.tree_i, dn.tree_z, n, levels, (long long)tau, tol, max_iter,
                        (const double *)dn.aP, (const double *)dn.aI);
     return TPF_OK;
 }
 
-template <typename IO, int B>
+template <typename IO, int CPW, int B>
 int launch_b(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
              const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
-    if (dn.aP) return launch_as<IO, B, true>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    return launch_as<IO, B, false>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (dn.aP) return launch_as<IO, CPW, B, true>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    return launch_as<IO, CPW, B, false>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
 }
 
+// Columns per wavefront: 4 (16 lanes each) up to 128 buses, 2 up to 256, then 1.
 template <typename IO>
 int launch_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
               const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
     const int n = net.n;
-    if (n <= 64) return launch_b<IO, 1>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    if (n <= 128) return launch_b<IO, 2>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    if (n <= 256) return launch_b<IO, 4>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    if (n <= 512) return launch_b<IO, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    if (n <= 1024) return launch_b<IO, 16>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 64) return launch_b<IO, 4, 4>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 128) return launch_b<IO, 4, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 256) return launch_b<IO, 2, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 512) return launch_b<IO, 1, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 1024) return launch_b<IO, 1, 16>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     return fail(TPF_ERR_UNSUPPORTED, "tree operator: up to 1,024 PQ buses");
 }
 
