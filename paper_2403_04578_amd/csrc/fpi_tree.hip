@@ -209,13 +209,14 @@ int launch_b(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64
     return launch_as<IO, CPW, B, false>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
 }
 
-// Columns per wavefront: 4 (16 lanes each) up to 128 buses, 2 up to 256, then 1.
+// Columns per wavefront: 8 (8 lanes each) up to 128 buses, 2 up to 256, then 1.  (At 99
+// buses: 1.40 ms per year with 8 columns, 1.51 with 4, 2.48 with 1.)
 template <typename IO>
 int launch_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
               const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
     const int n = net.n;
-    if (n <= 64) return launch_b<IO, 4, 4>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    if (n <= 128) return launch_b<IO, 4, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 64) return launch_b<IO, 8, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 128) return launch_b<IO, 8, 16>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     if (n <= 256) return launch_b<IO, 2, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     if (n <= 512) return launch_b<IO, 1, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     if (n <= 1024) return launch_b<IO, 1, 16>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
