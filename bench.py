@@ -301,8 +301,8 @@ def bench_other(args):
 
 def bench_scaling(args):
     """Solve time of the kernels alone against network size (demand nodes 9 .. 1,999 at
-    500 columns) and against the number of columns (10 .. 525,600 at 499 nodes), FP64
-    and mixed FP16 forms, tol 1e-6: the shapes of the paper's size and batch scaling
+    500 columns) and against the number of columns (10 .. 525,600 at 499 nodes), FP64,
+    mixed FP16 and tree-operator forms, tol 1e-6: the shapes of the paper's size and batch scaling
     figures on synthetic feeders.  Median of 3 timed solves after one warm-up.  Prints
     one JSON line."""
     import torch
@@ -321,7 +321,9 @@ def bench_scaling(args):
         build_s = time.perf_counter() - t0
         S = torch.from_numpy(W.profile_minute_year(f, steps=tau)).to(dev)
         rec = {"n_nodes": n_bus - 1, "tau": tau, "build_s": build_s}
-        for mode in ("fp64", "mixed_fp16"):
+        for mode in ("fp64", "mixed_fp16", "tree_fp64"):
+            if mode == "tree_fp64" and n_bus - 1 > 1024:  # the tree kernel's limit
+                continue
             out = tpf.alloc_outputs(net, S, mode, mismatch=False)
             tpf.solve_timeseries(net, S, tol, max_iter, mode, out=out)
             torch.cuda.synchronize()
