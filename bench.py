@@ -238,9 +238,7 @@ def bench_other(args):
     stream = torch.cuda.current_stream(dev)
     esz = S.element_size()
     forms = {}
-    runs = [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16")]
-    if not three:  # the tree operator needs a radial single-phase network
-        runs.append(("tree_fp64", "tree_fp64", net))
+    runs = [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16", "tree_fp64")]
     if zip_loads:
         runs.append(("fp64_constant_power", "fp64", tpf.Network.from_feeder(f)))
     for key, mode, net in runs:

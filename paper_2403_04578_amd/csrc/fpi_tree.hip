@@ -1,4 +1,4 @@
-// FP64 sweeps with the tree operator, for radial (tree) single-phase networks.
+// FP64 sweeps with the tree operator, for radial (tree) networks, single- or three-phase.
 //
 // On a radial feeder without shunts, Z = -Y_dd^-1 is minus the path-impedance matrix:
 // (Y_dd^-1)_ij is the sum of the impedances of the branches shared by the paths from the
@@ -177,6 +177,206 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
     }
 }
 
+// Three-phase networks: the same passes with three phase nodes per position; a branch
+// carries a 3x3 impedance matrix, so the forward pass is D_b = D_parent + Z_abc,b J_b.
+// Position p's node f is demand node 3 pq(p) + f.  tz: per position Z_abc (9 complex)
+// then w of the three phases; J: per column [np][3] complex.
+template <typename IO, int CPW, int B>
+__global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_kernel(
+    const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
+    int8_t *__restrict__ status_out, const IO *__restrict__ V0, const int32_t *__restrict__ tree_i,
+    const double *__restrict__ tree_z, int nb, int levels, long long tau, double tol, int max_iter) {
+    constexpr int LPC = 64 / CPW;
+    constexpr int TZ = 24;  // doubles per position in tz
+    extern __shared__ double lds[];
+    const int np = nb + 1;   // positions (buses)
+    const int n = 3 * nb;    // demand nodes per column
+    double *tz = lds;                                        // [np][24]
+    double *Jw = tz + TZ * np;                               // [waves][CPW][np][6]
+    int32_t *ti = reinterpret_cast<int32_t *>(Jw + kTreeWaves * CPW * 6 * np);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int slot = lane / LPC, sl = lane % LPC;
+    for (int e = threadIdx.x; e < TZ * np; e += kTreeWaves * 64) tz[e] = tree_z[e];
+    for (int e = threadIdx.x; e < 4 * np + levels + 2; e += kTreeWaves * 64) ti[e] = tree_i[e];
+    __syncthreads();
+    double *J = Jw + (wave * CPW + slot) * 6 * np;
+    const int32_t *ls = ti + 4 * np;
+    if (sl == 0)
+        for (int e = 0; e < 6; ++e) J[e] = 0.0;  // the slack's drop
+
+    const long long nslots = (long long)gridDim.x * kTreeWaves * CPW;
+    long long c = ((long long)blockIdx.x * kTreeWaves + wave) * CPW + slot;
+    double sr[B][3], si[B][3], vr[B][3], vi[B][3];
+    int it = 0;
+    auto load = [&]() __attribute__((always_inline)) {
+        int ok = 1;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                sr[r][f] = si[r][f] = vi[r][f] = 0.0;
+                vr[r][f] = 1.0;
+                if (c < tau && p <= nb) {
+                    const long long o = 2 * (c * n + 3 * ti[4 * p] + f);
+                    sr[r][f] = (double)S[o];
+                    si[r][f] = (double)S[o + 1];
+                    if (V0) {
+                        vr[r][f] = (double)V0[o];
+                        vi[r][f] = (double)V0[o + 1];
+                        const double m2 = vr[r][f] * vr[r][f] + vi[r][f] * vi[r][f];
+                        ok &= (m2 >= 0.25 && m2 <= 2.25) ? 1 : 0;
+                    }
+                }
+            }
+        }
+        if (V0) {
+#pragma unroll
+            for (int off = LPC / 2; off > 0; off >>= 1) ok &= __shfl_xor(ok, off);
+            if (!ok) {
+#pragma unroll
+                for (int r = 0; r < B; ++r)
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) vr[r][f] = 1.0, vi[r][f] = 0.0;
+            }
+        }
+        it = 0;
+    };
+    load();
+    while (__ballot(c < tau)) {
+        const bool live = c < tau;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            if (p <= nb) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const double inv = 1.0 / (vr[r][f] * vr[r][f] + vi[r][f] * vi[r][f]);
+                    J[6 * p + 2 * f] = (sr[r][f] * vr[r][f] + si[r][f] * vi[r][f]) * inv;
+                    J[6 * p + 2 * f + 1] = (sr[r][f] * vi[r][f] - si[r][f] * vr[r][f]) * inv;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int L = levels; L >= 1; --L) {
+            for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                double j[6];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) j[e] = J[6 * p + e];
+                for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) j[e] += J[6 * ch + e];
+                }
+#pragma unroll
+                for (int e = 0; e < 6; ++e) J[6 * p + e] = j[e];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int L = 1; L <= levels; ++L) {
+            for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                const int par = ti[4 * p + 1];
+                double j[6], d[6];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) j[e] = J[6 * p + e], d[e] = J[6 * par + e];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const double zr = tz[TZ * p + 2 * (3 * a + b)], zi = tz[TZ * p + 2 * (3 * a + b) + 1];
+                        d[2 * a] += zr * j[2 * b] - zi * j[2 * b + 1];
+                        d[2 * a + 1] += zr * j[2 * b + 1] + zi * j[2 * b];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 6; ++e) J[6 * p + e] = d[e];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        double dmax = 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            if (p <= nb) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const double nr = tz[TZ * p + 18 + 2 * f] - J[6 * p + 2 * f];
+                    const double ni = tz[TZ * p + 19 + 2 * f] - J[6 * p + 2 * f + 1];
+                    const double er = nr - vr[r][f], ei = ni - vi[r][f];
+                    const double e = er * er + ei * ei;
+                    bad |= !(e < HUGE_VAL);
+                    dmax = e > dmax ? e : dmax;
+                    vr[r][f] = nr;
+                    vi[r][f] = ni;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = LPC / 2; off > 0; off >>= 1) {
+            dmax = fmax(dmax, __shfl_xor(dmax, off));
+            bad |= __shfl_xor(bad, off);
+        }
+        ++it;
+        const bool conv = !bad && sqrt(dmax) < tol;
+        if (live && (bad || conv || it >= max_iter)) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const int p = 1 + sl + LPC * r;
+                if (p <= nb) {
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        const long long o = 2 * (c * n + 3 * ti[4 * p] + f);
+                        Vout[o] = (IO)vr[r][f];
+                        Vout[o + 1] = (IO)vi[r][f];
+                    }
+                }
+            }
+            if (sl == 0) {
+                iters_out[c] = it;
+                status_out[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            }
+            c += nslots;
+            load();
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <typename IO, int CPW, int B>
+int launch3_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
+               const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
+    const int nb = net.n / 3, np = nb + 1, levels = dn.tree_levels;
+    const size_t lds = (size_t)24 * np * 8 + (size_t)kTreeWaves * CPW * 6 * np * 8 + (size_t)(4 * np + levels + 2) * 4;
+    if (lds > (size_t)160 * 1024) return fail(TPF_ERR_UNSUPPORTED, "tree operator: network too large for LDS");
+    auto k = fpi_tree3_kernel<IO, CPW, B>;
+    if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kTreeWaves * 64, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const long long per_block = (long long)kTreeWaves * CPW;
+    const long long blocks =
+        std::max<long long>(1, std::min<long long>((long long)cus * per_cu, (tau + per_block - 1) / per_block));
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTreeWaves * 64), lds, st, (const IO *)S, (IO *)V, iters,
+                       status, (const IO *)V0, dn.tree_i, dn.tree_z, nb, levels, (long long)tau, tol, max_iter);
+    return TPF_OK;
+}
+
+// Three-phase: 2 columns per wavefront up to 128 buses, then 1, up to 512 buses.
+template <typename IO>
+int launch3_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
+               const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
+    const int nb = net.n / 3;
+    if (nb <= 128) return launch3_as<IO, 2, 4>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (nb <= 256) return launch3_as<IO, 1, 4>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (nb <= 512) return launch3_as<IO, 1, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    return fail(TPF_ERR_UNSUPPORTED, "tree operator: up to 512 three-phase buses");
+}
+
 template <typename IO, int CPW, int B, bool ZIP>
 int launch_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
               const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
@@ -228,8 +428,12 @@ int launch_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int6
 int launch_fpi_tree(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype, int64_t tau,
                     double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
                     unsigned long long *, hipStream_t stream) {
-    if (!dn.tree_i)
-        return fail(TPF_ERR_UNSUPPORTED, "the tree operator needs a radial single-phase network (n_bus - 1 branches)");
+    if (!dn.tree_i) return fail(TPF_ERR_UNSUPPORTED, "the tree operator needs a radial network (n_bus - 1 branches)");
+    if (dn.tree_phases == 3) {
+        if (dtype == TPF_C128)
+            return launch3_io<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);
+        return launch3_io<float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);
+    }
     if (dtype == TPF_C128)
         return launch_io<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);
     return launch_io<float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);

@@ -256,28 +256,35 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
             !h2d(dn.yval, yv.data(), nnz * 16) || !h2d(dn.cval, cv.data(), n * 16))
             return fail(TPF_ERR_DEVICE, "host-to-device copy failed (network staging)");
     }
-    // ---- breadth-first tree (radial single-phase networks)
+    // ---- breadth-first tree (radial networks): per position the branch impedance
+    // (phases x phases) and w of its phases, as doubles
     if (!net.tree_pq.empty()) {
         const int levels = (int)net.tree_level_start.size() - 2;
-        std::vector<int32_t> ti(4 * (n + 1) + levels + 2);
-        std::vector<double> tz(4 * (n + 1));
-        for (int p = 0; p <= n; ++p) {
+        const int np = (int)net.tree_pq.size(), ph = net.tree_phases, pp = ph * ph, stride = 2 * (pp + ph);
+        std::vector<int32_t> ti(4 * np + levels + 2);
+        std::vector<double> tz((size_t)stride * np);
+        for (int p = 0; p < np; ++p) {
             ti[4 * p] = net.tree_pq[p];
             ti[4 * p + 1] = net.tree_parent[p];
             ti[4 * p + 2] = net.tree_c0[p];
             ti[4 * p + 3] = net.tree_c1[p];
-            tz[4 * p] = net.tree_z[p].real();
-            tz[4 * p + 1] = net.tree_z[p].imag();
-            const tpf::cd wq = p > 0 ? net.w[net.tree_pq[p]] : tpf::cd(0.0);
-            tz[4 * p + 2] = wq.real();
-            tz[4 * p + 3] = wq.imag();
+            for (int e = 0; e < pp; ++e) {
+                tz[(size_t)stride * p + 2 * e] = net.tree_z[(size_t)pp * p + e].real();
+                tz[(size_t)stride * p + 2 * e + 1] = net.tree_z[(size_t)pp * p + e].imag();
+            }
+            for (int f = 0; f < ph; ++f) {
+                const tpf::cd wq = p > 0 ? net.w[ph * net.tree_pq[p] + f] : tpf::cd(0.0);
+                tz[(size_t)stride * p + 2 * pp + 2 * f] = wq.real();
+                tz[(size_t)stride * p + 2 * pp + 2 * f + 1] = wq.imag();
+            }
         }
-        for (int L = 0; L < levels + 2; ++L) ti[4 * (n + 1) + L] = net.tree_level_start[L];
+        for (int L = 0; L < levels + 2; ++L) ti[4 * np + L] = net.tree_level_start[L];
         if (!dalloc((void **)&dn.tree_i, ti.size() * 4) || !dalloc((void **)&dn.tree_z, tz.size() * 8))
             return fail(TPF_ERR_OOM, "device allocation failed (tree)");
         if (!h2d(dn.tree_i, ti.data(), ti.size() * 4) || !h2d(dn.tree_z, tz.data(), tz.size() * 8))
             return fail(TPF_ERR_DEVICE, "host-to-device copy failed (tree)");
         dn.tree_levels = levels;
+        dn.tree_phases = ph;
     }
     // ---- ZIP shares
     if (net.zip) {
@@ -408,21 +415,22 @@ static int finish_network(const std::vector<cd> &Y, int Nn, const std::vector<in
 }
 
 // Breadth-first layout of a connected network with n_bus - 1 branches (a tree): the
-// positions, parents, children ranges, levels and branch impedances the tree operator
-// walks.  Host work once per network.
+// positions (buses), parents, children ranges, levels and branch impedances (phases x
+// phases per branch, row-major, in zbr) the tree operator walks.  Host work once per
+// network.
 static void build_tree(tpf_network_s &net, int32_t n_branch, const int32_t *from, const int32_t *to,
-                       const double *r, const double *x) {
+                       const std::vector<cd> &zbr, int phases) {
     const int N = net.n_bus, slack = net.slack;
     std::vector<std::vector<std::pair<int, int>>> adj(N);  // (neighbour, branch)
     for (int k = 0; k < n_branch; ++k) adj[from[k]].push_back({to[k], k}), adj[to[k]].push_back({from[k], k});
     std::vector<int> pos(N, -1), order, lev;
     std::vector<int32_t> par, c0, c1;
-    std::vector<cd> zb;
+    const int pp = phases * phases;
+    std::vector<cd> zb(pp, 0.0);
     order.push_back(slack);
     pos[slack] = 0;
     par.push_back(-1);
     lev.push_back(0);
-    zb.push_back(0.0);
     for (size_t h = 0; h < order.size(); ++h) {
         const int u = order[h];
         c0.push_back((int32_t)order.size());
@@ -432,11 +440,12 @@ static void build_tree(tpf_network_s &net, int32_t n_branch, const int32_t *from
             order.push_back(v);
             par.push_back((int32_t)h);
             lev.push_back(lev[h] + 1);
-            zb.push_back(cd(r[k], x[k]));
+            zb.insert(zb.end(), zbr.begin() + (size_t)pp * k, zbr.begin() + (size_t)pp * (k + 1));
         }
         c1.push_back((int32_t)order.size());
     }
-    const int n = net.n;
+    const int n = N - 1;  // positions 1..n are the non-slack buses
+    net.tree_phases = phases;
     net.tree_pq.assign(n + 1, -1);
     for (int p = 1; p <= n; ++p) net.tree_pq[p] = order[p] < slack ? order[p] : order[p] - 1;
     net.tree_parent = par;
@@ -482,7 +491,15 @@ extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t 
         return fail(TPF_ERR_OOM, "host allocation failed");
     }
     rc = finish_network(Y, N, {slack_bus}, {cd(vs_re, vs_im)}, n_bus, slack_bus, out);
-    if (rc == TPF_OK && n_branch == n_bus - 1) build_tree(**out, n_branch, from, to, r, x);
+    if (rc == TPF_OK && n_branch == n_bus - 1) {
+        try {
+            std::vector<cd> zbr(n_branch);
+            for (int k = 0; k < n_branch; ++k) zbr[k] = cd(r[k], x[k]);
+            build_tree(**out, n_branch, from, to, zbr, 1);
+        } catch (const std::bad_alloc &) {  // the tree operator then reports the network unsupported
+            (*out)->tree_pq.clear();
+        }
+    }
     return rc;
 }
 
@@ -535,7 +552,18 @@ extern "C" int tpf_build_network_3ph(int32_t n_bus, int32_t n_branch, const int3
     const std::vector<int> sn = {3 * slack_bus, 3 * slack_bus + 1, 3 * slack_bus + 2};
     const std::vector<cd> vs = {cd(vs_abc[0], vs_abc[1]), cd(vs_abc[2], vs_abc[3]), cd(vs_abc[4], vs_abc[5])};
     rc = finish_network(Y, Nn, sn, vs, n_bus, slack_bus, out);
-    if (rc == TPF_OK) (*out)->phases = 3;
+    if (rc == TPF_OK) {
+        (*out)->phases = 3;
+        if (n_branch == n_bus - 1) {
+            try {
+                std::vector<cd> zbr((size_t)9 * n_branch);
+                for (size_t e = 0; e < zbr.size(); ++e) zbr[e] = cd(zabc[2 * e], zabc[2 * e + 1]);
+                build_tree(**out, n_branch, from, to, zbr, 3);
+            } catch (const std::bad_alloc &) {
+                (*out)->tree_pq.clear();
+            }
+        }
+    }
     return rc;
 }
 

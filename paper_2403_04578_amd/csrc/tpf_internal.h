@@ -60,11 +60,12 @@ struct DeviceNet {
     double *yval = nullptr;      // [nnz][2]
     double *cval = nullptr;      // [n][2]
     // ZIP load shares per PQ bus (Eq. (2), alpha_Z = 0); NULL for constant-power loads.
-    // Radial single-phase networks, tree operator (fpi_tree.hip): breadth-first positions
-    // 0..n (0 = slack).  tree_i = [pq index][parent][first child][end of children] per
-    // position (4 (n+1) int32) then the level starts (tree_levels + 2 int32);
-    // tree_z = [position][z re, z im, w re, w im] doubles.
+    // Radial networks, tree operator (fpi_tree.hip): breadth-first positions 0..n_bus-1
+    // (0 = slack).  tree_i = [pq bus][parent][first child][end of children] per position
+    // (4 n_bus int32) then the level starts (tree_levels + 2 int32); tree_z = per position
+    // the branch impedance (phases x phases complex) then w of its phases, as doubles.
     int tree_levels = 0;
+    int tree_phases = 1;
     int32_t *tree_i = nullptr;
     double *tree_z = nullptr;
     double *aI = nullptr, *aP = nullptr;  // [n] each
@@ -97,7 +98,8 @@ struct tpf_network_s {
     // of the branch from the parent; level starts.  Children of a position are
     // contiguous, and each level is a contiguous range of positions.
     std::vector<int32_t> tree_pq, tree_parent, tree_c0, tree_c1, tree_level_start;
-    std::vector<tpf::cd> tree_z;
+    std::vector<tpf::cd> tree_z;  // phases x phases per position
+    int tree_phases = 1;
     std::mutex mu;
     std::vector<tpf::DeviceNet *> dev;  // indexed by HIP device id
 };

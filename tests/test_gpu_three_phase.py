@@ -79,3 +79,23 @@ def test_three_phase_tensor_and_warm_start(gpu):
     assert same.mean() > 0.99
     assert np.abs(V.cpu().numpy().reshape(-1, 297)[same] - ref.V[same]).max() < 1e-9
     assert int(it[0].max()) == 1  # scenario 0 starts at its own solution
+
+
+def test_three_phase_tree_operator(gpu, feeder3):
+    """The tree operator with 3x3 branch blocks: the FP64 iterates up to rounding."""
+    f, net, onet = feeder3
+    S = W.profile_minute_year(f, steps=300, t0=2222)
+    for dt in (torch.complex128, torch.complex64):
+        Sd = _dev(S, gpu, dt)
+        V, it, st = tpf.solve_timeseries(net, Sd, tol=1e-9, max_iter=100, mode="tree_fp64")
+        Sh = Sd.cpu().numpy().astype(np.complex128)
+        ref = oracle.fpi(onet, Sh, 1e-9, 100)
+        ig = it.cpu().numpy()
+        same = ig == ref.iters
+        assert same.mean() > 0.99 and int(st.max()) == tpf.ST_CONVERGED
+        bound = 1e-9 if dt == torch.complex128 else 2e-7
+        assert np.abs(V.cpu().numpy().astype(np.complex128)[same] - ref.V[same]).max() < bound
+    # with a warm start from the solution, one sweep
+    V0 = torch.from_numpy(ref.V).to(gpu)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-8, max_iter=100, mode="tree_fp64", V0=V0)
+    assert int(it.max()) == 1

@@ -123,15 +123,18 @@ def test_tree_zip_loads(gpu):
     _compare(onet, S, V, it, st, 1e-9, 100, 1e-9, ref=oracle.fpi_zip(onet, S, ai, ap, 1e-9, 100))
 
 
-def test_tree_refuses_meshed_and_three_phase(gpu):
+def test_tree_refuses_meshed(gpu):
     meshed = tpf.Network(4, [0, 1, 2, 0], [1, 2, 3, 3], [0.01] * 4, [0.02] * 4)
     S = _dev(np.full((3, 3), 0.01 + 0.005j), gpu)
     with pytest.raises(tpf.TpfError) as e:
         tpf.solve_timeseries(meshed, S, tol=1e-9, max_iter=10, mode="tree_fp64")
     assert e.value.code == tpf.TPF_ERR_UNSUPPORTED
-    f3 = W.make_feeder_3ph(10)
-    net3 = tpf.Network.from_feeder_3ph(f3)
-    with pytest.raises(tpf.TpfError) as e:
-        tpf.solve_timeseries(net3, _dev(W.profile_minute_year(f3, steps=4), gpu), tol=1e-9, max_iter=10,
-                             mode="tree_fp64")
-    assert e.value.code == tpf.TPF_ERR_UNSUPPORTED
+
+
+def test_tree_two_bus_network(gpu):
+    z = 0.05 + 0.08j
+    net = tpf.Network(2, [0], [1], [z.real], [z.imag])
+    onet = oracle.build_network(2, [0], [1], [z.real], [z.imag])
+    S = np.array([[0.5 + 0.2j], [0.0], [1.0 + 0.3j]])
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-12, max_iter=200, mode="tree_fp64")
+    _compare(onet, S, V, it, st, 1e-12, 200, 1e-12)
