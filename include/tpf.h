@@ -73,8 +73,9 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
  *             -Z is the path-impedance matrix, so Z I = -D with branch currents
  *             J_b = I_b + sum over b's children of J (leaves to slack) and drops
  *             D_b = D_parent + z_b J_b (slack to leaves).  Same iterates up to rounding,
- *             O(n) instead of 8 n^2 flops per column and sweep.  Needs a single-phase
- *             network with n_bus - 1 branches (a tree) and n <= 1024; returns
+ *             O(n) instead of 8 n^2 flops per column and sweep.  Needs a network with
+ *             n_bus - 1 branches (a tree): single-phase with n <= 1024 PQ buses, or
+ *             three-phase (3x3 blocks per branch) with at most 512 PQ buses; returns
  *             TPF_ERR_UNSUPPORTED otherwise. */
 enum { TPF_MODE_FP64 = 0, TPF_MODE_FP32 = 1, TPF_MODE_MIXED_BF16 = 2, TPF_MODE_MIXED_FP16 = 3, TPF_MODE_TREE_FP64 = 4 };
 

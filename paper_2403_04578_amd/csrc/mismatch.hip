@@ -67,7 +67,7 @@ struct Pair2 {
     typedef IO T __attribute__((ext_vector_type(2)));
 };
 
-constexpr int kCsrLdsCap = 32 * 1024;
+constexpr int kCsrLdsCap = 96 * 1024;  // three-phase Y_dd has ~9x the nonzeros of a single-phase one
 constexpr int kTileVBytes = 64 * 1024;  // LDS for the tile's copy of V
 constexpr int kBatch = 8;               // independent loads issued before their data is used
 
