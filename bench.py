@@ -239,6 +239,8 @@ def bench_other(args):
     esz = S.element_size()
     forms = {}
     runs = [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16", "tree_fp64")]
+    if not three:  # the FP32 tree form is single-phase
+        runs.append(("tree_fp32", "tree_fp32", net))
     if zip_loads:
         runs.append(("fp64_constant_power", "fp64", tpf.Network.from_feeder(f)))
     for key, mode, net in runs:
@@ -319,8 +321,8 @@ def bench_scaling(args):
         build_s = time.perf_counter() - t0
         S = torch.from_numpy(W.profile_minute_year(f, steps=tau)).to(dev)
         rec = {"n_nodes": n_bus - 1, "tau": tau, "build_s": build_s}
-        for mode in ("fp64", "mixed_fp16", "tree_fp64"):
-            if mode == "tree_fp64" and n_bus - 1 > 1024:  # the tree kernel's limit
+        for mode in ("fp64", "mixed_fp16", "tree_fp64", "tree_fp32"):
+            if mode.startswith("tree") and n_bus - 1 > 1024:  # the tree kernel's limit
                 continue
             out = tpf.alloc_outputs(net, S, mode, mismatch=False)
             tpf.solve_timeseries(net, S, tol, max_iter, mode, out=out)
@@ -462,7 +464,7 @@ def main():
 
     forms = {}
     forms["fp64"] = time_form("fp64")  # the reference form is always timed
-    for mode in ("fp32", "mixed_bf16", "mixed_fp16", "tree_fp64"):
+    for mode in ("fp32", "mixed_bf16", "mixed_fp16", "tree_fp64", "tree_fp32"):
         if want(mode):
             forms[mode] = time_form(mode)
 

@@ -77,7 +77,16 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
  *             n_bus - 1 branches (a tree): single-phase with n <= 1024 PQ buses, or
  *             three-phase (3x3 blocks per branch) with at most 512 PQ buses; returns
  *             TPF_ERR_UNSUPPORTED otherwise. */
-enum { TPF_MODE_FP64 = 0, TPF_MODE_FP32 = 1, TPF_MODE_MIXED_BF16 = 2, TPF_MODE_MIXED_FP16 = 3, TPF_MODE_TREE_FP64 = 4 };
+/* TREE_FP32   the tree operator in FP32 arithmetic with the state kept as the FP32 drop
+ *             V - w (as in FP32 mode; tol >= 5e-7 pu); single-phase networks only. */
+enum {
+    TPF_MODE_FP64 = 0,
+    TPF_MODE_FP32 = 1,
+    TPF_MODE_MIXED_BF16 = 2,
+    TPF_MODE_MIXED_FP16 = 3,
+    TPF_MODE_TREE_FP64 = 4,
+    TPF_MODE_TREE_FP32 = 5
+};
 
 /* Per-column outcome written to status_out. */
 enum { TPF_ST_CONVERGED = 0, TPF_ST_MAX_ITER = 1, TPF_ST_NONFINITE = 2 };

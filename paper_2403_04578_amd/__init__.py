@@ -27,11 +27,11 @@ TPF_ERR_OOM = -4
 TPF_ERR_UNSUPPORTED = -5
 
 TPF_C64, TPF_C128 = 0, 1
-MODE_FP64, MODE_FP32, MODE_MIXED_BF16, MODE_MIXED_FP16, MODE_TREE_FP64 = 0, 1, 2, 3, 4
+MODE_FP64, MODE_FP32, MODE_MIXED_BF16, MODE_MIXED_FP16, MODE_TREE_FP64, MODE_TREE_FP32 = 0, 1, 2, 3, 4, 5
 ST_CONVERGED, ST_MAX_ITER, ST_NONFINITE = 0, 1, 2
 
 _MODES = {"fp64": MODE_FP64, "fp32": MODE_FP32, "mixed_bf16": MODE_MIXED_BF16, "mixed_fp16": MODE_MIXED_FP16,
-          "tree_fp64": MODE_TREE_FP64}
+          "tree_fp64": MODE_TREE_FP64, "tree_fp32": MODE_TREE_FP32}
 
 
 class TpfError(RuntimeError):
@@ -207,7 +207,7 @@ def solve_timeseries(net: Network, S, tol: float, max_iter: int, mode="fp64", V0
                      mismatch: bool = False, out=None):
     """Algorithm 1 over S [T, n] (CUDA complex tensor).  Returns (V, iters, status[, mismatch]).
 
-    ``mode``: "fp64" | "fp32" | "mixed_bf16" | "mixed_fp16" | "tree_fp64" (or the MODE_* ints).
+    ``mode``: "fp64" | "fp32" | "mixed_bf16" | "mixed_fp16" | "tree_fp64" | "tree_fp32" (or the MODE_* ints).
     ``V0``: optional start voltages [T, n] (same dtype); guarded columns fall back to flat.
     """
     return _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor=False)

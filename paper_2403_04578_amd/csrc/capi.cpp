@@ -22,7 +22,8 @@ int check_launch(const char *what) {
 extern "C" size_t tpf_workspace_bytes(tpf_network net, int64_t tau, const tpf_options *opts) {
     if (!net || tau < 0) return kQueueBytes;
     const int mode = opts ? opts->mode : TPF_MODE_FP64;
-    if (mode != TPF_MODE_TREE_FP64 && uses_large_path(net->n, mode)) return large_workspace_bytes(net->n, tau, mode);
+    if (mode != TPF_MODE_TREE_FP64 && mode != TPF_MODE_TREE_FP32 && uses_large_path(net->n, mode))
+        return large_workspace_bytes(net->n, tau, mode);
     return kQueueBytes;
 }
 
@@ -36,7 +37,7 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
     if (!(tol >= 0.0)) return fail(TPF_ERR_INVALID_ARG, "tol must be >= 0 (and not NaN)");
     if (max_iter < 0) return fail(TPF_ERR_INVALID_ARG, "max_iter must be >= 0");
     const int mode = opts ? opts->mode : TPF_MODE_FP64;
-    if (mode < TPF_MODE_FP64 || mode > TPF_MODE_TREE_FP64) return fail(TPF_ERR_INVALID_ARG, "unknown mode");
+    if (mode < TPF_MODE_FP64 || mode > TPF_MODE_TREE_FP32) return fail(TPF_ERR_INVALID_ARG, "unknown mode");
     if (mode != TPF_MODE_FP64 && mode != TPF_MODE_TREE_FP64 && tol < 5e-7)
         return fail(TPF_ERR_INVALID_ARG, "tol below the FP32 state floor (5e-7 pu) in a reduced-precision mode");
     if (T == 0) return TPF_OK;
@@ -53,8 +54,8 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
     if (rc != TPF_OK) return rc;
     if (max_iter == 0) {
         rc = launch_start_only(n, V0, dtype, T, V_out, iters_out, status_out, st);
-    } else if (mode == TPF_MODE_TREE_FP64) {
-        rc = launch_fpi_tree(*net, *dn, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out, nullptr, st);
+    } else if (mode == TPF_MODE_TREE_FP64 || mode == TPF_MODE_TREE_FP32) {
+        rc = launch_fpi_tree(*net, *dn, mode, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out, st);
     } else if (uses_large_path(n, mode)) {
         rc = launch_fpi_large(*net, *dn, mode, S, dtype, T, tol, max_iter, V0, V_out, iters_out, status_out,
                               workspace, st);

@@ -177,6 +177,215 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
     }
 }
 
+// FP32 form of the tree operator (single-phase): the state is the drop U = V - w in FP32
+// (as in the FP32 sweep kernels), and since V' = w - D the new state is simply U' = -D.
+// The injection uses V = w + U; w is added back in FP64 for the output.  The passes run
+// in FP32 (|D| ~ 1e-2 pu keeps their rounding near 1e-9 pu).
+template <typename IO, int CPW, int B, bool ZIP>
+__global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
+    const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
+    int8_t *__restrict__ status_out, const IO *__restrict__ V0, const int32_t *__restrict__ tree_i,
+    const double *__restrict__ tree_z, int n, int levels, long long tau, float tol, int max_iter,
+    const double *__restrict__ aP, const double *__restrict__ aI) {
+    constexpr int LPC = 64 / CPW;
+    extern __shared__ double lds[];
+    const int np = n + 1;
+    double *wd = lds;                                        // [np][2] w in FP64 (outputs)
+    float *tz = reinterpret_cast<float *>(wd + 2 * np);      // [np][4]: z, w in FP32
+    float *za = tz + 4 * np;                                 // [np][2] (ZIP)
+    float *Jw = za + (ZIP ? 2 * np : 0);                     // [waves][CPW][np][2]
+    int32_t *ti = reinterpret_cast<int32_t *>(Jw + kTreeWaves * CPW * 2 * np);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int slot = lane / LPC, sl = lane % LPC;
+    for (int p = threadIdx.x; p < np; p += kTreeWaves * 64) {
+        wd[2 * p] = tree_z[4 * p + 2];
+        wd[2 * p + 1] = tree_z[4 * p + 3];
+    }
+    for (int e = threadIdx.x; e < 4 * np; e += kTreeWaves * 64) tz[e] = (float)tree_z[e];
+    for (int e = threadIdx.x; e < 4 * np + levels + 2; e += kTreeWaves * 64) ti[e] = tree_i[e];
+    if constexpr (ZIP) {
+        for (int p = threadIdx.x; p < np; p += kTreeWaves * 64) {
+            const int q = tree_i[4 * p];
+            za[2 * p] = q >= 0 ? (float)aP[q] : 0.0f;
+            za[2 * p + 1] = q >= 0 ? (float)aI[q] : 0.0f;
+        }
+    }
+    __syncthreads();
+    float *J = Jw + (wave * CPW + slot) * 2 * np;
+    const int32_t *ls = ti + 4 * np;
+    if (sl == 0) J[0] = J[1] = 0.0f;
+
+    const long long nslots = (long long)gridDim.x * kTreeWaves * CPW;
+    long long c = ((long long)blockIdx.x * kTreeWaves + wave) * CPW + slot;
+    float sr[B], si[B], ur[B], ui[B];
+    int it = 0;
+    auto load = [&]() __attribute__((always_inline)) {
+        int ok = 1;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            sr[r] = si[r] = 0.0f;
+            ur[r] = ui[r] = 0.0f;
+            if (c < tau && p <= n) {
+                const long long o = 2 * (c * n + ti[4 * p]);
+                sr[r] = (float)S[o];
+                si[r] = (float)S[o + 1];
+                double vr = 1.0, vi = 0.0;
+                if (V0) {
+                    vr = (double)V0[o];
+                    vi = (double)V0[o + 1];
+                    const double m2 = vr * vr + vi * vi;
+                    ok &= (m2 >= 0.25 && m2 <= 2.25) ? 1 : 0;
+                }
+                ur[r] = (float)(vr - wd[2 * p]);
+                ui[r] = (float)(vi - wd[2 * p + 1]);
+            }
+        }
+        if (V0) {
+#pragma unroll
+            for (int off = LPC / 2; off > 0; off >>= 1) ok &= __shfl_xor(ok, off);
+            if (!ok) {
+#pragma unroll
+                for (int r = 0; r < B; ++r) {
+                    const int p = 1 + sl + LPC * r;
+                    if (p <= n) {
+                        ur[r] = (float)(1.0 - wd[2 * p]);
+                        ui[r] = (float)(0.0 - wd[2 * p + 1]);
+                    }
+                }
+            }
+        }
+        it = 0;
+    };
+    load();
+    while (__ballot(c < tau)) {
+        const bool live = c < tau;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            if (p <= n) {
+                const float vr = tz[4 * p + 2] + ur[r], vi = tz[4 * p + 3] + ui[r];
+                const float inv = 1.0f / (vr * vr + vi * vi);
+                float ir = (sr[r] * vr + si[r] * vi) * inv, ii = (sr[r] * vi - si[r] * vr) * inv;
+                if constexpr (ZIP) {
+                    const float ap = za[2 * p], ai = za[2 * p + 1];
+                    ir = ap * ir + ai * sr[r];
+                    ii = ap * ii - ai * si[r];
+                }
+                J[2 * p] = ir;
+                J[2 * p + 1] = ii;
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int L = levels; L >= 1; --L) {
+            for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                float jr = J[2 * p], ji = J[2 * p + 1];
+                for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
+                    jr += J[2 * ch];
+                    ji += J[2 * ch + 1];
+                }
+                J[2 * p] = jr;
+                J[2 * p + 1] = ji;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int L = 1; L <= levels; ++L) {
+            for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                const int par = ti[4 * p + 1];
+                const float zr = tz[4 * p], zi = tz[4 * p + 1], jr = J[2 * p], ji = J[2 * p + 1];
+                J[2 * p] = J[2 * par] + zr * jr - zi * ji;
+                J[2 * p + 1] = J[2 * par + 1] + zr * ji + zi * jr;
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        float dmax = 0.0f;
+        int bad = 0;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            if (p <= n) {
+                const float nr = -J[2 * p], ni = -J[2 * p + 1];  // U' = V' - w = -D
+                const float er = nr - ur[r], ei = ni - ui[r];
+                const float e = er * er + ei * ei;
+                bad |= !(e < INFINITY);
+                dmax = e > dmax ? e : dmax;
+                ur[r] = nr;
+                ui[r] = ni;
+            }
+        }
+#pragma unroll
+        for (int off = LPC / 2; off > 0; off >>= 1) {
+            dmax = fmaxf(dmax, __shfl_xor(dmax, off));
+            bad |= __shfl_xor(bad, off);
+        }
+        ++it;
+        const bool conv = !bad && sqrtf(dmax) < tol;
+        if (live && (bad || conv || it >= max_iter)) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const int p = 1 + sl + LPC * r;
+                if (p <= n) {
+                    const long long o = 2 * (c * n + ti[4 * p]);
+                    Vout[o] = (IO)(wd[2 * p] + (double)ur[r]);
+                    Vout[o + 1] = (IO)(wd[2 * p + 1] + (double)ui[r]);
+                }
+            }
+            if (sl == 0) {
+                iters_out[c] = it;
+                status_out[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            }
+            c += nslots;
+            load();
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <typename IO, int CPW, int B, bool ZIP>
+int launch32_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
+                const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
+    const int n = net.n, np = n + 1, levels = dn.tree_levels;
+    const size_t lds = (size_t)2 * np * 8 + (size_t)4 * np * 4 + (ZIP ? (size_t)2 * np * 4 : 0) +
+                       (size_t)kTreeWaves * CPW * 2 * np * 4 + (size_t)(4 * np + levels + 2) * 4;
+    if (lds > (size_t)160 * 1024) return fail(TPF_ERR_UNSUPPORTED, "tree operator: network too large for LDS");
+    auto k = fpi_tree32_kernel<IO, CPW, B, ZIP>;
+    if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kTreeWaves * 64, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const long long per_block = (long long)kTreeWaves * CPW;
+    const long long blocks =
+        std::max<long long>(1, std::min<long long>((long long)cus * per_cu, (tau + per_block - 1) / per_block));
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTreeWaves * 64), lds, st, (const IO *)S, (IO *)V, iters,
+                       status, (const IO *)V0, dn.tree_i, dn.tree_z, n, levels, (long long)tau, (float)tol, max_iter,
+                       (const double *)dn.aP, (const double *)dn.aI);
+    return TPF_OK;
+}
+
+template <typename IO, int CPW, int B>
+int launch32_b(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
+               const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
+    if (dn.aP) return launch32_as<IO, CPW, B, true>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    return launch32_as<IO, CPW, B, false>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+}
+
+template <typename IO>
+int launch32_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
+                const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
+    const int n = net.n;
+    if (n <= 64) return launch32_b<IO, 8, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 128) return launch32_b<IO, 8, 16>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 256) return launch32_b<IO, 2, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 512) return launch32_b<IO, 1, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 1024) return launch32_b<IO, 1, 16>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    return fail(TPF_ERR_UNSUPPORTED, "tree operator: up to 1,024 PQ buses");
+}
+
 // Three-phase networks: the same passes with three phase nodes per position; a branch
 // carries a 3x3 impedance matrix, so the forward pass is D_b = D_parent + Z_abc,b J_b.
 // Position p's node f is demand node 3 pq(p) + f.  tz: per position Z_abc (9 complex)
@@ -425,10 +634,16 @@ int launch_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int6
 
 }  // namespace
 
-int launch_fpi_tree(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype, int64_t tau,
+int launch_fpi_tree(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype, int64_t tau,
                     double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                    unsigned long long *, hipStream_t stream) {
+                    hipStream_t stream) {
     if (!dn.tree_i) return fail(TPF_ERR_UNSUPPORTED, "the tree operator needs a radial network (n_bus - 1 branches)");
+    if (mode == TPF_MODE_TREE_FP32) {
+        if (dn.tree_phases != 1) return fail(TPF_ERR_UNSUPPORTED, "the FP32 tree operator is single-phase");
+        if (dtype == TPF_C128)
+            return launch32_io<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);
+        return launch32_io<float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);
+    }
     if (dn.tree_phases == 3) {
         if (dtype == TPF_C128)
             return launch3_io<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);

@@ -117,9 +117,9 @@ int device_net(tpf_network net, DeviceNet **out);
 int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype,
                          int64_t tau, double tol, int max_iter, const void *V0, void *V,
                          int32_t *iters, int8_t *status, unsigned long long *queue, hipStream_t stream);
-int launch_fpi_tree(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype, int64_t tau,
+int launch_fpi_tree(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype, int64_t tau,
                     double tol, int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status,
-                    unsigned long long *queue, hipStream_t stream);
+                    hipStream_t stream);
 int launch_fpi_mixed(const tpf_network_s &net, const DeviceNet &dn, int mode, const void *S, int dtype,
                      int64_t tau, double tol, int max_iter, const void *V0, void *V, int32_t *iters,
                      int8_t *status, unsigned long long *queue, hipStream_t stream);

@@ -138,3 +138,50 @@ def test_tree_two_bus_network(gpu):
     S = np.array([[0.5 + 0.2j], [0.0], [1.0 + 0.3j]])
     V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-12, max_iter=200, mode="tree_fp64")
     _compare(onet, S, V, it, st, 1e-12, 200, 1e-12)
+
+
+@pytest.mark.parametrize("n_bus,T,dtype", [(31, 300, torch.complex128), (100, 700, torch.complex128),
+                                           (100, 300, torch.complex64), (200, 300, torch.complex128),
+                                           (400, 200, torch.complex128), (1000, 100, torch.complex128)])
+def test_tree_fp32_form(gpu, n_bus, T, dtype):
+    """The FP32 tree form (state as the FP32 drop V - w) to the fast-form contract: 1e-6
+    pu against a tol-1e-10 oracle solution, every register width of its kernel."""
+    f = W.make_feeder(n_bus)
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=T, t0=50)
+    if dtype == torch.complex64:
+        S = S.astype(np.complex64).astype(np.complex128)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu, dtype), tol=1e-6, max_iter=100, mode="tree_fp32")
+    assert int(st.max()) == tpf.ST_CONVERGED
+    ref = oracle.fpi(onet, S, 1e-10, 200)
+    bound = 1e-6 + (1e-7 if dtype == torch.complex64 else 0.0)
+    assert np.abs(V.cpu().numpy().astype(np.complex128) - ref.V).max() <= bound
+
+
+def test_tree_fp32_zip_edges_and_refusals(gpu):
+    f = W.make_feeder(100)
+    ai, ap = W.zip_shares(99)
+    net, onet = tpf.Network.from_feeder(f, alpha_i=ai, alpha_p=ap), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=200, t0=3)
+    S[5, 7] = np.nan
+    S[6] = 0.0
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode="tree_fp32")
+    st = st.cpu().numpy()
+    assert st[5] == tpf.ST_NONFINITE and int(it[5]) == 1
+    good = np.arange(200) != 5
+    assert np.all(st[good] == tpf.ST_CONVERGED)
+    ref = oracle.fpi_zip(onet, S[good], ai, ap, 1e-10, 200)
+    assert np.abs(V.cpu().numpy()[good] - ref.V).max() <= 1e-6
+    # warm start from the solution: converges at once
+    V0 = np.ones_like(S)
+    V0[good] = ref.V
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode="tree_fp32", V0=_dev(V0, gpu))
+    assert int(it.cpu().numpy()[good].max()) == 1
+    with pytest.raises(tpf.TpfError) as e:  # below the FP32 state floor
+        tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-8, max_iter=10, mode="tree_fp32")
+    assert e.value.code == tpf.TPF_ERR_INVALID_ARG
+    f3 = W.make_feeder_3ph(10)
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.solve_timeseries(tpf.Network.from_feeder_3ph(f3), _dev(W.profile_minute_year(f3, steps=4), gpu),
+                             tol=1e-6, max_iter=10, mode="tree_fp32")
+    assert e.value.code == tpf.TPF_ERR_UNSUPPORTED
