@@ -63,11 +63,10 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
  *               FP32-accurate sweep splits Z and I into FP16 high and low parts.
  *   Convergence is only declared on an FP32-accurate iterate.  In FP32 and mixed
  *   modes tol must be >= 5e-7 pu (the FP32 state floor).
- * Network size: FP64 runs any n; FP32 any n; the mixed modes run n <= 128 and return
- * TPF_ERR_UNSUPPORTED above.  FP64 beyond 320 and FP32 beyond 128 PQ buses use a
- * per-sweep kernel sequence (dense Z no longer fits one workgroup's registers) whose
- * host loop waits for the device once per sweep; smaller networks run one persistent
- * kernel per solve. */
+ * Network size: these four modes run any n.  FP64 beyond 320 PQ buses, and FP32 and
+ * the mixed modes beyond 128, use a per-sweep kernel sequence (dense Z no longer fits
+ * one workgroup's registers) whose host loop waits for the device once per sweep;
+ * smaller networks run one persistent kernel per solve. */
 /* TREE_FP64   the FP64 iteration with Z I evaluated by two passes over the feeder's
  *             tree instead of the dense product: on a radial network without shunts,
  *             -Z is the path-impedance matrix, so Z I = -D with branch currents
