@@ -185,3 +185,17 @@ def test_tree_fp32_zip_edges_and_refusals(gpu):
         tpf.solve_timeseries(tpf.Network.from_feeder_3ph(f3), _dev(W.profile_minute_year(f3, steps=4), gpu),
                              tol=1e-6, max_iter=10, mode="tree_fp32")
     assert e.value.code == tpf.TPF_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("mode", ["tree_fp64", "tree_fp32"])
+@pytest.mark.parametrize("T", [1, 5, 33])
+def test_tree_few_columns(gpu, mode, T):
+    """Fewer columns than the slots of one workgroup, and a ragged last round."""
+    f = W.make_feeder(100)
+    net, onet = tpf.Network.from_feeder(f), oracle.build_feeder(f)
+    S = W.profile_minute_year(f, steps=T, t0=999)
+    tol = 1e-9 if mode == "tree_fp64" else 1e-6
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=tol, max_iter=100, mode=mode)
+    assert V.shape == (T, 99) and int(st.max()) == tpf.ST_CONVERGED
+    ref = oracle.fpi(onet, S, 1e-10, 200)
+    assert np.abs(V.cpu().numpy() - ref.V).max() <= (1e-9 if mode == "tree_fp64" else 1e-6)
