@@ -239,9 +239,7 @@ def bench_other(args):
     stream = torch.cuda.current_stream(dev)
     esz = S.element_size()
     forms = {}
-    runs = [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16", "tree_fp64")]
-    if not three:  # the FP32 tree form is single-phase
-        runs.append(("tree_fp32", "tree_fp32", net))
+    runs = [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16", "tree_fp64", "tree_fp32")]
     if zip_loads:
         runs.append(("fp64_constant_power", "fp64", tpf.Network.from_feeder(f)))
     for key, mode, net in runs:

@@ -77,7 +77,7 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
  *             three-phase (3x3 blocks per branch) with at most 512 PQ buses; returns
  *             TPF_ERR_UNSUPPORTED otherwise. */
 /* TREE_FP32   the tree operator in FP32 arithmetic with the state kept as the FP32 drop
- *             V - w (as in FP32 mode; tol >= 5e-7 pu); single-phase networks only. */
+ *             V - w (as in FP32 mode; tol >= 5e-7 pu); the same networks as TREE_FP64. */
 enum {
     TPF_MODE_FP64 = 0,
     TPF_MODE_FP32 = 1,

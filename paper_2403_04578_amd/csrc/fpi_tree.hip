@@ -552,6 +552,218 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_kernel(
     }
 }
 
+// Three-phase FP32 form: the state is the FP32 drop U = V - w per phase node and U' = -D,
+// as in the single-phase FP32 kernel; the 3x3 blocks and w are staged in FP32 (w also in
+// FP64 for the output).
+template <typename IO, int CPW, int B>
+__global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_32_kernel(
+    const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
+    int8_t *__restrict__ status_out, const IO *__restrict__ V0, const int32_t *__restrict__ tree_i,
+    const double *__restrict__ tree_z, int nb, int levels, long long tau, float tol, int max_iter) {
+    constexpr int LPC = 64 / CPW;
+    constexpr int TZ = 24;
+    extern __shared__ double lds[];
+    const int np = nb + 1;
+    const int n = 3 * nb;
+    double *wd = lds;                                        // [np][6] w in FP64
+    float *tz = reinterpret_cast<float *>(wd + 6 * np);      // [np][24]
+    float *Jw = tz + TZ * np;                                // [waves][CPW][np][6]
+    int32_t *ti = reinterpret_cast<int32_t *>(Jw + kTreeWaves * CPW * 6 * np);
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int slot = lane / LPC, sl = lane % LPC;
+    for (int e = threadIdx.x; e < TZ * np; e += kTreeWaves * 64) tz[e] = (float)tree_z[e];
+    for (int p = threadIdx.x; p < np; p += kTreeWaves * 64)
+        for (int e = 0; e < 6; ++e) wd[6 * p + e] = tree_z[TZ * p + 18 + e];
+    for (int e = threadIdx.x; e < 4 * np + levels + 2; e += kTreeWaves * 64) ti[e] = tree_i[e];
+    __syncthreads();
+    float *J = Jw + (wave * CPW + slot) * 6 * np;
+    const int32_t *ls = ti + 4 * np;
+    if (sl == 0)
+        for (int e = 0; e < 6; ++e) J[e] = 0.0f;
+
+    const long long nslots = (long long)gridDim.x * kTreeWaves * CPW;
+    long long c = ((long long)blockIdx.x * kTreeWaves + wave) * CPW + slot;
+    float sr[B][3], si[B][3], ur[B][3], ui[B][3];
+    int it = 0;
+    auto load = [&]() __attribute__((always_inline)) {
+        int ok = 1;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                sr[r][f] = si[r][f] = ur[r][f] = ui[r][f] = 0.0f;
+                if (c < tau && p <= nb) {
+                    const long long o = 2 * (c * n + 3 * ti[4 * p] + f);
+                    sr[r][f] = (float)S[o];
+                    si[r][f] = (float)S[o + 1];
+                    double vr = 1.0, vi = 0.0;
+                    if (V0) {
+                        vr = (double)V0[o];
+                        vi = (double)V0[o + 1];
+                        const double m2 = vr * vr + vi * vi;
+                        ok &= (m2 >= 0.25 && m2 <= 2.25) ? 1 : 0;
+                    }
+                    ur[r][f] = (float)(vr - wd[6 * p + 2 * f]);
+                    ui[r][f] = (float)(vi - wd[6 * p + 2 * f + 1]);
+                }
+            }
+        }
+        if (V0) {
+#pragma unroll
+            for (int off = LPC / 2; off > 0; off >>= 1) ok &= __shfl_xor(ok, off);
+            if (!ok) {
+#pragma unroll
+                for (int r = 0; r < B; ++r) {
+                    const int p = 1 + sl + LPC * r;
+                    if (p <= nb) {
+#pragma unroll
+                        for (int f = 0; f < 3; ++f) {
+                            ur[r][f] = (float)(1.0 - wd[6 * p + 2 * f]);
+                            ui[r][f] = (float)(0.0 - wd[6 * p + 2 * f + 1]);
+                        }
+                    }
+                }
+            }
+        }
+        it = 0;
+    };
+    load();
+    while (__ballot(c < tau)) {
+        const bool live = c < tau;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            if (p <= nb) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const float vr = tz[TZ * p + 18 + 2 * f] + ur[r][f], vi = tz[TZ * p + 19 + 2 * f] + ui[r][f];
+                    const float inv = 1.0f / (vr * vr + vi * vi);
+                    J[6 * p + 2 * f] = (sr[r][f] * vr + si[r][f] * vi) * inv;
+                    J[6 * p + 2 * f + 1] = (sr[r][f] * vi - si[r][f] * vr) * inv;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        for (int L = levels; L >= 1; --L) {
+            for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                float j[6];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) j[e] = J[6 * p + e];
+                for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
+#pragma unroll
+                    for (int e = 0; e < 6; ++e) j[e] += J[6 * ch + e];
+                }
+#pragma unroll
+                for (int e = 0; e < 6; ++e) J[6 * p + e] = j[e];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        for (int L = 1; L <= levels; ++L) {
+            for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                const int par = ti[4 * p + 1];
+                float j[6], d[6];
+#pragma unroll
+                for (int e = 0; e < 6; ++e) j[e] = J[6 * p + e], d[e] = J[6 * par + e];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+#pragma unroll
+                    for (int b = 0; b < 3; ++b) {
+                        const float zr = tz[TZ * p + 2 * (3 * a + b)], zi = tz[TZ * p + 2 * (3 * a + b) + 1];
+                        d[2 * a] += zr * j[2 * b] - zi * j[2 * b + 1];
+                        d[2 * a + 1] += zr * j[2 * b + 1] + zi * j[2 * b];
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 6; ++e) J[6 * p + e] = d[e];
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        float dmax = 0.0f;
+        int bad = 0;
+#pragma unroll
+        for (int r = 0; r < B; ++r) {
+            const int p = 1 + sl + LPC * r;
+            if (p <= nb) {
+#pragma unroll
+                for (int f = 0; f < 3; ++f) {
+                    const float nr = -J[6 * p + 2 * f], ni = -J[6 * p + 2 * f + 1];
+                    const float er = nr - ur[r][f], ei = ni - ui[r][f];
+                    const float e = er * er + ei * ei;
+                    bad |= !(e < INFINITY);
+                    dmax = e > dmax ? e : dmax;
+                    ur[r][f] = nr;
+                    ui[r][f] = ni;
+                }
+            }
+        }
+#pragma unroll
+        for (int off = LPC / 2; off > 0; off >>= 1) {
+            dmax = fmaxf(dmax, __shfl_xor(dmax, off));
+            bad |= __shfl_xor(bad, off);
+        }
+        ++it;
+        const bool conv = !bad && sqrtf(dmax) < tol;
+        if (live && (bad || conv || it >= max_iter)) {
+#pragma unroll
+            for (int r = 0; r < B; ++r) {
+                const int p = 1 + sl + LPC * r;
+                if (p <= nb) {
+#pragma unroll
+                    for (int f = 0; f < 3; ++f) {
+                        const long long o = 2 * (c * n + 3 * ti[4 * p] + f);
+                        Vout[o] = (IO)(wd[6 * p + 2 * f] + (double)ur[r][f]);
+                        Vout[o + 1] = (IO)(wd[6 * p + 2 * f + 1] + (double)ui[r][f]);
+                    }
+                }
+            }
+            if (sl == 0) {
+                iters_out[c] = it;
+                status_out[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            }
+            c += nslots;
+            load();
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+template <typename IO, int CPW, int B>
+int launch3_32_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
+                  int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
+    const int nb = net.n / 3, np = nb + 1, levels = dn.tree_levels;
+    const size_t lds = (size_t)6 * np * 8 + (size_t)24 * np * 4 + (size_t)kTreeWaves * CPW * 6 * np * 4 +
+                       (size_t)(4 * np + levels + 2) * 4;
+    if (lds > (size_t)160 * 1024) return fail(TPF_ERR_UNSUPPORTED, "tree operator: network too large for LDS");
+    auto k = fpi_tree3_32_kernel<IO, CPW, B>;
+    if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, kTreeWaves * 64, lds) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const long long per_block = (long long)kTreeWaves * CPW;
+    const long long blocks =
+        std::max<long long>(1, std::min<long long>((long long)cus * per_cu, (tau + per_block - 1) / per_block));
+    hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTreeWaves * 64), lds, st, (const IO *)S, (IO *)V, iters,
+                       status, (const IO *)V0, dn.tree_i, dn.tree_z, nb, levels, (long long)tau, (float)tol,
+                       max_iter);
+    return TPF_OK;
+}
+
+template <typename IO>
+int launch3_32_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol,
+                  int max_iter, const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
+    const int nb = net.n / 3;
+    if (nb <= 128) return launch3_32_as<IO, 2, 4>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (nb <= 256) return launch3_32_as<IO, 1, 4>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (nb <= 512) return launch3_32_as<IO, 1, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    return fail(TPF_ERR_UNSUPPORTED, "tree operator: up to 512 three-phase buses");
+}
+
 template <typename IO, int CPW, int B>
 int launch3_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
                const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
@@ -639,7 +851,11 @@ int launch_fpi_tree(const tpf_network_s &net, const DeviceNet &dn, int mode, con
                     hipStream_t stream) {
     if (!dn.tree_i) return fail(TPF_ERR_UNSUPPORTED, "the tree operator needs a radial network (n_bus - 1 branches)");
     if (mode == TPF_MODE_TREE_FP32) {
-        if (dn.tree_phases != 1) return fail(TPF_ERR_UNSUPPORTED, "the FP32 tree operator is single-phase");
+        if (dn.tree_phases == 3) {
+            if (dtype == TPF_C128)
+                return launch3_32_io<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);
+            return launch3_32_io<float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);
+        }
         if (dtype == TPF_C128)
             return launch32_io<double>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);
         return launch32_io<float>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, stream);

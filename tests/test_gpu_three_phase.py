@@ -99,3 +99,26 @@ def test_three_phase_tree_operator(gpu, feeder3):
     V0 = torch.from_numpy(ref.V).to(gpu)
     V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-8, max_iter=100, mode="tree_fp64", V0=V0)
     assert int(it.max()) == 1
+
+
+@pytest.mark.parametrize("dtype", [torch.complex128, torch.complex64])
+def test_three_phase_tree_fp32(gpu, feeder3, dtype):
+    """The FP32 tree form with 3x3 branch blocks: 1e-6 pu from a tol-1e-10 oracle
+    solution over a ragged column count (not a multiple of the columns per workgroup);
+    a warm start whose column holds a modulus outside [0.5, 1.5] starts flat."""
+    f, net, onet = feeder3
+    S = W.profile_minute_year(f, steps=203, t0=4444)
+    if dtype == torch.complex64:
+        S = S.astype(np.complex64).astype(np.complex128)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu, dtype), tol=1e-6, max_iter=100, mode="tree_fp32")
+    assert int(st.max()) == tpf.ST_CONVERGED
+    ref = oracle.fpi(onet, S, 1e-10, 200)
+    bound = 1e-6 + (1e-7 if dtype == torch.complex64 else 0.0)
+    assert np.abs(V.cpu().numpy().astype(np.complex128) - ref.V).max() <= bound
+    V0 = ref.V.copy()
+    V0[7, 5] = 3.0
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu, dtype), tol=1e-6, max_iter=100, mode="tree_fp32",
+                                     V0=_dev(V0, gpu, dtype))
+    it = it.cpu().numpy()
+    assert it[0] <= 2 and it[7] >= 3
+    assert np.abs(V.cpu().numpy().astype(np.complex128) - ref.V).max() <= bound

@@ -180,11 +180,6 @@ def test_tree_fp32_zip_edges_and_refusals(gpu):
     with pytest.raises(tpf.TpfError) as e:  # below the FP32 state floor
         tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-8, max_iter=10, mode="tree_fp32")
     assert e.value.code == tpf.TPF_ERR_INVALID_ARG
-    f3 = W.make_feeder_3ph(10)
-    with pytest.raises(tpf.TpfError) as e:
-        tpf.solve_timeseries(tpf.Network.from_feeder_3ph(f3), _dev(W.profile_minute_year(f3, steps=4), gpu),
-                             tol=1e-6, max_iter=10, mode="tree_fp32")
-    assert e.value.code == tpf.TPF_ERR_UNSUPPORTED
 
 
 @pytest.mark.parametrize("mode", ["tree_fp64", "tree_fp32"])
