@@ -122,3 +122,27 @@ def test_three_phase_tree_fp32(gpu, feeder3, dtype):
     it = it.cpu().numpy()
     assert it[0] <= 2 and it[7] >= 3
     assert np.abs(V.cpu().numpy().astype(np.complex128) - ref.V).max() <= bound
+
+
+@pytest.mark.parametrize("n_bus", [200, 300])
+def test_three_phase_tree_wide_feeders(gpu, n_bus):
+    """The tree kernels' one-column-per-wavefront shapes (4 and 8 positions per lane)
+    on 199 and 299 three-phase buses, over a ragged column count: FP64 iterates up to
+    rounding, the FP32 drop state within 1e-6 pu of a tol-1e-10 oracle solution."""
+    f = W.make_feeder_3ph(n_bus)
+    net, onet = tpf.Network.from_feeder_3ph(f), oracle.build_feeder_3ph(f)
+    S = W.profile_minute_year(f, steps=37, t0=777)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-9, max_iter=100, mode="tree_fp64")
+    ref = oracle.fpi(onet, S, 1e-9, 100)
+    ig = it.cpu().numpy()
+    same = ig == ref.iters
+    assert same.mean() > 0.9 and int(st.max()) == tpf.ST_CONVERGED
+    Vg = V.cpu().numpy()
+    assert np.abs(Vg[same] - ref.V[same]).max() < 1e-9
+    for c in np.nonzero(~same)[0]:
+        r2 = oracle.fpi(onet, S[c:c + 1], 0.0, int(ig[c]))
+        assert np.abs(Vg[c] - r2.V[0]).max() < 1e-9
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode="tree_fp32")
+    assert int(st.max()) == tpf.ST_CONVERGED
+    ref = oracle.fpi(onet, S, 1e-10, 200)
+    assert np.abs(V.cpu().numpy() - ref.V).max() <= 1e-6
