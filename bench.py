@@ -139,8 +139,8 @@ def summarize_trace(trace_dir: str, out_txt: str, command: str):
                      f"{float(r['TotalDurationNs']) / 1e6:10.2f} {float(r['Percentage']):6.1f}")
     rows = sorted(csv.DictReader(open(trace[0])), key=lambda r: int(r["Start_Timestamp"]))
     lines += ["", "launches of the year-long sweep, inference and mismatch kernels, in order (us):"]
-    for key in ("fpi_f64_kernel", "fpi_mixed_kernel", "fpi_tree_kernel", "fpi_tree32_kernel", "predict_fused_kernel",
-                "mismatch_tile_kernel"):
+    for key in ("fpi_f64_kernel", "fpi_mixed_kernel", "fpi_tree_kernel", "fpi_tree32_kernel", "fpi_tree3_kernel",
+                "fpi_tree3_32_kernel", "predict_fused_kernel", "mismatch_tile_kernel"):
         by = {}
         for r in rows:
             if key in r["Kernel_Name"]:
