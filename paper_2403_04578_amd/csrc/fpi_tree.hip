@@ -1,4 +1,5 @@
-// FP64 sweeps with the tree operator, for radial (tree) networks, single- or three-phase.
+// Sweeps with the tree operator, for radial (tree) networks, single- or three-phase, in
+// FP64 or with the FP32 drop state V - w.
 //
 // On a radial feeder without shunts, Z = -Y_dd^-1 is minus the path-impedance matrix:
 // (Y_dd^-1)_ij is the sum of the impedances of the branches shared by the paths from the
