@@ -37,9 +37,9 @@ PEAK_HBM_GBS = 8000.0
 PEAK_F16_TFLOPS = 2500.0  # MI355X dense FP16/BF16 matrix
 
 
-def _kernel_sources_digest() -> str:
+def _kernel_sources_digest(names=("fpi_small.hip", "fpi_mixed.hip")) -> str:
     h = hashlib.sha256()
-    for name in ("fpi_small.hip", "fpi_mixed.hip"):
+    for name in names:
         with open(os.path.join(ROOT, "paper_2403_04578_amd", "csrc", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -75,9 +75,10 @@ def _pmc_per_kernel(run_dir: str, counter: str):
 
 
 def ingest_pmc(fetch_dir: str, write_dir: str):
-    """HBM bytes per launch of the FP64 and mixed sweep kernels from FETCH_SIZE and
+    """HBM bytes per launch of the FP64, mixed and tree sweep kernels from FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the counter reads for the
-    1 GiB negation (2^30 bytes read and 2^30 bytes written)."""
+    1 GiB negation (2^30 bytes read and 2^30 bytes written).  Kernels absent from these
+    runs keep their earlier entries."""
     fetch, nf = _pmc_per_kernel(fetch_dir, "FETCH_SIZE")
     write, _ = _pmc_per_kernel(write_dir, "WRITE_SIZE")
 
@@ -102,21 +103,25 @@ def ingest_pmc(fetch_dir: str, write_dir: str):
         raise SystemExit("no calibration negation kernel in the PMC runs (run them with --calib-copy)")
     cf = 2.0 ** 30 / (fetch[calib_f] * 1024.0)
     cw = 2.0 ** 30 / (write[calib_w] * 1024.0)
-    out = {"calibration": {"kernel": calib_f, "fetch_kib": fetch[calib_f], "write_kib": write[calib_w],
-                           "fetch_scale": cf, "write_scale": cw}}
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    out = json.load(open(path)) if os.path.exists(path) else {}
+    out["calibration"] = {"kernel": calib_f, "fetch_kib": fetch[calib_f], "write_kib": write[calib_w],
+                          "fetch_scale": cf, "write_scale": cw}
 
     def mixed(mode):  # fpi_mixed_kernel<TPW, NW, KTL, MODE, CG, PF, IO>
         return lambda k: (targs(k, "fpi_mixed_kernel") or [""] * 4)[3] == mode
-    for key, match in (("fp64/year100", lambda k: "fpi_f64_kernel<" in k),
-                       ("mixed_fp16+warm/year100", mixed("3")),
-                       ("mixed_bf16+warm/year100", mixed("2"))):
+    dense, tree = ("fpi_small.hip", "fpi_mixed.hip"), ("fpi_tree.hip",)
+    for key, match, src in (("fp64/year100", lambda k: "fpi_f64_kernel<" in k, dense),
+                            ("mixed_fp16+warm/year100", mixed("3"), dense),
+                            ("mixed_bf16+warm/year100", mixed("2"), dense),
+                            ("tree_fp64/year100", lambda k: "fpi_tree_kernel<" in k, tree),
+                            ("tree_fp32/year100", lambda k: "fpi_tree32_kernel<" in k, tree)):
         kf, kw = pick(fetch, match), pick(write, match)
         if kf is None or kw is None:
             continue
         b = fetch[kf] * 1024.0 * cf + write[kw] * 1024.0 * cw
         out[key] = {"kernel": kf, "fetch_kib": fetch[kf], "write_kib": write[kw], "bytes_per_launch": b,
-                    "source_digest": _kernel_sources_digest(), "dispatches": nf.get(kf, 0)}
-    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+                    "source_digest": _kernel_sources_digest(src), "dispatches": nf.get(kf, 0)}
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
