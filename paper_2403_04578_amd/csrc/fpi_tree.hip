@@ -375,12 +375,15 @@ int launch32_b(const tpf_network_s &net, const DeviceNet &dn, const void *S, int
     return launch32_as<IO, CPW, B, false>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
 }
 
+// The FP32 form takes 4 columns of 16 lanes up to 128 PQ buses: with half the FP64
+// kernel's registers per position, the wider column group measured fastest there
+// (8 columns of 8 lanes, the FP64 choice, ran the 100-bus year 16 % slower).
 template <typename IO>
 int launch32_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
                 const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
     const int n = net.n;
     if (n <= 64) return launch32_b<IO, 8, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    if (n <= 128) return launch32_b<IO, 8, 16>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (n <= 128) return launch32_b<IO, 4, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     if (n <= 256) return launch32_b<IO, 2, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     if (n <= 512) return launch32_b<IO, 1, 8>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     if (n <= 1024) return launch32_b<IO, 1, 16>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
