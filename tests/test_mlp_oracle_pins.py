@@ -78,3 +78,57 @@ def test_parameter_count_of_the_warm_start_network():
     assert M.num_params(sizes) == 234_438
     p = W.mlp_init_params(sizes)
     assert p.dtype == np.float32 and p.size == 234_438
+
+
+def test_adamw_constant_gradient_gives_unit_steps():
+    """With a constant gradient and no weight decay the bias-corrected moments are
+    exactly g and g^2 at every step (m_t = (1 - b1^t) g, v_t = (1 - b2^t) g^2), so
+    every step moves each parameter by -lr g / (|g| + eps).  Dropping the moment
+    memory or using a wrong bias-correction exponent breaks this from step 2 on."""
+    rng = np.random.default_rng(3)
+    p0 = rng.normal(size=40)
+    g = rng.normal(size=40) * np.logspace(-3, 1, 40)
+    p, m, v = p0.copy(), np.zeros(40), np.zeros(40)
+    for t in range(1, 8):
+        p, m, v = M.adamw_step(p, g, m, v, t, lr=1e-3, wd=0.0)
+        assert np.allclose(m, (1 - 0.9 ** t) * g, rtol=1e-14, atol=0)
+        assert np.allclose(v, (1 - 0.999 ** t) * g * g, rtol=1e-13, atol=0)
+        assert np.allclose(p - p0, -t * 1e-3 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-16)
+
+
+def test_adamw_three_varying_steps_written_out():
+    """Three steps with different gradients, the moments expanded by hand:
+    m_3 = 0.081 g1 + 0.09 g2 + 0.1 g3, v_3 = 0.000998001 g1^2 + 0.000999 g2^2 + 0.001 g3^2,
+    each step's update -lr (m_t/(1-0.9^t)) / (sqrt(v_t/(1-0.999^t)) + eps) - lr wd p_{t-1}."""
+    g1, g2, g3 = 0.5, -2.0, 0.25
+    p0, lr, wd, eps = 1.5, 1e-2, 0.1, 1e-8
+    p = np.array([p0])
+    m = v = np.zeros(1)
+    out = []
+    for t, gg in enumerate((g1, g2, g3), start=1):
+        p, m, v = M.adamw_step(p, np.array([gg]), m, v, t, lr=lr, wd=wd)
+        out.append((float(p[0]), float(m[0]), float(v[0])))
+    m1, v1 = 0.1 * g1, 0.001 * g1 ** 2
+    m2, v2 = 0.09 * g1 + 0.1 * g2, 0.000999 * g1 ** 2 + 0.001 * g2 ** 2
+    m3 = 0.081 * g1 + 0.09 * g2 + 0.1 * g3
+    v3 = 0.000998001 * g1 ** 2 + 0.000999 * g2 ** 2 + 0.001 * g3 ** 2
+    q = p0
+    for (pm, mm, vm), (mt, vt, t) in zip(out, ((m1, v1, 1), (m2, v2, 2), (m3, v3, 3))):
+        assert abs(mm - mt) < 1e-15 and abs(vm - vt) < 1e-17
+        q = q - lr * ((mt / (1 - 0.9 ** t)) / (math.sqrt(vt / (1 - 0.999 ** t)) + eps) + wd * q)
+        assert abs(pm - q) < 1e-14, (t, pm, q)
+
+
+def test_adamw_is_invariant_to_gradient_scale():
+    """Adam's update is homogeneous of degree zero in g (up to eps): scaling every
+    gradient of a run by 1000 leaves the trajectory unchanged."""
+    rng = np.random.default_rng(4)
+    p0 = rng.normal(size=30)
+    gs = rng.normal(size=(5, 30))
+    runs = []
+    for c in (1.0, 1000.0):
+        p, m, v = p0.copy(), np.zeros(30), np.zeros(30)
+        for t in range(5):
+            p, m, v = M.adamw_step(p, c * gs[t], m, v, t + 1, lr=1e-3, wd=0.01, eps=0.0)
+        runs.append(p)
+    assert np.allclose(runs[0], runs[1], rtol=0, atol=1e-15)
