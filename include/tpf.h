@@ -243,6 +243,26 @@ int tpf_mlp_train_step(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t 
                        int64_t rows, float lr, float weight_decay, float *loss_out, void *workspace,
                        size_t workspace_bytes, void *stream);
 
+/* Mini-batch training over a set of solved power flows: epochs first_epoch ..
+ * first_epoch + epochs - 1 of a run of total_epochs epochs.
+ *   S, V       device [rows][n] loads and target voltages (same dtype);  t_index  device int64 [rows]
+ *   batch      rows per AdamW step (batch > rows means one batch of all rows); an epoch takes
+ *              rows / batch steps over a fresh permutation of the rows, computed on the device
+ *              from (seed, epoch) (a 4-round Feistel network on 2h-bit integers, 4^h >= rows,
+ *              restricted to [0, rows) by cycle walking), so a resumed run revisits the same
+ *              batches; the rows past (rows / batch) * batch sit out that epoch
+ *   lr, lr_min cosine schedule over the run's total_epochs * (rows / batch) steps:
+ *              lr_k = lr_min + (lr - lr_min)(1 + cos(pi k / (total - 1)))/2 at global step k
+ *   epoch_loss_out  device float32 [epochs] mean batch loss per epoch (before each step), or NULL
+ *   workspace  >= tpf_mlp_workspace_bytes(mlp, min(batch, rows)) bytes
+ * The AdamW state (moments and step count) lives in the handle, so splitting a run into
+ * several calls, with tpf_mlp_save / tpf_mlp_load in between, gives the same parameters bit
+ * for bit as one call.  Errors: INVALID_ARG (sizes, epoch range, negative rates), DEVICE. */
+int tpf_mlp_train(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t *t_index, const void *V, int64_t rows,
+                  int32_t first_epoch, int32_t epochs, int32_t total_epochs, int32_t batch, float lr, float lr_min,
+                  float weight_decay, uint64_t seed, float *epoch_loss_out, void *workspace, size_t workspace_bytes,
+                  void *stream);
+
 /* Warm start V0 (device [rows][n], same dtype as S) for the loads S at minute indices t_index.
  * When every padded layer width is <= 256 (the 99-bus network's 202 -> 256 x 3 -> 198), one
  * fused kernel per 128-row tile computes it with the activations in LDS and erf from
@@ -251,7 +271,9 @@ int tpf_mlp_train_step(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t 
 int tpf_mlp_predict(tpf_mlp mlp, const void *S, int32_t dtype, const int64_t *t_index, int64_t rows, void *V0_out,
                     void *workspace, size_t workspace_bytes, void *stream);
 
-/* Binary file with sizes, slack voltage, Adam step count and FP32 parameters. */
+/* Binary file with sizes, slack voltage, AdamW step count, the FP32 parameters and the
+ * AdamW moments (format TPFMLP02; tpf_mlp_load also reads the parameters-only TPFMLP01
+ * format, whose optimiser restarts at step 0 with zero moments). */
 int tpf_mlp_save(tpf_mlp mlp, const char *path);
 int tpf_mlp_load(const char *path, tpf_mlp *out);
 

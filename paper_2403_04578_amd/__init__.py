@@ -78,6 +78,9 @@ def load_library() -> ctypes.CDLL:
         "tpf_mlp_loss_grad": (ctypes.c_int, [P, P, I32, P, P, I64, P, P, P, ctypes.c_size_t, P]),
         "tpf_mlp_train_step": (ctypes.c_int, [P, P, I32, P, P, I64, ctypes.c_float, ctypes.c_float, P, P,
                                               ctypes.c_size_t, P]),
+        "tpf_mlp_train": (ctypes.c_int, [P, P, I32, P, P, I64, I32, I32, I32, I32, ctypes.c_float,
+                                         ctypes.c_float, ctypes.c_float, ctypes.c_uint64, P, P,
+                                         ctypes.c_size_t, P]),
         "tpf_mlp_predict": (ctypes.c_int, [P, P, I32, P, I64, P, P, ctypes.c_size_t, P]),
         "tpf_mlp_save": (ctypes.c_int, [P, ctypes.c_char_p]),
         "tpf_mlp_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(P)]),
@@ -388,26 +391,24 @@ class WarmStart:
         return V0
 
     def fit(self, S, t_index, V, epochs: int = 10, batch: int = 1024, lr: float = 1e-3, lr_min: float = 1e-5,
-            weight_decay: float = 1e-4, seed: int = 0):
-        """Mini-batch AdamW with a cosine learning-rate schedule; returns the mean loss per epoch."""
+            weight_decay: float = 1e-4, seed: int = 0, first_epoch: int = 0, total_epochs: Optional[int] = None):
+        """Mini-batch AdamW with a cosine learning-rate schedule (one tpf_mlp_train call):
+        epochs first_epoch .. first_epoch + epochs - 1 of a run of total_epochs (default:
+        first_epoch + epochs).  Returns the mean loss per epoch."""
         torch = _torch()
-        rows = S.shape[0]
-        nb = max(1, rows // batch)
-        total = epochs * nb
-        gen = torch.Generator(device="cpu").manual_seed(seed)
-        hist = []
-        k = 0
-        for _ in range(epochs):
-            perm = torch.randperm(rows, generator=gen).to(S.device)
-            acc = torch.zeros(1, dtype=torch.float32, device=S.device)
-            for b in range(nb):
-                idx = perm[b * batch:(b + 1) * batch]
-                rate = lr_min + 0.5 * (lr - lr_min) * (1 + np.cos(np.pi * k / max(1, total - 1)))
-                acc += self.train_step(S[idx].contiguous(), t_index[idx].contiguous(), V[idx].contiguous(),
-                                       rate, weight_decay)
-                k += 1
-            hist.append(float(acc) / nb)
-        return hist
+        rows = self._rows(S, t_index)
+        if V.shape != S.shape or V.dtype != S.dtype or not V.is_contiguous():
+            raise ValueError("V must match S")
+        total = first_epoch + epochs if total_epochs is None else int(total_epochs)
+        losses = torch.zeros(max(1, epochs), dtype=torch.float32, device=S.device)
+        ws = self._workspace(min(int(batch), rows), S.device)
+        with torch.cuda.device(S.device):
+            _check(load_library().tpf_mlp_train(self._h, S.data_ptr(), _dtype_code(S), t_index.data_ptr(),
+                                                V.data_ptr(), rows, int(first_epoch), int(epochs), total,
+                                                int(batch), float(lr), float(lr_min), float(weight_decay),
+                                                int(seed) & 0xFFFFFFFFFFFFFFFF, losses.data_ptr(), ws.data_ptr(),
+                                                ws.numel(), _stream_ptr(S.device)))
+        return [float(x) for x in losses[:epochs].cpu()]
 
     def save(self, path: str):
         _check(load_library().tpf_mlp_save(self._h, path.encode()))

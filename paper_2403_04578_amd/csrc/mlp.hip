@@ -14,6 +14,8 @@
 //   adamw_kernel       decoupled-weight-decay Adam on the FP32 master vector
 //   sync_kernel        BF16 copies of the weights in both layouts the GEMMs read
 //   predict_out_kernel y -> V0 = v_s + (y_re + j y_im)/20
+//   gather_rows_kernel one shuffled mini-batch (S, V, minute index) for training
+//   loss_accum_kernel  running mean of the batch losses of an epoch
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -423,6 +425,67 @@ __global__ void predict_out_kernel(const float *__restrict__ Y, int64_t ldy, int
     }
 }
 
+// Shuffling for mini-batch training: a pseudo-random permutation of [0, rows) per epoch,
+// evaluated independently for every position.  A balanced Feistel network on 2h-bit
+// integers (4 rounds, round function: the 64-bit finaliser of MurmurHash3 applied to the
+// key, the round and the right half) is a bijection of [0, 4^h); "cycle walking" (apply
+// it again while the value is >= rows) restricts it to a bijection of [0, rows), since
+// every cycle of the permutation that starts inside [0, rows) comes back into it.  With
+// 4^h < 4 rows the walk takes fewer than four steps on average.
+__device__ __forceinline__ uint64_t fmix64(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
+}
+
+__device__ __forceinline__ uint64_t feistel(uint64_t x, int h, uint64_t key) {
+    const uint64_t mask = (1ULL << h) - 1;
+    uint64_t L = x >> h, R = x & mask;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t F = fmix64(key ^ (0x9e3779b97f4a7c15ULL * (uint64_t)(r + 1)) ^ (R << 8)) & mask;
+        const uint64_t T = L ^ F;
+        L = R;
+        R = T;
+    }
+    return (L << h) | R;
+}
+
+__device__ __forceinline__ int64_t shuffled_row(int64_t i, int64_t rows, int h, uint64_t key) {
+    uint64_t x = (uint64_t)i;
+    do {
+        x = feistel(x, h, key);
+    } while (x >= (uint64_t)rows);
+    return (int64_t)x;
+}
+
+// Rows first .. first + count - 1 of an epoch's order: S, V (n complex each) and t into
+// the contiguous batch buffers.
+template <typename IO>
+__global__ void gather_rows_kernel(const IO *__restrict__ S, const IO *__restrict__ V,
+                                   const int64_t *__restrict__ t_index, int64_t rows, int n, int64_t first,
+                                   int64_t count, int h, uint64_t key, IO *__restrict__ Sb, IO *__restrict__ Vb,
+                                   int64_t *__restrict__ tb) {
+    // one wavefront per row: the permuted index is computed once and the row copied by 64 lanes
+    const int64_t r = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64;
+    const int lane = threadIdx.x & 63;
+    if (r >= count) return;
+    const int64_t src = shuffled_row(first + r, rows, h, key);
+    if (lane == 0) tb[r] = t_index[src];
+    for (int e = lane; e < 2 * n; e += 64) {
+        Sb[r * 2 * n + e] = S[src * 2 * n + e];
+        Vb[r * 2 * n + e] = V[src * 2 * n + e];
+    }
+}
+
+// acc[0] += loss[0] * scale (one lane)
+__global__ void loss_accum_kernel(const float *__restrict__ loss, float *__restrict__ acc, float scale) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) acc[0] += loss[0] * scale;
+}
+
 __global__ void zero_f32_kernel(float *p, int64_t count) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = 0.0f;
@@ -457,13 +520,16 @@ namespace {
 int64_t rows_pad(int64_t rows) { return (rows + 63) / 64 * 64; }
 
 // Workspace carving: X/activations bf16 [rows_pad][Dmax] x (L+1), pre-activations f32
-// [rows_pad][Dmax] x L, output f32 [rows_pad][Dout], gradient scratch bf16 x 2.
+// [rows_pad][Dmax] x L, output f32 [rows_pad][Dout], gradient scratch bf16 x 2, and the
+// buffers of one gathered training batch (S, V, minute index) for tpf_mlp_train.
 struct MlpWs {
     std::vector<__bf16 *> H;   // H[0] = X, H[l] = activation of hidden layer l
     std::vector<float *> Z;    // Z[l] pre-activation of hidden layer l (1-based, l = 1..L)
     float *Y = nullptr;
     __bf16 *G0 = nullptr, *G1 = nullptr;
     float *loss = nullptr;
+    void *Sb = nullptr, *Vb = nullptr;  // a gathered training batch [rows][n] complex (up to complex128)
+    int64_t *tb = nullptr;              // its minute indices
 };
 
 size_t carve(const tpf_mlp_s &M, int64_t rows, void *base, MlpWs *ws) {
@@ -490,11 +556,17 @@ size_t carve(const tpf_mlp_s &M, int64_t rows, void *base, MlpWs *ws) {
     char *g0 = take((size_t)rp * Dmax * 2);
     char *g1 = take((size_t)rp * Dmax * 2);
     char *ls = take(256);
+    char *sb = take((size_t)rows * M.n * 16);
+    char *vb = take((size_t)rows * M.n * 16);
+    char *tb = take((size_t)rows * 8);
     if (ws) {
         ws->Y = reinterpret_cast<float *>(y);
         ws->G0 = reinterpret_cast<__bf16 *>(g0);
         ws->G1 = reinterpret_cast<__bf16 *>(g1);
         ws->loss = reinterpret_cast<float *>(ls);
+        ws->Sb = sb;
+        ws->Vb = vb;
+        ws->tb = reinterpret_cast<int64_t *>(tb);
     }
     return off;
 }
@@ -519,6 +591,30 @@ int sync_weights(tpf_mlp_s &M, hipStream_t st) {
                            M.boff[l]);
     }
     return last_launch("weight sync");
+}
+
+// One AdamW step of the FP32 master parameters with the gradient in M.grad (step count
+// advanced first: the bias corrections use t = 1 on the first step), then the BF16 copies.
+int adamw_update(tpf_mlp_s &M, float lr, float wd, hipStream_t st) {
+    M.step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float bc1 = 1.0f - (float)std::pow((double)b1, (double)M.step);
+    const float bc2 = 1.0f - (float)std::pow((double)b2, (double)M.step);
+    hipLaunchKernelGGL(adamw_kernel, dim3(grid_for(M.P)), dim3(256), 0, st, M.p, M.grad, M.m, M.v, M.P, lr, wd, b1,
+                       b2, 1e-8f, bc1, bc2);
+    int rc = last_launch("AdamW");
+    if (rc != TPF_OK) return rc;
+    return sync_weights(M, st);
+}
+
+// The shuffle key of an epoch: MurmurHash3's 64-bit finaliser of the seed and epoch.
+uint64_t fmix64_host(uint64_t k) {
+    k ^= k >> 33;
+    k *= 0xff51afd7ed558ccdULL;
+    k ^= k >> 33;
+    k *= 0xc4ceb9fe1a85ec53ULL;
+    k ^= k >> 33;
+    return k;
 }
 
 template <bool AK, bool BK, int EP>
@@ -689,12 +785,16 @@ extern "C" size_t tpf_mlp_workspace_bytes(tpf_mlp M, int64_t rows) {
     return carve(*M, std::max<int64_t>(rows, 1), nullptr, nullptr);
 }
 
-static int mlp_args(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t, int64_t rows, void *ws, size_t wsb) {
+// Argument checks shared by the MLP calls; the workspace must hold ws_rows rows (the
+// rows of the call, or one batch for tpf_mlp_train).
+static int mlp_args(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t, int64_t rows, void *ws, size_t wsb,
+                    int64_t ws_rows = -1) {
+    if (ws_rows < 0) ws_rows = rows;
     if (!M) return fail(TPF_ERR_INVALID_ARG, "mlp is NULL");
     if (dtype != TPF_C64 && dtype != TPF_C128) return fail(TPF_ERR_INVALID_ARG, "bad dtype");
     if (rows < 0 || rows > ((int64_t)1 << 31)) return fail(TPF_ERR_INVALID_ARG, "bad row count");
     if (rows > 0 && (!S || !t)) return fail(TPF_ERR_INVALID_ARG, "NULL array");
-    if (rows > 0 && (!ws || wsb < tpf_mlp_workspace_bytes(M, rows)))
+    if (rows > 0 && (!ws || wsb < tpf_mlp_workspace_bytes(M, ws_rows)))
         return fail(TPF_ERR_INVALID_ARG, "workspace missing or smaller than tpf_mlp_workspace_bytes()");
     return check_device(*M);
 }
@@ -723,16 +823,58 @@ extern "C" int tpf_mlp_train_step(tpf_mlp M, const void *S, int32_t dtype, const
     int rc = tpf_mlp_loss_grad(M, S, dtype, t_index, V, rows, loss_out, M ? M->grad : nullptr, workspace,
                                workspace_bytes, stream);
     if (rc != TPF_OK) return rc;
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-    M->step += 1;
-    const float b1 = 0.9f, b2 = 0.999f;
-    const float bc1 = 1.0f - (float)std::pow((double)b1, (double)M->step);
-    const float bc2 = 1.0f - (float)std::pow((double)b2, (double)M->step);
-    hipLaunchKernelGGL(adamw_kernel, dim3(grid_for(M->P)), dim3(256), 0, st, M->p, M->grad, M->m, M->v, M->P, lr,
-                       weight_decay, b1, b2, 1e-8f, bc1, bc2);
-    rc = last_launch("AdamW");
+    return adamw_update(*M, lr, weight_decay, reinterpret_cast<hipStream_t>(stream));
+}
+
+extern "C" int tpf_mlp_train(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t_index, const void *V,
+                             int64_t rows, int32_t first_epoch, int32_t epochs, int32_t total_epochs, int32_t batch,
+                             float lr, float lr_min, float weight_decay, uint64_t seed, float *epoch_loss_out,
+                             void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    if (batch < 1) return fail(TPF_ERR_INVALID_ARG, "batch must be >= 1");
+    if (rows < 1) return fail(TPF_ERR_INVALID_ARG, "training needs at least one row");
+    const int64_t B = std::min<int64_t>(batch, rows);
+    int rc = mlp_args(M, S, dtype, t_index, rows, workspace, workspace_bytes, B);
     if (rc != TPF_OK) return rc;
-    return sync_weights(*M, st);
+    if (!V) return fail(TPF_ERR_INVALID_ARG, "NULL array");
+    if (first_epoch < 0 || epochs < 0 || total_epochs < 1 || first_epoch + (int64_t)epochs > total_epochs)
+        return fail(TPF_ERR_INVALID_ARG, "need 0 <= first_epoch, 0 <= epochs, first_epoch + epochs <= total_epochs");
+    if (!(lr >= 0.0f) || !(lr_min >= 0.0f) || !(weight_decay >= 0.0f))
+        return fail(TPF_ERR_INVALID_ARG, "lr, lr_min and weight_decay must be >= 0");
+    MlpWs ws;
+    carve(*M, B, workspace, &ws);
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    const int64_t nb = rows / B;  // batches per epoch; the rows past nb * B sit out the epoch
+    const double total = (double)total_epochs * (double)nb;
+    int h = 1;
+    while (h < 32 && ((uint64_t)1 << (2 * h)) < (uint64_t)rows) ++h;
+    for (int32_t e = first_epoch; e < first_epoch + epochs; ++e) {
+        float *acc = epoch_loss_out ? epoch_loss_out + (e - first_epoch) : nullptr;
+        if (acc) hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, st, acc, (int64_t)1);
+        const uint64_t key = fmix64_host(seed * 0x100000001b3ULL + (uint64_t)e);
+        for (int64_t b = 0; b < nb; ++b) {
+            const double k = (double)e * (double)nb + (double)b;
+            const double rate = (double)lr_min + 0.5 * ((double)lr - (double)lr_min) *
+                                                     (1.0 + std::cos(M_PI * k / std::max(1.0, total - 1.0)));
+            const unsigned blocks = (unsigned)((B + 3) / 4);
+            if (dtype == TPF_C128) {
+                hipLaunchKernelGGL(gather_rows_kernel<double>, dim3(blocks), dim3(256), 0, st, (const double *)S,
+                                   (const double *)V, t_index, rows, M->n, b * B, B, h, key, (double *)ws.Sb,
+                                   (double *)ws.Vb, ws.tb);
+                rc = loss_grad(*M, (const double *)ws.Sb, ws.tb, (const double *)ws.Vb, B, nullptr, M->grad, ws, st);
+            } else {
+                hipLaunchKernelGGL(gather_rows_kernel<float>, dim3(blocks), dim3(256), 0, st, (const float *)S,
+                                   (const float *)V, t_index, rows, M->n, b * B, B, h, key, (float *)ws.Sb,
+                                   (float *)ws.Vb, ws.tb);
+                rc = loss_grad(*M, (const float *)ws.Sb, ws.tb, (const float *)ws.Vb, B, nullptr, M->grad, ws, st);
+            }
+            if (rc != TPF_OK) return rc;
+            if (acc) hipLaunchKernelGGL(loss_accum_kernel, dim3(1), dim3(64), 0, st, ws.loss, acc, 1.0f / (float)nb);
+            rc = adamw_update(*M, (float)rate, weight_decay, st);
+            if (rc != TPF_OK) return rc;
+        }
+    }
+    return last_launch("MLP training");
 }
 
 extern "C" int tpf_mlp_predict(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t_index, int64_t rows,
@@ -792,22 +934,29 @@ extern "C" int tpf_mlp_predict(tpf_mlp M, const void *S, int32_t dtype, const in
 }
 
 namespace {
+// Parameter file: header, then the FP32 master parameters, the AdamW first and second
+// moments (each [P] float32).  Version 01 files (parameters only) load with a restarted
+// optimiser: step 0 and zero moments, so that the next step's bias corrections match.
 struct MlpFileHeader {
     char magic[8];
     int32_t n, hidden, layers, reserved;
     double vs_re, vs_im;
     int64_t step, P;
 };
+constexpr char kMagicV1[9] = "TPFMLP01", kMagicV2[9] = "TPFMLP02";
 }  // namespace
 
 extern "C" int tpf_mlp_save(tpf_mlp M, const char *path) {
     clear_error();
     if (!M || !path) return fail(TPF_ERR_INVALID_ARG, "NULL argument");
-    std::vector<float> host(M->P);
-    int rc = tpf_mlp_get_params(M, host.data());
-    if (rc != TPF_OK) return rc;
+    std::vector<float> host(3 * M->P);
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(host.data(), M->p, M->P * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(host.data() + M->P, M->m, M->P * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(host.data() + 2 * M->P, M->v, M->P * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return fail(TPF_ERR_DEVICE, "device-to-host copy failed");
     MlpFileHeader h{};
-    std::memcpy(h.magic, "TPFMLP01", 8);
+    std::memcpy(h.magic, kMagicV2, 8);
     h.n = M->n;
     h.hidden = M->hidden;
     h.layers = M->layers;
@@ -817,21 +966,24 @@ extern "C" int tpf_mlp_save(tpf_mlp M, const char *path) {
     h.P = M->P;
     FILE *f = std::fopen(path, "wb");
     if (!f) return fail(TPF_ERR_INVALID_ARG, std::string("cannot open ") + path);
-    const bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 && std::fwrite(host.data(), 4, M->P, f) == (size_t)M->P;
-    std::fclose(f);
-    return ok ? TPF_OK : fail(TPF_ERR_INVALID_ARG, std::string("write failed: ") + path);
+    const bool ok = std::fwrite(&h, sizeof h, 1, f) == 1 && std::fwrite(host.data(), 4, 3 * M->P, f) == (size_t)(3 * M->P);
+    const bool closed = std::fclose(f) == 0;
+    return ok && closed ? TPF_OK : fail(TPF_ERR_INVALID_ARG, std::string("write failed: ") + path);
 }
 
 extern "C" int tpf_mlp_load(const char *path, tpf_mlp *out) {
     clear_error();
     if (!path || !out) return fail(TPF_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
     FILE *f = std::fopen(path, "rb");
     if (!f) return fail(TPF_ERR_INVALID_ARG, std::string("cannot open ") + path);
     MlpFileHeader h{};
-    bool ok = std::fread(&h, sizeof h, 1, f) == 1 && std::memcmp(h.magic, "TPFMLP01", 8) == 0 && h.P > 0 &&
-              h.P < ((int64_t)1 << 31);
-    std::vector<float> host(ok ? h.P : 0);
-    ok = ok && std::fread(host.data(), 4, h.P, f) == (size_t)h.P;
+    bool ok = std::fread(&h, sizeof h, 1, f) == 1 && h.P > 0 && h.P < ((int64_t)1 << 31);
+    const bool v2 = ok && std::memcmp(h.magic, kMagicV2, 8) == 0;
+    ok = ok && (v2 || std::memcmp(h.magic, kMagicV1, 8) == 0);
+    const int64_t count = (v2 ? 3 : 1) * (ok ? h.P : 0);
+    std::vector<float> host(count);
+    ok = ok && std::fread(host.data(), 4, count, f) == (size_t)count;
     std::fclose(f);
     if (!ok) return fail(TPF_ERR_INVALID_ARG, std::string("not a warm-start parameter file: ") + path);
     int rc = tpf_mlp_create(h.n, h.hidden, h.layers, host.data(), h.vs_re, h.vs_im, out);
@@ -841,6 +993,14 @@ extern "C" int tpf_mlp_load(const char *path, tpf_mlp *out) {
         *out = nullptr;
         return fail(TPF_ERR_INVALID_ARG, "parameter count mismatch");
     }
-    (*out)->step = h.step;
+    if (v2) {
+        if (hipMemcpy((*out)->m, host.data() + h.P, h.P * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy((*out)->v, host.data() + 2 * h.P, h.P * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            tpf_mlp_free(*out);
+            *out = nullptr;
+            return fail(TPF_ERR_DEVICE, "host-to-device copy failed (AdamW moments)");
+        }
+        (*out)->step = h.step;
+    }
     return TPF_OK;
 }
