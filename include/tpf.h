@@ -41,6 +41,7 @@ extern "C" {
 #endif
 
 typedef struct tpf_network_s *tpf_network; /* opaque; immutable after build */
+typedef struct tpf_mlp_s *tpf_mlp;         /* opaque learned warm start (see below) */
 
 enum {
     TPF_OK = 0,
@@ -98,7 +99,13 @@ typedef struct {
                               non-finite value or a modulus outside [0.5, 1.5] pu starts flat. */
     double *mismatch_out;  /* device [tau] float64, or NULL: per-column max |S + V.*conj(Y_ds v_s +
                               Y_dd V)| of the returned V, computed in FP64 (Eq. (1) balance). */
-    double reserved1[4];
+    tpf_mlp warm_start;    /* learned warm start (tpf_mlp_create / tpf_mlp_load on this device) or
+                              NULL.  The solve evaluates it on S (as tpf_mlp_predict, into the
+                              workspace) and starts each column from its output, guarded like V0;
+                              V0 must then be NULL.  Any mode. */
+    const int64_t *t_index;  /* device int64 [tau]: minute index of each column for the warm
+                              start's calendar features, or NULL (t = column index) */
+    double reserved1[2];
 } tpf_options;
 
 /* Sec. II Eq. (1)-(2): build the network from its branch list.
@@ -166,7 +173,8 @@ int tpf_network_get_zw(tpf_network net, double *Z_out, double *w_out);
 /* Bytes of device workspace that tpf_solve_* needs for tau columns with these
  * options (opts may be NULL).  The solve calls allocate nothing themselves.  Small
  * networks need 256 B; the per-sweep path for large networks holds its state, operand
- * and active lists there (about tau * 2n * 16 B in FP64). */
+ * and active lists there (about tau * 2n * 16 B in FP64); a warm start adds its V0
+ * (tau * n * 16 B) and inference scratch. */
 size_t tpf_workspace_bytes(tpf_network net, int64_t tau, const tpf_options *opts);
 
 /* Algorithm 1 over a [T][n] load matrix (Sec. IV-A: each time step is a column).
@@ -215,8 +223,6 @@ int tpf_mismatch(tpf_network net, const void *S, const void *V, int32_t dtype, i
  * Parameters are one flat float32 vector [W_1 (out x in, row-major), b_1, W_2, b_2, ...].
  * A handle is bound to the device that is current when it is created.
  * --------------------------------------------------------------------------------------- */
-typedef struct tpf_mlp_s *tpf_mlp;
-
 /* n_pq PQ buses, `layers` hidden layers of width `hidden`; params: host float32 [num_params]
  * initial values (NULL: zeros); vs: slack voltage.  Errors: INVALID_ARG, DEVICE, OOM. */
 int tpf_mlp_create(int32_t n_pq, int32_t hidden, int32_t layers, const float *params, double vs_re,

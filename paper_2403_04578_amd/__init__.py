@@ -42,7 +42,8 @@ class TpfError(RuntimeError):
 
 class _Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("V0", ctypes.c_void_p),
-                ("mismatch_out", ctypes.c_void_p), ("reserved1", ctypes.c_double * 4)]
+                ("mismatch_out", ctypes.c_void_p), ("warm_start", ctypes.c_void_p), ("t_index", ctypes.c_void_p),
+                ("reserved1", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -201,28 +202,34 @@ def _stream_ptr(device):
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
-def workspace_bytes(net: Network, tau: int, mode: int = MODE_FP64) -> int:
-    o = _Options(mode=mode)
+def workspace_bytes(net: Network, tau: int, mode: int = MODE_FP64, warm_start=None) -> int:
+    o = _Options(mode=_MODES[mode] if isinstance(mode, str) else int(mode))
+    if warm_start is not None:
+        o.warm_start = warm_start.handle.value
     return int(load_library().tpf_workspace_bytes(net.handle, int(tau), ctypes.byref(o)))
 
 
 def solve_timeseries(net: Network, S, tol: float, max_iter: int, mode="fp64", V0=None,
-                     mismatch: bool = False, out=None):
+                     mismatch: bool = False, out=None, warm_start=None, t_index=None):
     """Algorithm 1 over S [T, n] (CUDA complex tensor).  Returns (V, iters, status[, mismatch]).
 
     ``mode``: "fp64" | "fp32" | "mixed_bf16" | "mixed_fp16" | "tree_fp64" | "tree_fp32" (or the MODE_* ints).
     ``V0``: optional start voltages [T, n] (same dtype); guarded columns fall back to flat.
+    ``warm_start``: a :class:`WarmStart` evaluated by the solve itself (instead of V0), with
+    ``t_index`` (int64 [T] minute indices, default: the column index) for its calendar features.
     """
-    return _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor=False)
+    return _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor=False, warm_start=warm_start,
+                  t_index=t_index)
 
 
 def solve_tensor(net: Network, S, tol: float, max_iter: int, mode="fp64", V0=None,
-                 mismatch: bool = False, out=None):
+                 mismatch: bool = False, out=None, warm_start=None, t_index=None):
     """Algorithm 1 over S [P, T, n]; outputs shaped [P, T, n], [P, T]."""
-    return _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor=True)
+    return _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor=True, warm_start=warm_start,
+                  t_index=t_index)
 
 
-def _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor):
+def _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor, warm_start=None, t_index=None):
     torch = _torch()
     lib = load_library()
     if not S.is_cuda:
@@ -246,10 +253,17 @@ def _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor):
         iters = torch.empty(lead, dtype=torch.int32, device=dev)
         status = torch.empty(lead, dtype=torch.int8, device=dev)
         mm = torch.empty(lead, dtype=torch.float64, device=dev) if mismatch else None
-        ws = torch.empty(max(workspace_bytes(net, tau, mode_i), 256), dtype=torch.uint8, device=dev)
+        ws = torch.empty(max(workspace_bytes(net, tau, mode_i, warm_start), 256), dtype=torch.uint8, device=dev)
     else:
         V, iters, status, mm, ws = out
     opts = _Options(mode=mode_i)
+    if warm_start is not None:
+        opts.warm_start = warm_start.handle.value
+        if t_index is not None:
+            if t_index.dtype != torch.int64 or t_index.numel() != tau or not t_index.is_contiguous() \
+                    or t_index.device != dev:
+                raise ValueError("t_index must be a contiguous int64 tensor with one entry per column")
+            opts.t_index = t_index.data_ptr()
     if V0 is not None:
         if V0.shape != S.shape or V0.dtype != S.dtype or not V0.is_contiguous() or V0.device != dev:
             raise ValueError("V0 must match S in shape, dtype and device and be contiguous")
@@ -272,7 +286,7 @@ def _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor):
     return V, iters, status
 
 
-def alloc_outputs(net: Network, S, mode="fp64", mismatch: bool = False, tensor: bool = False):
+def alloc_outputs(net: Network, S, mode="fp64", mismatch: bool = False, tensor: bool = False, warm_start=None):
     """Pre-allocates (V, iters, status, mismatch, workspace) for repeated solves of S's shape."""
     torch = _torch()
     lead = tuple(S.shape[:2]) if tensor else (S.shape[0],)
@@ -282,7 +296,7 @@ def alloc_outputs(net: Network, S, mode="fp64", mismatch: bool = False, tensor: 
     return (torch.empty_like(S), torch.empty(lead, dtype=torch.int32, device=dev),
             torch.empty(lead, dtype=torch.int8, device=dev),
             torch.empty(lead, dtype=torch.float64, device=dev) if mismatch else None,
-            torch.empty(max(workspace_bytes(net, tau, mode_i), 256), dtype=torch.uint8, device=dev))
+            torch.empty(max(workspace_bytes(net, tau, mode_i, warm_start), 256), dtype=torch.uint8, device=dev))
 
 
 def mismatch(net: Network, S, V):
@@ -326,6 +340,10 @@ class WarmStart:
         self.n = int(n_pq)
         self.num_params = int(lib.tpf_mlp_num_params(self._h))
         self._ws = None
+
+    @property
+    def handle(self):
+        return self._h
 
     def _workspace(self, rows, device):
         torch = _torch()

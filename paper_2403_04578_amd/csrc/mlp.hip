@@ -52,7 +52,7 @@ __global__ void features_kernel(const IO *__restrict__ S, const int64_t *__restr
             } else if (f < 2 * n) {
                 v = kFeatScale * (float)S[2 * (r * n + f - n) + 1];
             } else if (f < 2 * n + 4) {
-                const int64_t t = t_index[r];
+                const int64_t t = t_index ? t_index[r] : r;
                 const double mod = (double)(t % 1440) / 1440.0;
                 const double day = (double)((t / 1440) % 365) / 365.0;
                 const double ang = 2.0 * M_PI * (f < 2 * n + 2 ? mod : day);
@@ -211,6 +211,32 @@ __global__ void sync_kernel(const float *__restrict__ p, int64_t woff, int in, i
     }
 }
 
+// BF16 MFMA A fragments of layer l, [T][K / 32][64 lanes][8] (lane (g, j) of fragment (t, s)
+// holds row 16 t + j, inputs 32 s + 8 g .. 32 s + 8 g + 7): element (row r, input k) goes to
+// ((t K/32 + s) 64 + 16 g + j) 8 + i with r = 16 t + j, k = 32 s + 8 g + i.  With
+// n_out_pairs = n > 0 (the output layer) row r holds neuron (r % 2) n + r / 2, i.e. Re and
+// Im of PQ bus r / 2 interleaved; otherwise row r is neuron r.  With n_in_pairs = n > 0 (the
+// first layer) input k < 2 n is feature (k % 2) n + k / 2, i.e. 50 P and 50 Q of bus k / 2
+// interleaved, and inputs from 2 n on (the calendar phases) keep their place.  Padding is zero.
+__global__ void frag_kernel(const float *__restrict__ p, int64_t woff, int64_t boff, int in, int out, int in_p,
+                            int rows, int n_out_pairs, int n_in_pairs, uint16_t *__restrict__ Wf,
+                            float *__restrict__ bf) {
+    const int64_t total = (int64_t)rows * in_p;
+    const int ks = in_p / 32;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / in_p), k = (int)(e - (int64_t)r * in_p);
+        int o = r;
+        if (n_out_pairs > 0) o = r / 2 < n_out_pairs ? (r % 2) * n_out_pairs + r / 2 : out;
+        int ki = k;
+        if (n_in_pairs > 0 && k < 2 * n_in_pairs) ki = (k % 2) * n_in_pairs + k / 2;
+        const float w = (o < out && ki < in) ? p[woff + (int64_t)o * in + ki] : 0.0f;
+        const int t = r / 16, j = r % 16, s = k / 32, g = (k % 32) / 8, i = k % 8;
+        const __bf16 h = (__bf16)w;
+        Wf[((((int64_t)t * ks + s) * 64) + 16 * g + j) * 8 + i] = *reinterpret_cast<const uint16_t *>(&h);
+        if (k == 0) bf[r] = o < out ? p[boff + o] : 0.0f;
+    }
+}
+
 // ---- fused inference (every padded layer width <= 256)
 //
 // One workgroup of 4 waves carries a tile of 16 RT rows from the loads to the start
@@ -218,10 +244,13 @@ __global__ void sync_kernel(const float *__restrict__ p, int64_t woff, int in, i
 // LDS ([rows][264] BF16, updated in place between two barriers: the layer's outputs wait
 // in the accumulators until every wave has read its inputs), and the voltage write.  Wave
 // w owns output neurons 64 w .. 64 w + 63 of all rows (RT x 4 tiles of 16x16x32) and
-// streams its weight fragments from L2 two k-steps ahead; with RT = 8 each fragment feeds
-// 32 products, halving the weight traffic per row against 64-row tiles.  The output layer
-// goes through LDS as FP32, 64 rows at a time, so that the voltages leave as contiguous
-// complex stores.  Nothing but S and V0 touches HBM.
+// streams its weight fragments (the fragment copy: 1 KB contiguous per fragment) from L2
+// two k-steps ahead; with RT = 8 each fragment feeds 32 products, halving the weight
+// traffic per row against 64-row tiles.  The first layer's inputs and the output layer's
+// neurons are ordered (Re, Im) per bus, so each complex load of S becomes one 4-byte LDS
+// write and each complex voltage two adjacent outputs.  The output layer goes through LDS
+// as FP32, 64 rows at a time, so that the voltages leave as contiguous complex stores.
+// Nothing but S and V0 touches HBM.
 constexpr int kFusedWidth = 256, kHStride = 264, kYStride = 257;
 
 // Complex pairs as clang vectors, so that the streamed loads and stores can carry the
@@ -232,9 +261,11 @@ struct Pair {
 };
 
 struct MlpView {
-    const __bf16 *W[17];  // [out_p][in_p] per layer
-    const float *b[17];   // padded bias per layer
-    int dp[18];           // padded widths
+    const uint16_t *W[17];  // BF16 MFMA fragments per layer (frag_kernel: interleaved first-layer
+                            // inputs and output rows)
+    const float *b[17];     // bias in the fragments' row order
+    int T[17];              // row tiles of each layer's fragment copy
+    int dp[18];             // padded widths
     int L, n;
 };
 
@@ -291,9 +322,11 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
             }
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
-                if (e0 + 256 * u < total) {
-                    H[r * kHStride + b] = (__bf16)(kFeatScale * (float)v[u].x);
-                    H[r * kHStride + n + b] = (__bf16)(kFeatScale * (float)v[u].y);
+                if (e0 + 256 * u < total) {  // (50 P, 50 Q) of bus b at inputs 2 b, 2 b + 1
+                    const __bf16 hr = (__bf16)(kFeatScale * (float)v[u].x), hi = (__bf16)(kFeatScale * (float)v[u].y);
+                    reinterpret_cast<uint32_t *>(H)[r * (kHStride / 2) + b] =
+                        (uint32_t)*reinterpret_cast<const uint16_t *>(&hr) |
+                        ((uint32_t)*reinterpret_cast<const uint16_t *>(&hi) << 16);
                 }
                 r += dr;
                 b += db;
@@ -308,7 +341,7 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
             const int rr = p >> 2, f = 2 * n + (p & 3);
             float v = 0.0f;
             if (rr < valid_rows) {
-                const int64_t t = t_index[r0 + rr];
+                const int64_t t = t_index ? t_index[r0 + rr] : r0 + rr;
                 const double mod = (double)(t % 1440) / 1440.0;
                 const double day = (double)((t / 1440) % 365) / 365.0;
                 const double ang = 2.0 * M_PI * (f < 2 * n + 2 ? mod : day);
@@ -321,9 +354,9 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
     }
     __syncthreads();
     for (int l = 0; l <= mv.L; ++l) {
-        const int K = mv.dp[l], N = mv.dp[l + 1];
+        const int K = mv.dp[l], T = mv.T[l];
         const int n0 = 64 * wave;
-        const bool mine = n0 < N;
+        const bool mine = 4 * wave < T;
         const bool last = l == mv.L;
         f4 acc[RT][4];
 #pragma unroll
@@ -333,11 +366,16 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
         if (mine) {
             // weight fragments stream from L2 through a ring of three register sets, two
             // k-steps ahead of the products that use them (K <= 256: at most 8 k-steps)
-            const __bf16 *Wl = mv.W[l] + (int64_t)(n0 + j) * K + 8 * g;
             const int ks = K / 32;
+            // fragment (tile 4 wave + b, k-step k0 / 32): lane (g, j) holds neuron 16 t + j,
+            // inputs k0 + 8 g .. k0 + 8 g + 7 -- the B operand of these products
+            const uint16_t *Wl = mv.W[l] + (size_t)lane * 8;
             auto ldw = [&](b8(&w)[4], int k0) {
 #pragma unroll
-                for (int b = 0; b < 4; ++b) w[b] = *reinterpret_cast<const b8 *>(Wl + (int64_t)16 * b * K + k0);
+                for (int b = 0; b < 4; ++b) {
+                    const int t = 4 * wave + b;
+                    w[b] = t < T ? *reinterpret_cast<const b8 *>(Wl + ((size_t)t * ks + k0 / 32) * 512) : b8{};
+                }
             };
             b8 w[3][4];
 #pragma unroll
@@ -364,7 +402,7 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int col = n0 + 16 * b + j;
-                    const float bc = bias[col];
+                    const float bc = 4 * wave + b < T ? bias[col] : 0.0f;
 #pragma unroll
                     for (int a = 0; a < RT; ++a)
 #pragma unroll
@@ -384,7 +422,7 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                     const int col = n0 + 16 * b + j;
-                    const float bc = bias[col];
+                    const float bc = 4 * wave + b < T ? bias[col] : 0.0f;  // the bias has 16 T entries
 #pragma unroll
                     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -398,8 +436,8 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
             int r = tid / n, b = tid - (tid / n) * n;
             const int dr = 256 / n, db = 256 - dr * n;
             for (int e = tid; e < 64 * n && e < valid; e += 256) {
-                const P2 o = P2{(IO)(vs_re + (double)Yf[r * kYStride + b] * inv_scale),
-                                (IO)(vs_im + (double)Yf[r * kYStride + n + b] * inv_scale)};
+                const P2 o = P2{(IO)(vs_re + (double)Yf[r * kYStride + 2 * b] * inv_scale),
+                                (IO)(vs_im + (double)Yf[r * kYStride + 2 * b + 1] * inv_scale)};
                 __builtin_nontemporal_store(o, dst + (int64_t)64 * half * n + e);
                 r += dr;
                 b += db;
@@ -512,6 +550,9 @@ struct tpf_mlp_s {
     float *p = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;  // device FP32 [P]
     std::vector<__bf16 *> Wt, Wn;        // device BF16 copies per layer
     std::vector<float *> bias;           // device padded FP32 bias per layer
+    std::vector<uint16_t *> Wf;          // BF16 MFMA A fragments per layer (frag_kernel)
+    std::vector<float *> bf;             // bias in the fragments' row order
+    std::vector<int> frows;              // rows of the fragment copy per layer (16 T)
     std::vector<void *> owned;
 };
 
@@ -589,6 +630,9 @@ int sync_weights(tpf_mlp_s &M, hipStream_t st) {
         hipLaunchKernelGGL(sync_kernel, dim3(grid_for((int64_t)M.dp[l] * M.dp[l + 1])), dim3(256), 0, st, M.p,
                            M.woff[l], M.d[l], M.d[l + 1], M.dp[l], M.dp[l + 1], M.Wt[l], M.Wn[l], M.bias[l],
                            M.boff[l]);
+        hipLaunchKernelGGL(frag_kernel, dim3(grid_for((int64_t)M.frows[l] * M.dp[l])), dim3(256), 0, st, M.p,
+                           M.woff[l], M.boff[l], M.d[l], M.d[l + 1], M.dp[l], M.frows[l], l == M.layers ? M.n : 0,
+                           l == 0 ? M.n : 0, M.Wf[l], M.bf[l]);
     }
     return last_launch("weight sync");
 }
@@ -725,10 +769,16 @@ extern "C" int tpf_mlp_create(int32_t n_pq, int32_t hidden, int32_t layers, cons
     M->Wt.resize(layers + 1);
     M->Wn.resize(layers + 1);
     M->bias.resize(layers + 1);
+    M->Wf.resize(layers + 1);
+    M->bf.resize(layers + 1);
+    M->frows.resize(layers + 1);
+    for (int l = 0; l <= layers; ++l) M->frows[l] = l < layers ? M->dp[l + 1] : 16 * ((n_pq + 7) / 8);
     for (int l = 0; ok && l <= layers; ++l)
         ok = dalloc((void **)&M->Wt[l], (size_t)M->dp[l] * M->dp[l + 1] * 2) &&
              dalloc((void **)&M->Wn[l], (size_t)M->dp[l] * M->dp[l + 1] * 2) &&
-             dalloc((void **)&M->bias[l], (size_t)M->dp[l + 1] * 4);
+             dalloc((void **)&M->bias[l], (size_t)M->dp[l + 1] * 4) &&
+             dalloc((void **)&M->Wf[l], (size_t)M->dp[l] * M->frows[l] * 2) &&
+             dalloc((void **)&M->bf[l], (size_t)M->frows[l] * 4);
     if (!ok) {
         tpf_mlp_free(M);
         return fail(TPF_ERR_OOM, "device allocation failed (MLP)");
@@ -877,27 +927,28 @@ extern "C" int tpf_mlp_train(tpf_mlp M, const void *S, int32_t dtype, const int6
     return last_launch("MLP training");
 }
 
-extern "C" int tpf_mlp_predict(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t_index, int64_t rows,
-                               void *V0_out, void *workspace, size_t workspace_bytes, void *stream) {
-    clear_error();
-    int rc = mlp_args(M, S, dtype, t_index, rows, workspace, workspace_bytes);
-    if (rc != TPF_OK) return rc;
-    if (rows == 0) return TPF_OK;
-    if (!V0_out) return fail(TPF_ERR_INVALID_ARG, "NULL array");
-    MlpWs ws;
-    carve(*M, rows, workspace, &ws);
-    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+namespace {
+
+bool fused_predict_fits(const tpf_mlp_s &M) {
     int Dmax = 0;
-    for (int w : M->dp) Dmax = std::max(Dmax, w);
-    if (Dmax <= kFusedWidth && 2 * M->n + 4 <= M->dp[0]) {
+    for (int w : M.dp) Dmax = std::max(Dmax, w);
+    return Dmax <= kFusedWidth && 2 * M.n + 4 <= M.dp[0];
+}
+
+// V0 for `rows` rows: the fused kernel when every padded width is <= 256, else the
+// layer-by-layer GEMMs in the carved workspace `ws`.  t_index may be NULL (t = row).
+int predict_impl(tpf_mlp_s &M, const void *S, int32_t dtype, const int64_t *t_index, int64_t rows, void *V0_out,
+                 void *workspace, hipStream_t st) {
+    if (fused_predict_fits(M)) {
         MlpView mv{};
-        for (int l = 0; l <= M->layers; ++l) {
-            mv.W[l] = M->Wt[l];
-            mv.b[l] = M->bias[l];
+        for (int l = 0; l <= M.layers; ++l) {
+            mv.W[l] = M.Wf[l];
+            mv.b[l] = M.bf[l];
+            mv.T[l] = M.frows[l] / 16;
         }
-        for (int l = 0; l < M->layers + 2; ++l) mv.dp[l] = M->dp[l];
-        mv.L = M->layers;
-        mv.n = M->n;
+        for (int l = 0; l < M.layers + 2; ++l) mv.dp[l] = M.dp[l];
+        mv.L = M.layers;
+        mv.n = M.n;
         constexpr int RT = 8;
         constexpr size_t lds = fused_lds<RT>();
         const unsigned blocks = (unsigned)((rows + 16 * RT - 1) / (16 * RT));
@@ -906,32 +957,67 @@ extern "C" int tpf_mlp_predict(tpf_mlp M, const void *S, int32_t dtype, const in
             if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
                 hipSuccess)
                 return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
-            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, (const double *)S, t_index, rows, mv, M->vs_re,
-                               M->vs_im, (double *)V0_out);
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, (const double *)S, t_index, rows, mv, M.vs_re,
+                               M.vs_im, (double *)V0_out);
         } else {
             auto k = predict_fused_kernel<float, RT>;
             if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
                 hipSuccess)
                 return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
-            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, (const float *)S, t_index, rows, mv, M->vs_re,
-                               M->vs_im, (float *)V0_out);
+            hipLaunchKernelGGL(k, dim3(blocks), dim3(256), lds, st, (const float *)S, t_index, rows, mv, M.vs_re,
+                               M.vs_im, (float *)V0_out);
         }
         return last_launch("MLP fused predict");
     }
+    MlpWs ws;
+    carve(M, rows, workspace, &ws);
+    int Dmax = 0;
+    for (int w : M.dp) Dmax = std::max(Dmax, w);
+    int rc;
     if (dtype == TPF_C128) {
-        rc = forward(*M, (const double *)S, t_index, rows, ws, st);
+        rc = forward(M, (const double *)S, t_index, rows, ws, st);
         if (rc == TPF_OK)
-            hipLaunchKernelGGL(predict_out_kernel<double>, dim3(grid_for(rows * M->n)), dim3(256), 0, st, ws.Y,
-                               (int64_t)Dmax, M->n, rows, M->vs_re, M->vs_im, (double *)V0_out);
+            hipLaunchKernelGGL(predict_out_kernel<double>, dim3(grid_for(rows * M.n)), dim3(256), 0, st, ws.Y,
+                               (int64_t)Dmax, M.n, rows, M.vs_re, M.vs_im, (double *)V0_out);
     } else {
-        rc = forward(*M, (const float *)S, t_index, rows, ws, st);
+        rc = forward(M, (const float *)S, t_index, rows, ws, st);
         if (rc == TPF_OK)
-            hipLaunchKernelGGL(predict_out_kernel<float>, dim3(grid_for(rows * M->n)), dim3(256), 0, st, ws.Y,
-                               (int64_t)Dmax, M->n, rows, M->vs_re, M->vs_im, (float *)V0_out);
+            hipLaunchKernelGGL(predict_out_kernel<float>, dim3(grid_for(rows * M.n)), dim3(256), 0, st, ws.Y,
+                               (int64_t)Dmax, M.n, rows, M.vs_re, M.vs_im, (float *)V0_out);
     }
     if (rc != TPF_OK) return rc;
     return last_launch("MLP predict");
 }
+
+}  // namespace
+
+extern "C" int tpf_mlp_predict(tpf_mlp M, const void *S, int32_t dtype, const int64_t *t_index, int64_t rows,
+                               void *V0_out, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    int rc = mlp_args(M, S, dtype, t_index, rows, workspace, workspace_bytes);
+    if (rc != TPF_OK) return rc;
+    if (rows == 0) return TPF_OK;
+    if (!V0_out) return fail(TPF_ERR_INVALID_ARG, "NULL array");
+    return predict_impl(*M, S, dtype, t_index, rows, V0_out, workspace, reinterpret_cast<hipStream_t>(stream));
+}
+
+namespace tpf {
+
+size_t mlp_predict_scratch_bytes(tpf_mlp M, int64_t rows) {
+    if (!M || fused_predict_fits(*M)) return 0;
+    return carve(*M, std::max<int64_t>(rows, 1), nullptr, nullptr);
+}
+
+int mlp_predict_into(tpf_mlp M, const void *S, int dtype, const int64_t *t_index, int64_t rows, void *V0,
+                     void *scratch, hipStream_t stream) {
+    if (!M) return fail(TPF_ERR_INVALID_ARG, "warm-start network is NULL");
+    int rc = check_device(*M);
+    if (rc != TPF_OK) return rc;
+    if (rows == 0) return TPF_OK;
+    return predict_impl(*M, S, dtype, t_index, rows, V0, scratch, stream);
+}
+
+}  // namespace tpf
 
 namespace {
 // Parameter file: header, then the FP32 master parameters, the AdamW first and second

@@ -73,6 +73,13 @@ struct DeviceNet {
     std::vector<void *> owned;   // every allocation above, freed with the network
 };
 
+// Inference into V0 (device [rows][n], dtype of S), as tpf_mlp_predict, for the solve
+// calls' warm start when the fused kernel does not apply; `t_index` may be NULL (t =
+// column index).  `scratch` holds at least mlp_predict_scratch_bytes(mlp, rows) bytes.
+size_t mlp_predict_scratch_bytes(tpf_mlp mlp, int64_t rows);
+int mlp_predict_into(tpf_mlp mlp, const void *S, int dtype, const int64_t *t_index, int64_t rows, void *V0,
+                     void *scratch, hipStream_t stream);
+
 // Sparse Y_dd and c = Y_ds v_s on the device, for the FP64 power-balance mismatch
 // (Eq. (1)); `out` is NULL when no mismatch is requested.
 }  // namespace tpf
