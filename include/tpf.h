@@ -200,6 +200,21 @@ int tpf_solve_tensor(tpf_network net, const void *S, int32_t dtype, int64_t n_sc
                      int32_t *iters_out, int8_t *status_out, void *workspace,
                      size_t workspace_bytes, void *stream);
 
+/* Allocation-free variant of tpf_solve_timeseries, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments and results as tpf_solve_timeseries without the workspace: the scratch its
+ * kernels need (the atomic column queue of the persistent sweep kernels) lives in a static
+ * device array of 4096 bytes that each GPU holds until the process ends.  It allocates
+ * nothing: the network must already be resident on the current device (the first
+ * tpf_solve_timeseries, tpf_solve_tensor or tpf_mismatch call with it there uploads it), else
+ * TPF_ERR_UNSUPPORTED.  A request whose tpf_workspace_bytes exceeds 4096 -- the per-sweep path
+ * of large networks, a learned warm start -- returns TPF_ERR_UNSUPPORTED.  Every call on a
+ * GPU uses that GPU's one array (cleared by each call where it must start at zero), so calls
+ * that overlap on one GPU (other streams or threads) race: the caller serialises them. */
+int tpf_solve_timeseries_noalloc(tpf_network net, const void *S, int32_t dtype, int64_t T, double tol,
+                                 int32_t max_iter, const tpf_options *opts, void *V_out, int32_t *iters_out,
+                                 int8_t *status_out, void *stream);
+
 /* FP64 power-balance mismatch of given voltages (Eq. (1)):
  * out[c] = max_i |S_ci + V_ci conj((Y_ds v_s)_i + (Y_dd V_c)_i)|
  * (for a ZIP network the load term S_ci is S_ci (alpha_P,i + alpha_I,i V_ci)).

@@ -68,6 +68,7 @@ def load_library() -> ctypes.CDLL:
         "tpf_workspace_bytes": (ctypes.c_size_t, [P, I64, P]),
         "tpf_solve_timeseries": (ctypes.c_int, [P, P, I32, I64, D, I32, P, P, P, P, P, ctypes.c_size_t, P]),
         "tpf_solve_tensor": (ctypes.c_int, [P, P, I32, I64, I64, D, I32, P, P, P, P, P, ctypes.c_size_t, P]),
+        "tpf_solve_timeseries_noalloc": (ctypes.c_int, [P, P, I32, I64, D, I32, P, P, P, P, P]),
         "tpf_mismatch": (ctypes.c_int, [P, P, P, I32, I64, P, P]),
         "tpf_last_error": (ctypes.c_char_p, []),
         "tpf_mlp_create": (ctypes.c_int, [I32, I32, I32, P, D, D, ctypes.POINTER(P)]),
@@ -284,6 +285,35 @@ def _solve(net, S, tol, max_iter, mode, V0, mismatch, out, tensor, warm_start=No
     if mismatch:
         return V, iters, status, mm
     return V, iters, status
+
+
+def solve_timeseries_noalloc(net: Network, S, tol: float, max_iter: int, mode="fp64", V0=None, out=None,
+                             mismatch: bool = False):
+    """tpf_solve_timeseries_noalloc: the solve without a workspace (the library's static
+    scratch; the network must already be resident on S's device).  ``out`` = (V, iters,
+    status[, mismatch]) preallocated by the caller, or None (allocated here by torch)."""
+    torch = _torch()
+    lib = load_library()
+    if not S.is_cuda or not S.is_contiguous() or S.dim() != 2 or S.shape[1] != net.n:
+        raise ValueError(f"S must be a contiguous device tensor [T, {net.n}]")
+    T = S.shape[0]
+    dev = S.device
+    if out is None:
+        out = (torch.empty_like(S), torch.empty(T, dtype=torch.int32, device=dev),
+               torch.empty(T, dtype=torch.int8, device=dev),
+               torch.empty(T, dtype=torch.float64, device=dev) if mismatch else None)
+    V, iters, status, mm = (tuple(out) + (None,))[:4]
+    opts = _Options(mode=_MODES[mode] if isinstance(mode, str) else int(mode))
+    if V0 is not None:
+        opts.V0 = V0.data_ptr()
+    if mm is not None:
+        opts.mismatch_out = mm.data_ptr()
+    with torch.cuda.device(dev):
+        rc = lib.tpf_solve_timeseries_noalloc(net.handle, S.data_ptr(), _dtype_code(S), T, float(tol), int(max_iter),
+                                              ctypes.byref(opts), V.data_ptr(), iters.data_ptr(), status.data_ptr(),
+                                              _stream_ptr(dev))
+    _check(rc)
+    return (V, iters, status, mm) if mm is not None else (V, iters, status)
 
 
 def alloc_outputs(net: Network, S, mode="fp64", mismatch: bool = False, tensor: bool = False, warm_start=None):

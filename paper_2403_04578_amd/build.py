@@ -22,7 +22,7 @@ LIB = os.path.join(HERE, "libtpf.so")
 ARCH = os.environ.get("TPF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["network.cpp", "capi.cpp", "fpi_small.hip", "fpi_mixed.hip", "mismatch.hip", "mlp.hip", "fpi_large.hip",
-           "fpi_tree.hip"]
+           "fpi_tree.hip", "noalloc.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

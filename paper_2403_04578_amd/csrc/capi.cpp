@@ -48,10 +48,11 @@ extern "C" size_t tpf_workspace_bytes(tpf_network net, int64_t tau, const tpf_op
     return warm ? align256(base) + warm : base;
 }
 
-extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtype, int64_t T, double tol,
-                                    int32_t max_iter, const tpf_options *opts, void *V_out, int32_t *iters_out,
-                                    int8_t *status_out, void *workspace, size_t workspace_bytes, void *stream) {
-    clear_error();
+namespace tpf {
+
+int solve_impl(tpf_network net, const void *S, int32_t dtype, int64_t T, double tol, int32_t max_iter,
+               const tpf_options *opts, void *V_out, int32_t *iters_out, int8_t *status_out, void *workspace,
+               size_t workspace_bytes, void *stream, bool resident_only) {
     if (!net) return fail(TPF_ERR_INVALID_ARG, "net is NULL");
     if (!valid_dtype(dtype)) return fail(TPF_ERR_INVALID_ARG, "dtype must be TPF_C64 or TPF_C128");
     if (T < 0) return fail(TPF_ERR_INVALID_ARG, "T must be >= 0");
@@ -73,7 +74,7 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
     if (reinterpret_cast<uintptr_t>(workspace) % 256 != 0) return fail(TPF_ERR_INVALID_ARG, "workspace not 256-byte aligned");
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     DeviceNet *dn = nullptr;
-    int rc = device_net(net, &dn);
+    int rc = resident_only ? device_net_resident(net, &dn) : device_net(net, &dn);
     if (rc != TPF_OK) return rc;
     double *mismatch_out = opts ? opts->mismatch_out : nullptr;
     const int64_t *t_index = opts ? opts->t_index : nullptr;
@@ -115,6 +116,16 @@ extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtyp
         if (rc == TPF_OK) rc = check_launch("mismatch kernel launch");
     }
     return rc;
+}
+
+}  // namespace tpf
+
+extern "C" int tpf_solve_timeseries(tpf_network net, const void *S, int32_t dtype, int64_t T, double tol,
+                                    int32_t max_iter, const tpf_options *opts, void *V_out, int32_t *iters_out,
+                                    int8_t *status_out, void *workspace, size_t workspace_bytes, void *stream) {
+    clear_error();
+    return solve_impl(net, S, dtype, T, tol, max_iter, opts, V_out, iters_out, status_out, workspace,
+                      workspace_bytes, stream, false);
 }
 
 extern "C" int tpf_solve_tensor(tpf_network net, const void *S, int32_t dtype, int64_t n_scen, int64_t T, double tol,

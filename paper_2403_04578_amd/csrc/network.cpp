@@ -320,6 +320,17 @@ int device_net(tpf_network net, DeviceNet **out) {
     return TPF_OK;
 }
 
+int device_net_resident(tpf_network net, DeviceNet **out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(TPF_ERR_DEVICE, "hipGetDevice failed (no GPU?)");
+    std::lock_guard<std::mutex> lock(net->mu);
+    if ((int)net->dev.size() <= dev || !net->dev[dev])
+        return fail(TPF_ERR_UNSUPPORTED, "the network is not yet resident on this device (a first tpf_solve_timeseries, "
+                                         "tpf_solve_tensor or tpf_mismatch call with it uploads it)");
+    *out = net->dev[dev];
+    return TPF_OK;
+}
+
 }  // namespace tpf
 
 using namespace tpf;

@@ -119,6 +119,13 @@ void clear_error();
 
 // Returns the device copies of `net` on the current device, uploading on first use.
 int device_net(tpf_network net, DeviceNet **out);
+// The same when the copies already exist on the current device; TPF_ERR_UNSUPPORTED
+// otherwise (allocates nothing).
+int device_net_resident(tpf_network net, DeviceNet **out);
+// tpf_solve_timeseries's body; resident_only: the network must already be on the device.
+int solve_impl(tpf_network net, const void *S, int32_t dtype, int64_t T, double tol, int32_t max_iter,
+               const tpf_options *opts, void *V_out, int32_t *iters_out, int8_t *status_out, void *workspace,
+               size_t workspace_bytes, void *stream, bool resident_only);
 
 // Launchers (device code in fpi_small.hip / mismatch.hip).  All asynchronous on `stream`.
 int launch_fpi_small_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, int dtype,
