@@ -75,7 +75,8 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
  *             D_b = D_parent + z_b J_b (slack to leaves).  Same iterates up to rounding,
  *             O(n) instead of 8 n^2 flops per column and sweep.  Needs a network with
  *             n_bus - 1 branches (a tree): single-phase with n <= 1024 PQ buses, or
- *             three-phase (3x3 blocks per branch) with at most 512 PQ buses; returns
+ *             three-phase (3x3 blocks per branch) with at most 408 PQ buses in TREE_FP64
+ *             (the LDS holds 400 bytes of state per bus) and 512 in TREE_FP32; returns
  *             TPF_ERR_UNSUPPORTED otherwise. */
 /* TREE_FP32   the tree operator in FP32 arithmetic with the state kept as the FP32 drop
  *             V - w (as in FP32 mode; tol >= 5e-7 pu); the same networks as TREE_FP64. */

@@ -372,7 +372,7 @@ __global__ void inject_refine_kernel(const IO *__restrict__ S, const float *__re
             const long long c = act[a], o = 2 * (c * n + b);
             const float sr = (float)S[o], si = (float)S[o + 1];
             const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
-            const float r = 1.0f / (vr * vr + vi * vi);
+            const float r = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
             out = zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, aP, aI, b);
             *reinterpret_cast<float2 *>(Ip + o) = out;
         }
@@ -402,7 +402,7 @@ __global__ void inject_low_kernel(const IO *__restrict__ S, const float *__restr
             const float ks = ms[c].ks;
             const float sr = (float)S[o], si = (float)S[o + 1];
             const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
-            const float r = 1.0f / (vr * vr + vi * vi);
+            const float r = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
             const float2 iz = zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, aP, aI, b);
             const float ir = iz.x, ii = iz.y;
             float br = ir, bi = ii;

@@ -79,7 +79,7 @@ struct LowOps<TPF_MODE_FP32> : LowOps<TPF_MODE_MIXED_BF16> {};
 // conj(S./V) = conj(S) V / |V|^2 for the two buses (Re, Im, Re, Im) of a lane's tile.
 __device__ __forceinline__ f4 injection(const f4 &s, float w0r, float w0i, float w1r, float w1i, const f4 &u) {
     const float v0r = w0r + u[0], v0i = w0i + u[1], v1r = w1r + u[2], v1i = w1i + u[3];
-    const float i0 = 1.0f / (v0r * v0r + v0i * v0i), i1 = 1.0f / (v1r * v1r + v1i * v1i);
+    const float i0 = 1.0f / fmaxf(v0r * v0r + v0i * v0i, kMinV2), i1 = 1.0f / fmaxf(v1r * v1r + v1i * v1i, kMinV2);
     return f4{(s[0] * v0r + s[1] * v0i) * i0, (s[0] * v0i - s[1] * v0r) * i0,
               (s[2] * v1r + s[3] * v1i) * i1, (s[2] * v1i - s[3] * v1r) * i1};
 }
@@ -194,8 +194,8 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     // conj(S./V) 2^sB for the lane's two buses of tile q (rcp: ~1 ulp, far below the FP32 state floor)
     auto inject = [&](const f4 &sv, const f4 &w, const f4 &u, float k) -> f4 {
         const f4 v = w + u;
-        const float r0 = __builtin_amdgcn_rcpf(v[0] * v[0] + v[1] * v[1]) * k;
-        const float r1 = __builtin_amdgcn_rcpf(v[2] * v[2] + v[3] * v[3]) * k;
+        const float r0 = __builtin_amdgcn_rcpf(fmaxf(v[0] * v[0] + v[1] * v[1], kMinV2)) * k;
+        const float r1 = __builtin_amdgcn_rcpf(fmaxf(v[2] * v[2] + v[3] * v[3], kMinV2)) * k;
         return f4{(sv[0] * v[0] + sv[1] * v[1]) * r0, (sv[0] * v[1] - sv[1] * v[0]) * r0,
                   (sv[2] * v[2] + sv[3] * v[3]) * r1, (sv[2] * v[3] - sv[3] * v[2]) * r1};
     };

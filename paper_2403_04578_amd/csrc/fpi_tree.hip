@@ -22,6 +22,15 @@
 
 namespace tpf {
 
+// Orders the LDS accesses of a wavefront's lanes around a point where they exchange values:
+// the wave barrier is only a convergence and scheduling point, so wavefront-scope release and
+// acquire fences on either side make the cross-lane reads see the writes before it.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 namespace {
 
 constexpr int kTreeWaves = 4;
@@ -110,7 +119,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
                 J[2 * p + 1] = ii;
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         // backward pass, deepest level first: J_b += J of b's children
         for (int L = levels; L >= 1; --L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
@@ -122,7 +131,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
                 J[2 * p] = jr;
                 J[2 * p + 1] = ji;
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         // forward pass, level 1 first: D_b = D_parent + z_b J_b (in place of J_b)
         for (int L = 1; L <= levels; ++L) {
@@ -132,7 +141,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
                 J[2 * p] = J[2 * par] + zr * jr - zi * ji;
                 J[2 * p + 1] = J[2 * par + 1] + zr * ji + zi * jr;
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         // V' = w + Z I = w - D; step max |V' - V| per column
         double dmax = 0.0;
@@ -174,7 +183,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
             c += nslots;
             load();
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
     }
 }
 
@@ -267,7 +276,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
             const int p = 1 + sl + LPC * r;
             if (p <= n) {
                 const float vr = tz[4 * p + 2] + ur[r], vi = tz[4 * p + 3] + ui[r];
-                const float inv = 1.0f / (vr * vr + vi * vi);
+                const float inv = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
                 float ir = (sr[r] * vr + si[r] * vi) * inv, ii = (sr[r] * vi - si[r] * vr) * inv;
                 if constexpr (ZIP) {
                     const float ap = za[2 * p], ai = za[2 * p + 1];
@@ -278,7 +287,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
                 J[2 * p + 1] = ii;
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         for (int L = levels; L >= 1; --L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
                 float jr = J[2 * p], ji = J[2 * p + 1];
@@ -289,7 +298,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
                 J[2 * p] = jr;
                 J[2 * p + 1] = ji;
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         for (int L = 1; L <= levels; ++L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
@@ -298,7 +307,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
                 J[2 * p] = J[2 * par] + zr * jr - zi * ji;
                 J[2 * p + 1] = J[2 * par + 1] + zr * ji + zi * jr;
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         float dmax = 0.0f;
         int bad = 0;
@@ -339,7 +348,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
             c += nslots;
             load();
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
     }
 }
 
@@ -471,7 +480,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_kernel(
                 }
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         for (int L = levels; L >= 1; --L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
                 double j[6];
@@ -484,7 +493,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_kernel(
 #pragma unroll
                 for (int e = 0; e < 6; ++e) J[6 * p + e] = j[e];
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         for (int L = 1; L <= levels; ++L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
@@ -504,7 +513,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_kernel(
 #pragma unroll
                 for (int e = 0; e < 6; ++e) J[6 * p + e] = d[e];
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         double dmax = 0.0;
         int bad = 0;
@@ -552,7 +561,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_kernel(
             c += nslots;
             load();
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
     }
 }
 
@@ -643,13 +652,13 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_32_kernel(
 #pragma unroll
                 for (int f = 0; f < 3; ++f) {
                     const float vr = tz[TZ * p + 18 + 2 * f] + ur[r][f], vi = tz[TZ * p + 19 + 2 * f] + ui[r][f];
-                    const float inv = 1.0f / (vr * vr + vi * vi);
+                    const float inv = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
                     J[6 * p + 2 * f] = (sr[r][f] * vr + si[r][f] * vi) * inv;
                     J[6 * p + 2 * f + 1] = (sr[r][f] * vi - si[r][f] * vr) * inv;
                 }
             }
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
         for (int L = levels; L >= 1; --L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
                 float j[6];
@@ -662,7 +671,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_32_kernel(
 #pragma unroll
                 for (int e = 0; e < 6; ++e) J[6 * p + e] = j[e];
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         for (int L = 1; L <= levels; ++L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
@@ -682,7 +691,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_32_kernel(
 #pragma unroll
                 for (int e = 0; e < 6; ++e) J[6 * p + e] = d[e];
             }
-            __builtin_amdgcn_wave_barrier();
+            wave_sync();
         }
         float dmax = 0.0f;
         int bad = 0;
@@ -729,7 +738,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree3_32_kernel(
             c += nslots;
             load();
         }
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
     }
 }
 
@@ -791,7 +800,10 @@ int launch3_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int
     return TPF_OK;
 }
 
-// Three-phase: 2 columns per wavefront up to 128 buses, then 1, up to 512 buses.
+// Three-phase FP64: 2 columns per wavefront up to 128 buses, then 1, as far as the LDS holds
+// the per-position state (3x3 blocks, w and the per-column drops: 400 bytes per position
+// with 4 wavefronts, so up to 408 buses); larger networks return TPF_ERR_UNSUPPORTED from
+// the launch (the FP32 form reaches 512).
 template <typename IO>
 int launch3_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
                const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {

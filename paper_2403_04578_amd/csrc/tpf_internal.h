@@ -25,6 +25,11 @@ inline void rows_config(int MT, int &NW, int &TPW) {
     NW = MT <= 4 ? 4 : 8;
     TPW = (MT + NW - 1) / NW;
 }
+// Floor of |V|^2 in the FP32 injections conj(S) V / |V|^2: an iterate passing through
+// V = 0 (an infeasible load's orbit can) then gives a large finite injection,
+// |I| <= |S| 1e15, instead of inf, so a column with finite inputs stays finite and ends
+// MAX_ITER, never NONFINITE.  Every feasible iterate has |V|^2 far above it.
+constexpr float kMinV2 = 1e-30f;
 // The FP64 fragment array carries this many zero k-steps past the end so that the
 // k-loop's prefetch ring never needs a bounds branch.
 constexpr int kFragPadSteps = 4;

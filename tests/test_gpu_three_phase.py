@@ -146,3 +146,28 @@ def test_three_phase_tree_wide_feeders(gpu, n_bus):
     assert int(st.max()) == tpf.ST_CONVERGED
     ref = oracle.fpi(onet, S, 1e-10, 200)
     assert np.abs(V.cpu().numpy() - ref.V).max() <= 1e-6
+
+
+def test_three_phase_tree_fp64_lds_limit(gpu):
+    """The FP64 three-phase tree kernel keeps 400 bytes of state per bus in LDS: 408 PQ buses
+    run, 409 return TPF_ERR_UNSUPPORTED, where the FP32 form (240 bytes per bus) still runs."""
+    S_by_size = {}
+    for n_bus in (409, 410):
+        f = W.make_feeder_3ph(n_bus)
+        net = tpf.Network.from_feeder_3ph(f)
+        S = _dev(W.profile_minute_year(f, steps=20, t0=99), gpu)
+        S_by_size[n_bus] = (f, net, S)
+    f, net, S = S_by_size[409]
+    V64, it64, st64 = tpf.solve_timeseries(net, S, tol=1e-9, max_iter=100, mode="tree_fp64")
+    V32, it32, st32 = tpf.solve_timeseries(net, S, tol=1e-6, max_iter=100, mode="tree_fp32")
+    assert int(st64.max()) == tpf.ST_CONVERGED and int(st32.max()) == tpf.ST_CONVERGED
+    assert float((V64 - V32).abs().max()) < 1e-6
+    f, net, S = S_by_size[410]
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.solve_timeseries(net, S, tol=1e-9, max_iter=100, mode="tree_fp64")
+    assert e.value.code == tpf.TPF_ERR_UNSUPPORTED
+    V, it, st = tpf.solve_timeseries(net, S, tol=1e-6, max_iter=100, mode="tree_fp32")
+    onet = oracle.build_feeder_3ph(f)
+    ref = oracle.fpi(onet, S[:4].cpu().numpy(), 1e-10, 200)
+    assert int(st.max()) == tpf.ST_CONVERGED
+    assert np.abs(V[:4].cpu().numpy() - ref.V).max() <= 1e-6
