@@ -317,7 +317,7 @@ def bench_other(args):
 
 
 def bench_scaling(args):
-    """Solve time of the kernels alone against network size (demand nodes 9 .. 1,999 at
+    """Solve time of the kernels alone against network size (demand nodes 9 .. 4,999 at
     500 columns) and against the number of columns (10 .. 525,600 at 499 nodes), FP64,
     mixed FP16 and tree-operator forms, tol 1e-6: the shapes of the paper's size and batch scaling
     figures on synthetic feeders.  Median of 3 timed solves after one warm-up.  Prints
@@ -332,12 +332,14 @@ def bench_scaling(args):
     tol, max_iter = 1e-6, 100
 
     def point(n_bus, tau):
-        f = W.make_feeder(n_bus)
+        # above 2,000 buses the base loading has no solution (the voltage collapses), so
+        # larger feeders carry the 2,000-bus feeder's total load
+        f = W.make_feeder(n_bus, load_scale=min(1.0, 2000.0 / n_bus))
         t0 = time.perf_counter()
         net = tpf.Network.from_feeder(f)
         build_s = time.perf_counter() - t0
         S = torch.from_numpy(W.profile_minute_year(f, steps=tau)).to(dev)
-        rec = {"n_nodes": n_bus - 1, "tau": tau, "build_s": build_s}
+        rec = {"n_nodes": n_bus - 1, "tau": tau, "load_scale": min(1.0, 2000.0 / n_bus), "build_s": build_s}
         for mode in ("fp64", "mixed_fp16", "tree_fp64", "tree_fp32"):
             if mode.startswith("tree") and n_bus - 1 > 1024:  # the tree kernel's limit
                 continue
@@ -363,7 +365,7 @@ def bench_scaling(args):
         print(json.dumps(rec), file=sys.stderr, flush=True)
         return rec
 
-    size_curve = [point(nb, 500) for nb in (10, 31, 100, 200, 300, 500, 1000, 2000)]
+    size_curve = [point(nb, 500) for nb in (10, 31, 100, 200, 300, 500, 1000, 2000, 3000, 5000)]
     tau_curve = [point(500, t) for t in (10, 100, 1_000, 10_000, 100_000, 525_600)]
     print(json.dumps({"metric": "solve time vs network size and batch", "size_curve_tau500": size_curve,
                       "tau_curve_n499": tau_curve}), flush=True)

@@ -84,7 +84,30 @@ __global__ void init_kernel(const IO *__restrict__ V0, const double *__restrict_
     }
 }
 
-// I = conj(S./V), or alpha_P conj(S./V) + alpha_I conj(S) for ZIP loads (aP, aI non-NULL).
+// I = conj(S./V), or alpha_P conj(S./V) + alpha_I conj(S) for ZIP loads (aP, aI non-NULL),
+// at bus b of column c; zero on the K padding (b >= n).
+template <typename T, typename IO>
+__device__ __forceinline__ void injection_at(const IO *__restrict__ S, const T *__restrict__ x,
+                                             const double *__restrict__ w, int n, long long c, int b,
+                                             const double *__restrict__ aP, const double *__restrict__ aI, T &ir,
+                                             T &ii) {
+    ir = 0, ii = 0;
+    if (b >= n) return;
+    const double sr = (double)S[2 * (c * n + b)], si = (double)S[2 * (c * n + b) + 1];
+    double vr = (double)x[2 * (c * n + b)], vi = (double)x[2 * (c * n + b) + 1];
+    if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
+    const double inv = 1.0 / (vr * vr + vi * vi);
+    double jr = (sr * vr + si * vi) * inv, ji = (sr * vi - si * vr) * inv;
+    if (aP) {
+        const double ap = aP[b], ai = aI[b];
+        jr = ap * jr + ai * sr;
+        ji = ap * ji - ai * si;
+    }
+    ir = (T)jr;
+    ii = (T)ji;
+}
+
+// The first sweep's B operand [rows][KP]: row a = injection of column act[a] (zero past na).
 template <typename T, typename IO>
 __global__ void inject_kernel(const IO *__restrict__ S, const T *__restrict__ x, const double *__restrict__ w, int n,
                               int KP, const long long *__restrict__ act, const int *__restrict__ na, int rows,
@@ -96,21 +119,7 @@ __global__ void inject_kernel(const IO *__restrict__ S, const T *__restrict__ x,
         const long long a = e / (KP / 2);
         const int b = (int)(e - a * (KP / 2));
         T ir = 0, ii = 0;
-        if (a < nact && b < n) {
-            const long long c = act[a];
-            const double sr = (double)S[2 * (c * n + b)], si = (double)S[2 * (c * n + b) + 1];
-            double vr = (double)x[2 * (c * n + b)], vi = (double)x[2 * (c * n + b) + 1];
-            if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
-            const double inv = 1.0 / (vr * vr + vi * vi);
-            double jr = (sr * vr + si * vi) * inv, ji = (sr * vi - si * vr) * inv;
-            if (aP) {
-                const double ap = aP[b], ai = aI[b];
-                jr = ap * jr + ai * sr;
-                ji = ap * ji - ai * si;
-            }
-            ir = (T)jr;
-            ii = (T)ji;
-        }
+        if (a < nact) injection_at<T, IO>(S, x, w, n, act[a], b, aP, aI, ir, ii);
         B[a * KP + 2 * b] = ir;
         B[a * KP + 2 * b + 1] = ii;
     }
@@ -120,135 +129,168 @@ __global__ void inject_kernel(const IO *__restrict__ S, const T *__restrict__ x,
 template <typename T>
 __global__ __launch_bounds__(256) void gemm_kernel(const T *__restrict__ A, int KP, const T *__restrict__ B,
                                                    const long long *__restrict__ act, const int *__restrict__ na,
-                                                   const double *__restrict__ w, int n, T *__restrict__ x,
-                                                   unsigned long long *__restrict__ dmax, int *__restrict__ badf) {
+                                                   int row_blocks, const double *__restrict__ w, int n,
+                                                   T *__restrict__ x, unsigned long long *__restrict__ dmax,
+                                                   int *__restrict__ badf) {
     using Ops = Acc<T>;
     typedef typename Ops::v4 v4;
     const int nact = *na;
-    const int c0 = blockIdx.x * 64;
-    if (c0 >= nact) return;
-    const int r0 = blockIdx.y * 64;
+    const int ct = (nact + 63) / 64;
     __shared__ T As[2][64][17];  // two buffers: the next k-slab lands while this one is used
     __shared__ T Bs[2][64][17];
     __shared__ double red[2][64];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    v4 acc[2][2];
-    for (int a = 0; a < 2; ++a)
-        for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
-    const int rr = tid >> 2, kk = (tid & 3) * 4;
-    const T *Ap = A + (size_t)(r0 + rr) * KP + kk, *Bp = B + (size_t)(c0 + rr) * KP + kk;
-    // the next k-slab is fetched into registers while the current one is multiplied
-    T pa0 = Ap[0], pa1 = Ap[1], pa2 = Ap[2], pa3 = Ap[3];
-    T pb0 = Bp[0], pb1 = Bp[1], pb2 = Bp[2], pb3 = Bp[3];
-    As[0][rr][kk] = pa0, As[0][rr][kk + 1] = pa1, As[0][rr][kk + 2] = pa2, As[0][rr][kk + 3] = pa3;
-    Bs[0][rr][kk] = pb0, Bs[0][rr][kk + 1] = pb1, Bs[0][rr][kk + 2] = pb2, Bs[0][rr][kk + 3] = pb3;
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < KP; k0 += 16) {
-        const bool more = k0 + 16 < KP;
-        if (more) {
-            const int o = k0 + 16;
-            pa0 = Ap[o], pa1 = Ap[o + 1], pa2 = Ap[o + 2], pa3 = Ap[o + 3];
-            pb0 = Bp[o], pb1 = Bp[o + 1], pb2 = Bp[o + 2], pb3 = Bp[o + 3];
-        }
-#pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            T af[2], bf[2];
-#pragma unroll
-            for (int a = 0; a < 2; ++a) af[a] = As[buf][wr + 16 * a + j][4 * ks + g];
-#pragma unroll
-            for (int b = 0; b < 2; ++b) bf[b] = Bs[buf][wc + 16 * b + j][4 * ks + g];
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = Ops::mma(af[a], bf[b], acc[a][b]);
-        }
-        if (more) {  // the other buffer: its last readers passed the previous barrier
-            T *as = &As[buf ^ 1][rr][kk], *bs = &Bs[buf ^ 1][rr][kk];
-            as[0] = pa0, as[1] = pa1, as[2] = pa2, as[3] = pa3;
-            bs[0] = pb0, bs[1] = pb1, bs[2] = pb2, bs[3] = pb3;
-        }
+    // a fixed grid walks the tiles of the active columns (none once every column is done);
+    // column tiles run fastest, so resident blocks share the A row block
+    for (int t = blockIdx.x; t < ct * row_blocks; t += gridDim.x) {
+        const int c0 = (t % ct) * 64, r0 = (t / ct) * 64;
+        v4 acc[2][2];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
+        const int rr = tid >> 2, kk = (tid & 3) * 4;
+        const T *Ap = A + (size_t)(r0 + rr) * KP + kk, *Bp = B + (size_t)(c0 + rr) * KP + kk;
+        // the next k-slab is fetched into registers while the current one is multiplied
+        T pa0 = Ap[0], pa1 = Ap[1], pa2 = Ap[2], pa3 = Ap[3];
+        T pb0 = Bp[0], pb1 = Bp[1], pb2 = Bp[2], pb3 = Bp[3];
+        As[0][rr][kk] = pa0, As[0][rr][kk + 1] = pa1, As[0][rr][kk + 2] = pa2, As[0][rr][kk + 3] = pa3;
+        Bs[0][rr][kk] = pb0, Bs[0][rr][kk + 1] = pb1, Bs[0][rr][kk + 2] = pb2, Bs[0][rr][kk + 3] = pb3;
         __syncthreads();
-        buf ^= 1;
-    }
-    // epilogue: each lane holds both parts of two buses (FP64 layout) or of two buses
-    // (FP32 interleaved layout: rows 4g..4g+3 = Re/Im of two buses) of column j
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const int ac = c0 + wc + 16 * b + j;
-        double emax = 0.0;
-        int bad = 0;
-        const bool live = ac < nact;
-        const long long c = live ? act[ac] : 0;
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-            const int tile0 = r0 + wr + 16 * a;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                // the two registers holding Re and Im of one bus
-                const int rre = sizeof(T) == 8 ? h : 2 * h, rim = sizeof(T) == 8 ? h + 2 : 2 * h + 1;
-                int bus, part;
-                row_bus<T>(tile0 + Ops::row(g, rre), bus, part);
-                if (live && bus < n) {
-                    const double nr = (double)acc[a][b][rre] + (sizeof(T) == 8 ? w[2 * bus] : 0.0);
-                    const double ni = (double)acc[a][b][rim] + (sizeof(T) == 8 ? w[2 * bus + 1] : 0.0);
-                    T *xp = x + 2 * (c * n + bus);
-                    const double dr = nr - (double)xp[0], di = ni - (double)xp[1];
-                    const double e2 = dr * dr + di * di;
-                    bad |= !(e2 < HUGE_VAL);
-                    emax = e2 > emax ? e2 : emax;
-                    xp[0] = (T)nr;
-                    xp[1] = (T)ni;
+        int buf = 0;
+        for (int k0 = 0; k0 < KP; k0 += 16) {
+            const bool more = k0 + 16 < KP;
+            if (more) {
+                const int o = k0 + 16;
+                pa0 = Ap[o], pa1 = Ap[o + 1], pa2 = Ap[o + 2], pa3 = Ap[o + 3];
+                pb0 = Bp[o], pb1 = Bp[o + 1], pb2 = Bp[o + 2], pb3 = Bp[o + 3];
+            }
+    #pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                T af[2], bf[2];
+    #pragma unroll
+                for (int a = 0; a < 2; ++a) af[a] = As[buf][wr + 16 * a + j][4 * ks + g];
+    #pragma unroll
+                for (int b = 0; b < 2; ++b) bf[b] = Bs[buf][wc + 16 * b + j][4 * ks + g];
+    #pragma unroll
+                for (int a = 0; a < 2; ++a)
+    #pragma unroll
+                    for (int b = 0; b < 2; ++b) acc[a][b] = Ops::mma(af[a], bf[b], acc[a][b]);
+            }
+            if (more) {  // the other buffer: its last readers passed the previous barrier
+                T *as = &As[buf ^ 1][rr][kk], *bs = &Bs[buf ^ 1][rr][kk];
+                as[0] = pa0, as[1] = pa1, as[2] = pa2, as[3] = pa3;
+                bs[0] = pb0, bs[1] = pb1, bs[2] = pb2, bs[3] = pb3;
+            }
+            __syncthreads();
+            buf ^= 1;
+        }
+        // epilogue: each lane holds both parts of two buses (FP64 layout) or of two buses
+        // (FP32 interleaved layout: rows 4g..4g+3 = Re/Im of two buses) of column j
+    #pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const int ac = c0 + wc + 16 * b + j;
+            double emax = 0.0;
+            int bad = 0;
+            const bool live = ac < nact;
+            const long long c = live ? act[ac] : 0;
+    #pragma unroll
+            for (int a = 0; a < 2; ++a) {
+                const int tile0 = r0 + wr + 16 * a;
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    // the two registers holding Re and Im of one bus
+                    const int rre = sizeof(T) == 8 ? h : 2 * h, rim = sizeof(T) == 8 ? h + 2 : 2 * h + 1;
+                    int bus, part;
+                    row_bus<T>(tile0 + Ops::row(g, rre), bus, part);
+                    if (live && bus < n) {
+                        const double nr = (double)acc[a][b][rre] + (sizeof(T) == 8 ? w[2 * bus] : 0.0);
+                        const double ni = (double)acc[a][b][rim] + (sizeof(T) == 8 ? w[2 * bus + 1] : 0.0);
+                        T *xp = x + 2 * (c * n + bus);
+                        const double dr = nr - (double)xp[0], di = ni - (double)xp[1];
+                        const double e2 = dr * dr + di * di;
+                        bad |= !(e2 < HUGE_VAL);
+                        emax = e2 > emax ? e2 : emax;
+                        xp[0] = (T)nr;
+                        xp[1] = (T)ni;
+                    }
                 }
             }
+            emax = fmax(emax, __shfl_xor(emax, 16));
+            emax = fmax(emax, __shfl_xor(emax, 32));
+            bad |= __shfl_xor(bad, 16);
+            bad |= __shfl_xor(bad, 32);
+            if (g == 0) {
+                red[wave >> 1][wc + 16 * b + j] = emax;
+                if (live && bad) atomicOr(badf + c, 1);
+            }
         }
-        emax = fmax(emax, __shfl_xor(emax, 16));
-        emax = fmax(emax, __shfl_xor(emax, 32));
-        bad |= __shfl_xor(bad, 16);
-        bad |= __shfl_xor(bad, 32);
-        if (g == 0) {
-            red[wave >> 1][wc + 16 * b + j] = emax;
-            if (live && bad) atomicOr(badf + c, 1);
+        __syncthreads();
+        if (tid < 64 && c0 + tid < nact) {  // non-negative doubles order like their bit patterns
+            const double e = fmax(red[0][tid], red[1][tid]);
+            atomicMax(dmax + act[c0 + tid], (unsigned long long)__double_as_longlong(e));
         }
-    }
-    __syncthreads();
-    if (tid < 64 && c0 + tid < nact) {  // non-negative doubles order like their bit patterns
-        const double e = fmax(red[0][tid], red[1][tid]);
-        atomicMax(dmax + act[c0 + tid], (unsigned long long)__double_as_longlong(e));
     }
 }
 
+// Tells the host that queues the sweeps that none is left to do (a store to pinned host
+// memory, visible to the host without any wait on the device).
+__device__ __forceinline__ void post_done(int *done_flag, int seq) {
+    if (done_flag) __hip_atomic_store(done_flag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+// One wave per active column: convergence test (Eq. (3)), retirement, and for a column
+// that stays active its place in the next list and its injection there (the next
+// sweep's B row).  `cnt_next` was cleared a sweep earlier; `cnt_clear` (the count two
+// sweeps back, read by no kernel still to run) is cleared for the sweep after next.
 template <typename T, typename IO>
-__global__ void finish_kernel(const long long *__restrict__ act, const int *__restrict__ na, const T *__restrict__ x,
-                              const double *__restrict__ w, int n, double tol, int max_iter,
-                              unsigned long long *__restrict__ dmax, int *__restrict__ badf, int32_t *iters,
-                              int8_t *status, IO *__restrict__ V, long long *__restrict__ act_next, int *na_next) {
-    const long long a = blockIdx.x * 4LL + (threadIdx.x >> 6);
+__global__ void finish_kernel(const long long *__restrict__ act, const int *__restrict__ cnt, int *cnt_clear,
+                              const IO *__restrict__ S, const T *__restrict__ x, const double *__restrict__ w, int n,
+                              int KP, const double *__restrict__ aP, const double *__restrict__ aI, double tol,
+                              int max_iter, unsigned long long *__restrict__ dmax, const int *__restrict__ badf,
+                              int32_t *iters, int8_t *status, IO *__restrict__ V, long long *__restrict__ act_next,
+                              int *cnt_next, T *__restrict__ B, int *done_flag, int seq) {
     const int lane = threadIdx.x & 63;
-    if (a >= *na) return;
-    const long long c = act[a];
-    const double e = __longlong_as_double((long long)dmax[c]);
-    const int bad = badf[c];
-    const int it = iters[c] + 1;
-    const bool conv = !bad && sqrt(e) < tol;
-    const bool done = bad || conv || it >= max_iter;
-    if (done) {
-        for (int b = lane; b < n; b += 64) {
-            double vr = (double)x[2 * (c * n + b)], vi = (double)x[2 * (c * n + b) + 1];
-            if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
-            V[2 * (c * n + b)] = (IO)vr;
-            V[2 * (c * n + b) + 1] = (IO)vi;
-        }
+    const int nact = *cnt;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *cnt_clear = 0;
+        if (nact == 0) post_done(done_flag, seq);
     }
-    if (lane == 0) {
-        iters[c] = it;
-        dmax[c] = 0ull;
+    for (long long a = blockIdx.x * 4LL + (threadIdx.x >> 6); a < nact; a += gridDim.x * 4LL) {
+        const long long c = act[a];
+        const double e = __longlong_as_double((long long)dmax[c]);
+        const int bad = badf[c];
+        const int it = iters[c] + 1;
+        const bool conv = !bad && sqrt(e) < tol;
+        const bool done = bad || conv || it >= max_iter;
         if (done) {
-            status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
-        } else {
-            act_next[atomicAdd(na_next, 1)] = c;
+            for (int b = lane; b < n; b += 64) {
+                double vr = (double)x[2 * (c * n + b)], vi = (double)x[2 * (c * n + b) + 1];
+                if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
+                V[2 * (c * n + b)] = (IO)vr;
+                V[2 * (c * n + b) + 1] = (IO)vi;
+            }
+        }
+        int slot = 0;
+        if (lane == 0) {
+            iters[c] = it;
+            dmax[c] = 0ull;
+            if (done) {
+                status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            } else {
+                slot = atomicAdd(cnt_next, 1);
+                act_next[slot] = c;
+            }
+        }
+        if (!done) {  // wave-uniform
+            slot = __shfl(slot, 0);
+            T *Br = B + (long long)slot * KP;
+            for (int b = lane; b < KP / 2; b += 64) {
+                T ir, ii;
+                injection_at<T, IO>(S, x, w, n, c, b, aP, aI, ir, ii);
+                Br[2 * b] = ir;
+                Br[2 * b + 1] = ii;
+            }
         }
     }
 }
@@ -354,34 +396,32 @@ __device__ __forceinline__ float2 zip_injection(float ir, float ii, float sr, fl
     return make_float2(ap * ir + ai * sr, ap * ii - ai * si);
 }
 
-// I = conj(S./V) in FP32 for the refine list: B32 [rows][KP] and I_prev.
+// FP32 injection of column c at bus b (o = 2 (c n + b)) from U = V - w.
 template <typename IO>
-__global__ void inject_refine_kernel(const IO *__restrict__ S, const float *__restrict__ U,
-                                     const double *__restrict__ w, float *__restrict__ Ip, int n, int KP,
-                                     const long long *__restrict__ act, const int *__restrict__ na, int rows,
-                                     const double *__restrict__ aP, const double *__restrict__ aI,
-                                     float *__restrict__ B) {
-    const int nact = *na;
-    const int half = KP / 2;
-    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)rows * half;
-         e += (long long)gridDim.x * blockDim.x) {
-        const long long a = e / half;
-        const int b = (int)(e - a * half);
-        float2 out = make_float2(0.f, 0.f);
-        if (a < nact && b < n) {
-            const long long c = act[a], o = 2 * (c * n + b);
-            const float sr = (float)S[o], si = (float)S[o + 1];
-            const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
-            const float r = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
-            out = zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, aP, aI, b);
-            *reinterpret_cast<float2 *>(Ip + o) = out;
-        }
-        *reinterpret_cast<float2 *>(B + a * KP + 2 * b) = out;
-    }
+__device__ __forceinline__ float2 injection32(const IO *__restrict__ S, const float *__restrict__ U,
+                                              const double *__restrict__ w, long long o, int b,
+                                              const double *__restrict__ aP, const double *__restrict__ aI) {
+    const float sr = (float)S[o], si = (float)S[o + 1];
+    const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
+    const float r = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
+    return zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, aP, aI, b);
 }
 
-// Low list: B16 [rows][KP16] holds (I 2^sB) for full sweeps, ((I - I_prev) 2^sB) for
-// difference sweeps; I_prev <- I.
+// 16-bit B entry of a low-list column: I 2^sB on a full sweep (ph = 0), (I - I_prev) 2^sB
+// on a difference sweep; I_prev <- I.
+template <int MODE>
+__device__ __forceinline__ uint32_t low_entry(float2 iz, float2 *ip, int ph, float ks) {
+    float br = iz.x, bi = iz.y;
+    if (ph) {
+        const float2 p = *ip;
+        br -= p.x;
+        bi -= p.y;
+    }
+    *ip = iz;
+    return Low16<MODE>::enc2(br * ks, bi * ks);
+}
+
+// The first sweep's B16 [rows][KP16] for the low list act[0..na).
 template <int MODE, typename IO>
 __global__ void inject_low_kernel(const IO *__restrict__ S, const float *__restrict__ U,
                                   const double *__restrict__ w, float *__restrict__ Ip,
@@ -398,22 +438,8 @@ __global__ void inject_low_kernel(const IO *__restrict__ S, const float *__restr
         uint32_t out = 0u;
         if (a < nact && b < n) {
             const long long c = act[a], o = 2 * (c * n + b);
-            const int ph = ms[c].ph;
-            const float ks = ms[c].ks;
-            const float sr = (float)S[o], si = (float)S[o + 1];
-            const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
-            const float r = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
-            const float2 iz = zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, aP, aI, b);
-            const float ir = iz.x, ii = iz.y;
-            float br = ir, bi = ii;
-            float2 *ip = reinterpret_cast<float2 *>(Ip + o);
-            if (ph) {
-                const float2 p = *ip;
-                br -= p.x;
-                bi -= p.y;
-            }
-            *ip = make_float2(ir, ii);
-            out = Low16<MODE>::enc2(br * ks, bi * ks);
+            out = low_entry<MODE>(injection32(S, U, w, o, b, aP, aI), reinterpret_cast<float2 *>(Ip + o), ms[c].ph,
+                                  ms[c].ks);
         }
         B[a * half + b] = out;
     }
@@ -427,175 +453,226 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
                                                        const long long *__restrict__ act, const int *__restrict__ na,
                                                        const MixState *__restrict__ ms, int n, float *__restrict__ U,
                                                        unsigned long long *__restrict__ dmax,
-                                                       unsigned *__restrict__ umax, int *__restrict__ badf) {
+                                                       unsigned *__restrict__ umax, int *__restrict__ badf,
+                                                       int row_blocks) {
     const int nact = *na;
-    const int c0 = blockIdx.x * 128;
-    if (c0 >= nact) return;
-    const int r0 = blockIdx.y * 128;
+    const int ct = (nact + 127) / 128;
     __shared__ uint4 As[2][128][5];  // 32 K values per row + one pad quad against bank conflicts;
     __shared__ uint4 Bs[2][128][5];  // two buffers: the next k-slab lands while this one is used
     __shared__ float redd[2][128], redu[2][128];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    f4x acc[4][4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = f4x{0.f, 0.f, 0.f, 0.f};
-    // thread tid moves quads (row tid / 4, q) and (row 64 + tid / 4, q) of both operands
-    const int lrow = tid >> 2, lq = tid & 3;
-    const uint4 *Ap = reinterpret_cast<const uint4 *>(A + (size_t)(r0 + lrow) * KP16 + 8 * lq);
-    const uint4 *Bp = reinterpret_cast<const uint4 *>(B + (size_t)(c0 + lrow) * KP16 + 8 * lq);
-    const size_t half = (size_t)64 * KP16 / 8;  // 64 rows further, in quads
-    // the next k-slab is fetched into registers while the current one is multiplied
-    uint4 pa0 = Ap[0], pa1 = Ap[half], pb0 = Bp[0], pb1 = Bp[half];
-    As[0][lrow][lq] = pa0;
-    As[0][64 + lrow][lq] = pa1;
-    Bs[0][lrow][lq] = pb0;
-    Bs[0][64 + lrow][lq] = pb1;
-    __syncthreads();
-    int buf = 0;
-    for (int k0 = 0; k0 < KP16; k0 += 32) {
-        const bool more = k0 + 32 < KP16;
-        if (more) {
-            const int o = (k0 + 32) / 8;
-            pa0 = Ap[o];
-            pa1 = Ap[half + o];
-            pb0 = Bp[o];
-            pb1 = Bp[half + o];
-        }
-        uint4 af[4], bf[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) af[a] = As[buf][wr + 16 * a + j][g];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) bf[b] = Bs[buf][wc + 16 * b + j][g];
-#pragma unroll
+    // a fixed grid walks the tiles of the active columns, column tiles fastest
+    for (int t = blockIdx.x; t < ct * row_blocks; t += gridDim.x) {
+        const int c0 = (t % ct) * 128, r0 = (t / ct) * 128;
+        f4x acc[4][4];
+    #pragma unroll
         for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = Low16<MODE>::mma(af[a], bf[b], acc[a][b]);
-        if (more) {  // the other buffer: its last readers passed the previous barrier
-            As[buf ^ 1][lrow][lq] = pa0;
-            As[buf ^ 1][64 + lrow][lq] = pa1;
-            Bs[buf ^ 1][lrow][lq] = pb0;
-            Bs[buf ^ 1][64 + lrow][lq] = pb1;
-        }
+    #pragma unroll
+            for (int b = 0; b < 4; ++b) acc[a][b] = f4x{0.f, 0.f, 0.f, 0.f};
+        // thread tid moves quads (row tid / 4, q) and (row 64 + tid / 4, q) of both operands
+        const int lrow = tid >> 2, lq = tid & 3;
+        const uint4 *Ap = reinterpret_cast<const uint4 *>(A + (size_t)(r0 + lrow) * KP16 + 8 * lq);
+        const uint4 *Bp = reinterpret_cast<const uint4 *>(B + (size_t)(c0 + lrow) * KP16 + 8 * lq);
+        const size_t half = (size_t)64 * KP16 / 8;  // 64 rows further, in quads
+        // the next k-slab is fetched into registers while the current one is multiplied
+        uint4 pa0 = Ap[0], pa1 = Ap[half], pb0 = Bp[0], pb1 = Bp[half];
+        As[0][lrow][lq] = pa0;
+        As[0][64 + lrow][lq] = pa1;
+        Bs[0][lrow][lq] = pb0;
+        Bs[0][64 + lrow][lq] = pb1;
         __syncthreads();
-        buf ^= 1;
-    }
-    // lane group g holds rows 4g..4g+3 of each 16-row tile: Re/Im of two buses
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const int ac = c0 + wc + 16 * b + j;
-        const bool live = ac < nact;
-        const long long c = live ? act[ac] : 0;
-        int ph = 0;
-        float inv = 1.f;
-        if (live) {
-            ph = ms[c].ph;
-            inv = ms[c].inv;
+        int buf = 0;
+        for (int k0 = 0; k0 < KP16; k0 += 32) {
+            const bool more = k0 + 32 < KP16;
+            if (more) {
+                const int o = (k0 + 32) / 8;
+                pa0 = Ap[o];
+                pa1 = Ap[half + o];
+                pb0 = Bp[o];
+                pb1 = Bp[half + o];
+            }
+            uint4 af[4], bf[4];
+    #pragma unroll
+            for (int a = 0; a < 4; ++a) af[a] = As[buf][wr + 16 * a + j][g];
+    #pragma unroll
+            for (int b = 0; b < 4; ++b) bf[b] = Bs[buf][wc + 16 * b + j][g];
+    #pragma unroll
+            for (int a = 0; a < 4; ++a)
+    #pragma unroll
+                for (int b = 0; b < 4; ++b) acc[a][b] = Low16<MODE>::mma(af[a], bf[b], acc[a][b]);
+            if (more) {  // the other buffer: its last readers passed the previous barrier
+                As[buf ^ 1][lrow][lq] = pa0;
+                As[buf ^ 1][64 + lrow][lq] = pa1;
+                Bs[buf ^ 1][lrow][lq] = pb0;
+                Bs[buf ^ 1][64 + lrow][lq] = pb1;
+            }
+            __syncthreads();
+            buf ^= 1;
         }
-        float emax = 0.f, umx = 0.f;
-        int bad = 0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int bus = (r0 + wr + 16 * a + 4 * g + 2 * h) >> 1;
-                if (live && bus < n) {
-                    float2 *up = reinterpret_cast<float2 *>(U + 2 * (c * n + bus));
-                    const float2 old = *up;
-                    const float pr = acc[a][b][2 * h] * inv, pi = acc[a][b][2 * h + 1] * inv;
-                    const float nr = ph ? old.x + pr : pr, ni = ph ? old.y + pi : pi;
-                    const float dr = nr - old.x, di = ni - old.y;
-                    const float e2 = dr * dr + di * di;
-                    bad |= !(e2 < HUGE_VALF);
-                    emax = e2 > emax ? e2 : emax;
-                    umx = fmaxf(umx, fmaxf(fabsf(nr), fabsf(ni)));
-                    *up = make_float2(nr, ni);
+        // lane group g holds rows 4g..4g+3 of each 16-row tile: Re/Im of two buses
+    #pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int ac = c0 + wc + 16 * b + j;
+            const bool live = ac < nact;
+            const long long c = live ? act[ac] : 0;
+            int ph = 0;
+            float inv = 1.f;
+            if (live) {
+                ph = ms[c].ph;
+                inv = ms[c].inv;
+            }
+            float emax = 0.f, umx = 0.f;
+            int bad = 0;
+    #pragma unroll
+            for (int a = 0; a < 4; ++a) {
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int bus = (r0 + wr + 16 * a + 4 * g + 2 * h) >> 1;
+                    if (live && bus < n) {
+                        float2 *up = reinterpret_cast<float2 *>(U + 2 * (c * n + bus));
+                        const float2 old = *up;
+                        const float pr = acc[a][b][2 * h] * inv, pi = acc[a][b][2 * h + 1] * inv;
+                        const float nr = ph ? old.x + pr : pr, ni = ph ? old.y + pi : pi;
+                        const float dr = nr - old.x, di = ni - old.y;
+                        const float e2 = dr * dr + di * di;
+                        bad |= !(e2 < HUGE_VALF);
+                        emax = e2 > emax ? e2 : emax;
+                        umx = fmaxf(umx, fmaxf(fabsf(nr), fabsf(ni)));
+                        *up = make_float2(nr, ni);
+                    }
                 }
             }
+            emax = fmaxf(emax, __shfl_xor(emax, 16));
+            emax = fmaxf(emax, __shfl_xor(emax, 32));
+            umx = fmaxf(umx, __shfl_xor(umx, 16));
+            umx = fmaxf(umx, __shfl_xor(umx, 32));
+            bad |= __shfl_xor(bad, 16);
+            bad |= __shfl_xor(bad, 32);
+            if (g == 0) {
+                redd[wave >> 1][wc + 16 * b + j] = emax;
+                redu[wave >> 1][wc + 16 * b + j] = umx;
+                if (live && bad) atomicOr(badf + c, 1);
+            }
         }
-        emax = fmaxf(emax, __shfl_xor(emax, 16));
-        emax = fmaxf(emax, __shfl_xor(emax, 32));
-        umx = fmaxf(umx, __shfl_xor(umx, 16));
-        umx = fmaxf(umx, __shfl_xor(umx, 32));
-        bad |= __shfl_xor(bad, 16);
-        bad |= __shfl_xor(bad, 32);
-        if (g == 0) {
-            redd[wave >> 1][wc + 16 * b + j] = emax;
-            redu[wave >> 1][wc + 16 * b + j] = umx;
-            if (live && bad) atomicOr(badf + c, 1);
+        __syncthreads();
+        if (tid < 128 && c0 + tid < nact) {  // non-negative values order like their bit patterns
+            const long long c = act[c0 + tid];
+            const double e = (double)fmaxf(redd[0][tid], redd[1][tid]);
+            atomicMax(dmax + c, (unsigned long long)__double_as_longlong(e));
+            atomicMax(umax + c, __float_as_uint(fmaxf(redu[0][tid], redu[1][tid])));
         }
-    }
-    __syncthreads();
-    if (tid < 128 && c0 + tid < nact) {  // non-negative values order like their bit patterns
-        const long long c = act[c0 + tid];
-        const double e = (double)fmaxf(redd[0][tid], redd[1][tid]);
-        atomicMax(dmax + c, (unsigned long long)__double_as_longlong(e));
-        atomicMax(umax + c, __float_as_uint(fmaxf(redu[0][tid], redu[1][tid])));
     }
 }
 
 // One wave per column of the refine list (first) and the low list: schedule update,
-// retirement, and the next sweep's lists.
+// retirement, and for a column that stays active its place in the next refine or low
+// list with its injection there (B32 row: I; B16 row: as low_entry), I_prev <- I.
+// cnt = {low, refine} counts of this sweep; cnt_next was cleared a sweep earlier;
+// cnt_clear (the pair two sweeps back) is cleared for the sweep after next.
 template <int MODE, typename IO>
 __global__ void finish_mixed_kernel(const long long *__restrict__ actR, const long long *__restrict__ actL,
-                                    const int *__restrict__ cnt, const float *__restrict__ U,
-                                    const double *__restrict__ w, int n, float tol, int max_iter,
-                                    unsigned long long *__restrict__ dmax, unsigned *__restrict__ umax,
-                                    const int *__restrict__ badf, MixState *__restrict__ ms, int32_t *iters,
-                                    int8_t *status, IO *__restrict__ V, long long *__restrict__ nextR,
-                                    long long *__restrict__ nextL, int *cnt_next) {
-    const long long a = blockIdx.x * 4LL + (threadIdx.x >> 6);
+                                    const int *__restrict__ cnt, int *cnt_clear, const IO *__restrict__ S,
+                                    const float *__restrict__ U, const double *__restrict__ w, int n, int KP,
+                                    int KP16, const double *__restrict__ aP, const double *__restrict__ aI,
+                                    float tol, int max_iter, unsigned long long *__restrict__ dmax,
+                                    unsigned *__restrict__ umax, const int *__restrict__ badf,
+                                    MixState *__restrict__ ms, int32_t *iters, int8_t *status, IO *__restrict__ V,
+                                    float *__restrict__ Ip, long long *__restrict__ nextR,
+                                    long long *__restrict__ nextL, int *cnt_next, float *__restrict__ B32,
+                                    uint32_t *__restrict__ B16, int *done_flag, int seq) {
     const int lane = threadIdx.x & 63;
     const int nl = cnt[0], nr = cnt[1];
-    if (a >= (long long)nr + nl) return;
-    const bool refine = a < nr;
-    const long long c = refine ? actR[a] : actL[a - nr];
-    MixState m = ms[c];
-    const float d = (float)sqrt(__longlong_as_double((long long)dmax[c]));
-    const float um = __uint_as_float(umax[c]);
-    const int bad = badf[c];
+    if (blockIdx.x == 0 && threadIdx.x < 2) cnt_clear[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nl + nr == 0) post_done(done_flag, seq);
     constexpr float u = Low16<MODE>::u;
     const float theta = 4.0f * u, refresh = 6.7e-8f / u, margin = 1.0f + 8.0f * u;
-    m.it += 1;
-    bool conv = false;
-    if (refine) {
-        conv = d < tol;
-        m.ph = 1;
-        m.want = 0;
-        m.sumd = 0.f;
-    } else if (m.ph == 0) {
-        m.uref = fmaxf(m.uref, um);
-        if (!m.want && (d <= theta * m.uref || (m.it >= 2 && d > 0.5f * m.dprev))) m.want = 1;
-    } else {
-        conv = d * margin < tol;
-        m.sumd += d;
-        if (!m.want && m.sumd > refresh) m.want = 1;
-    }
-    m.dprev = d;
-    const bool done = bad || conv || m.it >= max_iter;
-    if (done)
-        for (int b = lane; b < n; b += 64) {
-            V[2 * (c * n + b)] = (IO)(w[2 * b] + (double)U[2 * (c * n + b)]);
-            V[2 * (c * n + b) + 1] = (IO)(w[2 * b + 1] + (double)U[2 * (c * n + b) + 1]);
+    for (long long a = blockIdx.x * 4LL + (threadIdx.x >> 6); a < (long long)nr + nl; a += gridDim.x * 4LL) {
+        const bool refine = a < nr;
+        const long long c = refine ? actR[a] : actL[a - nr];
+        MixState m = ms[c];
+        const float d = (float)sqrt(__longlong_as_double((long long)dmax[c]));
+        const float um = __uint_as_float(umax[c]);
+        const int bad = badf[c];
+        m.it += 1;
+        bool conv = false;
+        if (refine) {
+            conv = d < tol;
+            m.ph = 1;
+            m.want = 0;
+            m.sumd = 0.f;
+        } else if (m.ph == 0) {
+            m.uref = fmaxf(m.uref, um);
+            if (!m.want && (d <= theta * m.uref || (m.it >= 2 && d > 0.5f * m.dprev))) m.want = 1;
+        } else {
+            conv = d * margin < tol;
+            m.sumd += d;
+            if (!m.want && m.sumd > refresh) m.want = 1;
         }
-    if (lane == 0) {
-        iters[c] = m.it;
-        dmax[c] = 0ull;
-        umax[c] = 0u;
-        ms[c] = m;
+        m.dprev = d;
+        const bool done = bad || conv || m.it >= max_iter;
         if (done)
-            status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
-        else if (m.want)
-            nextR[atomicAdd(cnt_next + 1, 1)] = c;
-        else
-            nextL[atomicAdd(cnt_next, 1)] = c;
+            for (int b = lane; b < n; b += 64) {
+                V[2 * (c * n + b)] = (IO)(w[2 * b] + (double)U[2 * (c * n + b)]);
+                V[2 * (c * n + b) + 1] = (IO)(w[2 * b + 1] + (double)U[2 * (c * n + b) + 1]);
+            }
+        int slot = 0;
+        if (lane == 0) {
+            iters[c] = m.it;
+            dmax[c] = 0ull;
+            umax[c] = 0u;
+            ms[c] = m;
+            if (done) {
+                status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            } else if (m.want) {
+                slot = atomicAdd(cnt_next + 1, 1);
+                nextR[slot] = c;
+            } else {
+                slot = atomicAdd(cnt_next, 1);
+                nextL[slot] = c;
+            }
+        }
+        if (done) continue;  // wave-uniform
+        slot = __shfl(slot, 0);
+        if (m.want) {
+            float2 *Br = reinterpret_cast<float2 *>(B32 + (long long)slot * KP);
+            for (int b = lane; b < KP / 2; b += 64) {
+                float2 iz = make_float2(0.f, 0.f);
+                if (b < n) {
+                    const long long o = 2 * (c * n + b);
+                    iz = injection32(S, U, w, o, b, aP, aI);
+                    *reinterpret_cast<float2 *>(Ip + o) = iz;
+                }
+                Br[b] = iz;
+            }
+        } else {
+            uint32_t *Br = B16 + (long long)slot * (KP16 / 2);
+            for (int b = lane; b < KP16 / 2; b += 64) {
+                uint32_t out = 0u;
+                if (b < n) {
+                    const long long o = 2 * (c * n + b);
+                    out = low_entry<MODE>(injection32(S, U, w, o, b, aP, aI), reinterpret_cast<float2 *>(Ip + o),
+                                          m.ph, m.ks);
+                }
+                Br[b] = out;
+            }
+        }
     }
 }
 
 }  // namespace
+
+// Whether a sweep of solve `seq` already found every column retired: the sweeps queued
+// after it would all exit at once, so the host queues no more.  A read of pinned host
+// memory; it never waits for the device.
+static bool all_retired(const DeviceNet &dn, int seq) {
+    return dn.done_host && __atomic_load_n(dn.done_host, __ATOMIC_ACQUIRE) == seq;
+}
+
+// Fixed grids of the queued sweeps: enough blocks to fill the chip, few enough that a
+// sweep with nothing left to do costs little.
+constexpr int64_t kGemmGrid = 1024, kFinishGrid = 1024;
 
 // Workspace of the large path: state [tau][2n] (T), B operand [tau rounded to 64][KP] (T),
 // dmax [tau] (u64), bad flags [tau] (int), two active lists [tau] (i64), counters.
@@ -639,33 +716,33 @@ static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *
     p += al((size_t)tau * 8);
     act[1] = reinterpret_cast<long long *>(p);
     p += al((size_t)tau * 8);
-    int *cnt = reinterpret_cast<int *>(p);  // [0], [1]: active counts of the two lists
+    int *cnt = reinterpret_cast<int *>(p);  // three active counts in rotation
     const T *A = sizeof(T) == 8 ? (const T *)(const void *)dn.AL64 : (const T *)(const void *)dn.AL32;
     const double *w = dn.wl;
     hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)std::min<int64_t>(65536, (tau + 255) / 256)), dim3(256), 0, st,
                        badf, (long long)tau);
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cnt, 2LL);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cnt, 3LL);
     hipLaunchKernelGGL((init_kernel<T, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)V0, w, n,
                        (long long)tau, x, iters, act[0], cnt, dmax);
-    int na = (int)tau, cur = 0;
-    for (int sweep = 0; sweep < max_iter && na > 0; ++sweep) {
-        const long long arows = (na + 63) / 64 * 64;
-        hipLaunchKernelGGL((inject_kernel<T, IO>), dim3((unsigned)std::min<long long>(65536, (arows * KP / 2 + 255) / 256)),
-                           dim3(256), 0, st, (const IO *)S, x, w, n, KP, act[cur], cnt + cur, (int)arows, dn.aP,
-                           dn.aI, B);
-        hipLaunchKernelGGL((gemm_kernel<T>), dim3((unsigned)(arows / 64), (unsigned)(MP / 64)), dim3(256), 0, st, A, KP,
-                           B, act[cur], cnt + cur, w, n, x, dmax, badf);
-        hipLaunchKernelGGL((finish_kernel<T, IO>), dim3((unsigned)((na + 3) / 4)), dim3(256), 0, st, act[cur],
-                           cnt + cur, x, w, n, tol, max_iter, dmax, badf, iters, status, (IO *)V,
-                           act[cur ^ 1], cnt + (cur ^ 1));
-        // next sweep's count to the host; the list just consumed is cleared for reuse
-        int next = 0;
-        if (hipMemcpyAsync(&next, cnt + (cur ^ 1), sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
-            return fail(TPF_ERR_DEVICE, "active-count copy failed");
-        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cnt + cur, 1LL);
-        if (hipStreamSynchronize(st) != hipSuccess) return fail(TPF_ERR_DEVICE, "large sweep failed");
-        na = next;
-        cur ^= 1;
+    hipLaunchKernelGGL((inject_kernel<T, IO>), dim3((unsigned)std::min<long long>(65536, (rows * KP / 2 + 255) / 256)),
+                       dim3(256), 0, st, (const IO *)S, x, w, n, KP, act[0], cnt, (int)rows, dn.aP, dn.aI, B);
+    // Every sweep is queued without waiting, with grids fixed from tau: the active counts
+    // stay on the device (three of them in rotation: read, appended, cleared) and the
+    // kernels of a sweep with no active column exit at once.  Queueing stops early when
+    // the device has already posted that none is left (all_retired).
+    const int row_blocks = MP / 64;
+    const unsigned g_mm = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)row_blocks * (rows / 64));
+    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + 3) / 4);
+    const int seq = ++dn.solve_seq;
+    for (int sweep = 0; sweep < max_iter; ++sweep) {
+        if (all_retired(dn, seq)) break;
+        const int cur = sweep & 1;
+        int *cr = cnt + sweep % 3, *cn = cnt + (sweep + 1) % 3, *cz = cnt + (sweep + 2) % 3;
+        hipLaunchKernelGGL((gemm_kernel<T>), dim3(g_mm), dim3(256), 0, st, A, KP, B, act[cur], cr, row_blocks, w, n, x,
+                           dmax, badf);
+        hipLaunchKernelGGL((finish_kernel<T, IO>), dim3(g_fin), dim3(256), 0, st, act[cur], cr, cz, (const IO *)S, x, w,
+                           n, KP, dn.aP, dn.aI, tol, max_iter, dmax, badf, iters, status, (IO *)V, act[cur ^ 1], cn,
+                           B, dn.done_dev, seq);
     }
     return TPF_OK;
 }
@@ -694,7 +771,7 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
     p += al((size_t)tau * 8);
     actL[1] = reinterpret_cast<long long *>(p);
     p += al((size_t)tau * 8);
-    int *cnt = reinterpret_cast<int *>(p);  // [2 * parity + {0: low, 1: refine}]
+    int *cnt = reinterpret_cast<int *>(p);  // [3 pairs in rotation][0: low, 1: refine]
     p += 256;
     float *Ip = reinterpret_cast<float *>(p);
     p += al((size_t)tau * 2 * n * 4);
@@ -711,42 +788,33 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
     const uint16_t *A16 = MODE == TPF_MODE_MIXED_FP16 ? dn.ALh : dn.ALbf;
     hipLaunchKernelGGL(zero_i32_kernel, dim3((unsigned)std::min<int64_t>(65536, (tau + 255) / 256)), dim3(256), 0, st,
                        badf, (long long)tau);
-    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cnt, 4LL);
+    hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cnt, 6LL);
     hipLaunchKernelGGL((init_kernel<float, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)V0, w,
                        n, (long long)tau, U, iters, actL[0], cnt, dmax);
     hipLaunchKernelGGL((init_mix_kernel<MODE, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)S,
                        n, (long long)tau, dn.sZ, dn.aP ? dn.zscale : 1.0f, ms, umax);
-    int nl = (int)tau, nr = 0, cur = 0;
-    for (int sweep = 0; sweep < max_iter && nl + nr > 0; ++sweep) {
-        int *cc = cnt + 2 * cur, *cn = cnt + 2 * (cur ^ 1);
-        if (nr > 0) {
-            const long long ar = (nr + 63) / 64 * 64;
-            hipLaunchKernelGGL((inject_refine_kernel<IO>), dim3((unsigned)std::min<long long>(65536, (ar * KP / 2 + 255) / 256)),
-                               dim3(256), 0, st, (const IO *)S, U, w, Ip, n, KP, actR[cur], cc + 1, (int)ar, dn.aP,
-                               dn.aI, B32);
-            hipLaunchKernelGGL((gemm_kernel<float>), dim3((unsigned)(ar / 64), (unsigned)(MP / 64)), dim3(256), 0, st,
-                               dn.AL32, KP, B32, actR[cur], cc + 1, w, n, U, dmax, badf);
-        }
-        if (nl > 0) {
-            const long long ar = (nl + 127) / 128 * 128;
-            hipLaunchKernelGGL((inject_low_kernel<MODE, IO>),
-                               dim3((unsigned)std::min<long long>(65536, (ar * K16 / 2 + 255) / 256)), dim3(256), 0, st,
-                               (const IO *)S, U, w, Ip, ms, n, K16, actL[cur], cc, (int)ar, dn.aP, dn.aI,
-                               reinterpret_cast<uint32_t *>(B16));
-            hipLaunchKernelGGL((gemm_low_kernel<MODE>), dim3((unsigned)(ar / 128), (unsigned)(MP / 128)), dim3(256), 0,
-                               st, A16, K16, B16, actL[cur], cc, ms, n, U, dmax, umax, badf);
-        }
-        hipLaunchKernelGGL((finish_mixed_kernel<MODE, IO>), dim3((unsigned)(((long long)nl + nr + 3) / 4)), dim3(256), 0,
-                           st, actR[cur], actL[cur], cc, U, w, n, (float)tol, max_iter, dmax, umax, badf, ms, iters,
-                           status, (IO *)V, actR[cur ^ 1], actL[cur ^ 1], cn);
-        int next[2] = {0, 0};
-        if (hipMemcpyAsync(next, cn, 2 * sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess)
-            return fail(TPF_ERR_DEVICE, "active-count copy failed");
-        hipLaunchKernelGGL(zero_i32_kernel, dim3(1), dim3(64), 0, st, cc, 2LL);
-        if (hipStreamSynchronize(st) != hipSuccess) return fail(TPF_ERR_DEVICE, "large sweep failed");
-        nl = next[0];
-        nr = next[1];
-        cur ^= 1;
+    hipLaunchKernelGGL((inject_low_kernel<MODE, IO>),
+                       dim3((unsigned)std::min<long long>(65536, (rows16 * K16 / 2 + 255) / 256)), dim3(256), 0, st,
+                       (const IO *)S, U, w, Ip, ms, n, K16, actL[0], cnt, (int)rows16, dn.aP, dn.aI,
+                       reinterpret_cast<uint32_t *>(B16));
+    // Queued at once as in run_large; counts in pairs {low, refine}, three pairs in rotation.
+    const unsigned g_r = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 64) * (rows / 64));
+    const unsigned g_l = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 128) * (rows16 / 128));
+    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + 3) / 4);
+    const int seq = ++dn.solve_seq;
+    for (int sweep = 0; sweep < max_iter; ++sweep) {
+        if (all_retired(dn, seq)) break;
+        const int cur = sweep & 1;
+        int *cc = cnt + 2 * (sweep % 3), *cn = cnt + 2 * ((sweep + 1) % 3), *cz = cnt + 2 * ((sweep + 2) % 3);
+        if (sweep > 0)  // the first sweep has no refine list
+            hipLaunchKernelGGL((gemm_kernel<float>), dim3(g_r), dim3(256), 0, st, dn.AL32, KP, B32, actR[cur], cc + 1,
+                               MP / 64, w, n, U, dmax, badf);
+        hipLaunchKernelGGL((gemm_low_kernel<MODE>), dim3(g_l), dim3(256), 0, st, A16, K16, B16, actL[cur], cc, ms, n,
+                           U, dmax, umax, badf, MP / 128);
+        hipLaunchKernelGGL((finish_mixed_kernel<MODE, IO>), dim3(g_fin), dim3(256), 0, st, actR[cur], actL[cur], cc, cz,
+                           (const IO *)S, U, w, n, KP, K16, dn.aP, dn.aI, (float)tol, max_iter, dmax, umax, badf, ms,
+                           iters, status, (IO *)V, Ip, actR[cur ^ 1], actL[cur ^ 1], cn, B32,
+                           reinterpret_cast<uint32_t *>(B16), dn.done_dev, seq);
     }
     return TPF_OK;
 }

@@ -215,6 +215,13 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
         int e = 0;
         (void)std::frexp(zmax > 0 ? zmax : 1.0, &e);
         dn.sZ = 14 - e;  // FP16 operand Z 2^sZ: largest entry just below 2^14
+        if (hipHostMalloc((void **)&dn.done_host, 256, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+            dn.done_host = nullptr;
+            return fail(TPF_ERR_OOM, "pinned host allocation failed (network staging)");
+        }
+        *dn.done_host = 0;
+        if (hipHostGetDevicePointer((void **)&dn.done_dev, dn.done_host, 0) != hipSuccess)
+            return fail(TPF_ERR_DEVICE, "pinned host word not mapped (network staging)");
         std::vector<double> a64((size_t)M64 * KP, 0.0);
         std::vector<float> a32((size_t)M32 * KP, 0.0f);
         std::vector<uint16_t> abf((size_t)M32 * K16, 0), ah((size_t)M32 * K16, 0);
@@ -311,6 +318,7 @@ int device_net(tpf_network net, DeviceNet **out) {
         int rc = upload(*net, *dn);
         if (rc != TPF_OK) {
             for (void *p : dn->owned) (void)hipFree(p);
+            if (dn->done_host) (void)hipHostFree(dn->done_host);
             delete dn;
             return rc;
         }
@@ -365,11 +373,64 @@ static int check_topology(int32_t n_bus, int32_t n_branch, const int32_t *from, 
     return TPF_OK;
 }
 
+// Branches of a radial network (n_bus - 1 branches, connected), for its tree layout and
+// its factorisation-free Z.
+struct TreeBranches {
+    int32_t n_branch;
+    const int32_t *from, *to;
+    std::vector<cd> zbr;  // phases x phases per branch, row-major
+    int phases;
+};
+
+static void build_tree(tpf_network_s &net, int32_t n_branch, const int32_t *from, const int32_t *to,
+                       const std::vector<cd> &zbr, int phases);
+
+// Eq. (2) for a radial network with series branches only: Y_dd = A^T diag(y_b) A with A
+// the square branch-bus incidence of the tree, whose inverse marks the branches on each
+// bus's path from the slack.  So Y_dd^-1 between demand nodes of buses p and q is the sum
+// of the impedance blocks of the branches their two paths share, and Z = -Y_dd^-1 follows
+// in O(n^2) from the tree layout: the row of bus p is its parent's row, with the columns
+// of p's subtree set to p's own path impedance.
+static void tree_inverse(tpf_network_s &net) {
+    const int N = net.n_bus, P = net.tree_phases, n = net.n, pp = P * P;
+    const auto &par = net.tree_parent, &c0 = net.tree_c0, &c1 = net.tree_c1;
+    // path impedance per position (positions are breadth-first: parents come first)
+    std::vector<cd> zp((size_t)N * pp, 0.0);
+    for (int p = 1; p < N; ++p)
+        for (int e = 0; e < pp; ++e) zp[(size_t)p * pp + e] = zp[(size_t)par[p] * pp + e] + net.tree_z[(size_t)p * pp + e];
+    // depth-first preorder: each subtree is the contiguous range [pre[p], pre[p] + size[p])
+    std::vector<int> pre(N), size(N, 1), dfs;
+    dfs.reserve(N);
+    std::vector<int> stack = {0};
+    while (!stack.empty()) {
+        const int u = stack.back();
+        stack.pop_back();
+        pre[u] = (int)dfs.size();
+        dfs.push_back(u);
+        for (int v = c1[u] - 1; v >= c0[u]; --v) stack.push_back(v);
+    }
+    for (int p = N - 1; p >= 1; --p) size[par[p]] += size[p];
+    net.Z.assign((size_t)n * n, 0.0);
+    for (int i = 1; i < N; ++i) {  // preorder: the parent's rows are already complete
+        const int p = dfs[i], k = net.tree_pq[p], pa = par[p];
+        for (int a = 0; a < P; ++a) {
+            cd *row = &net.Z[(size_t)(P * k + a) * n];
+            if (pa > 0) std::copy_n(&net.Z[(size_t)(P * net.tree_pq[pa] + a) * n], n, row);
+            for (int j = pre[p]; j < pre[p] + size[p]; ++j) {
+                const int m = net.tree_pq[dfs[j]];
+                for (int b = 0; b < P; ++b) row[P * m + b] = -zp[(size_t)p * pp + a * P + b];
+            }
+        }
+    }
+}
+
 // Sec. II Eqs. (1)-(2) from a node-level admittance matrix Y [Nn][Nn]: the slack nodes
 // (with their voltages) against the demand nodes in ascending node order; CSR of Y_dd,
-// c = Y_ds v_s, Z = -Y_dd^-1 (LU with partial pivoting), w = Z c.
+// c = Y_ds v_s, Z = -Y_dd^-1 (LU with partial pivoting, or the path sums of tree_inverse
+// for a radial network given its branches), w = Z c.
 static int finish_network(const std::vector<cd> &Y, int Nn, const std::vector<int> &slack_nodes,
-                          const std::vector<cd> &vs_nodes, int n_bus, int slack_bus, tpf_network *out) {
+                          const std::vector<cd> &vs_nodes, int n_bus, int slack_bus, const TreeBranches *tree,
+                          tpf_network *out) {
     auto *net = new (std::nothrow) tpf_network_s();
     if (!net) return fail(TPF_ERR_OOM, "host allocation failed");
     try {
@@ -383,34 +444,42 @@ static int finish_network(const std::vector<cd> &Y, int Nn, const std::vector<in
         std::vector<int> pq;
         for (int b = 0; b < Nn; ++b)
             if (!is_slack[b]) pq.push_back(b);
-        std::vector<cd> Ydd((size_t)n * n);
         net->c.assign(n, 0.0);
-        for (int i = 0; i < n; ++i) {
+        for (int i = 0; i < n; ++i)
             for (size_t p = 0; p < slack_nodes.size(); ++p)
                 net->c[i] += Y[(size_t)pq[i] * Nn + slack_nodes[p]] * vs_nodes[p];
-            for (int j = 0; j < n; ++j) Ydd[(size_t)i * n + j] = Y[(size_t)pq[i] * Nn + pq[j]];
-        }
         net->rowptr.assign(1, 0);
         for (int i = 0; i < n; ++i) {
-            for (int j = 0; j < n; ++j)
-                if (Ydd[(size_t)i * n + j] != 0.0) net->colidx.push_back(j), net->yval.push_back(Ydd[(size_t)i * n + j]);
+            for (int j = 0; j < n; ++j) {
+                const cd y = Y[(size_t)pq[i] * Nn + pq[j]];
+                if (y != 0.0) net->colidx.push_back(j), net->yval.push_back(y);
+            }
             net->rowptr.push_back((int32_t)net->colidx.size());
         }
-        // Eq. (2): Z = -Y_dd^-1 (column by column from the LU factors), w = Z (Y_ds v_s).
-        std::vector<int> piv;
-        std::vector<cd> lu = Ydd;
-        if (!lu_factor(lu, piv, n)) {
-            delete net;
-            return fail(TPF_ERR_SINGULAR, "Y_dd is numerically singular");
+        if (tree) {
+            net->phases = tree->phases;
+            build_tree(*net, tree->n_branch, tree->from, tree->to, tree->zbr, tree->phases);
+            tree_inverse(*net);
+        } else {
+            // Eq. (2): Z = -Y_dd^-1 (column by column from the LU factors)
+            std::vector<int> piv;
+            std::vector<cd> lu((size_t)n * n);
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) lu[(size_t)i * n + j] = Y[(size_t)pq[i] * Nn + pq[j]];
+            if (!lu_factor(lu, piv, n)) {
+                delete net;
+                return fail(TPF_ERR_SINGULAR, "Y_dd is numerically singular");
+            }
+            net->Z.assign((size_t)n * n, 0.0);
+            std::vector<cd> col(n);
+            for (int j = 0; j < n; ++j) {
+                std::fill(col.begin(), col.end(), cd(0.0));
+                col[j] = -1.0;
+                lu_solve(lu, piv, n, col.data());
+                for (int i = 0; i < n; ++i) net->Z[(size_t)i * n + j] = col[i];
+            }
         }
-        net->Z.assign((size_t)n * n, 0.0);
-        std::vector<cd> col(n);
-        for (int j = 0; j < n; ++j) {
-            std::fill(col.begin(), col.end(), cd(0.0));
-            col[j] = -1.0;
-            lu_solve(lu, piv, n, col.data());
-            for (int i = 0; i < n; ++i) net->Z[(size_t)i * n + j] = col[i];
-        }
+        // w = Z (Y_ds v_s)
         net->w.assign(n, 0.0);
         for (int i = 0; i < n; ++i) {
             cd acc = 0.0;
@@ -501,17 +570,17 @@ extern "C" int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t 
     } catch (const std::bad_alloc &) {
         return fail(TPF_ERR_OOM, "host allocation failed");
     }
-    rc = finish_network(Y, N, {slack_bus}, {cd(vs_re, vs_im)}, n_bus, slack_bus, out);
-    if (rc == TPF_OK && n_branch == n_bus - 1) {
-        try {
-            std::vector<cd> zbr(n_branch);
-            for (int k = 0; k < n_branch; ++k) zbr[k] = cd(r[k], x[k]);
-            build_tree(**out, n_branch, from, to, zbr, 1);
-        } catch (const std::bad_alloc &) {  // the tree operator then reports the network unsupported
-            (*out)->tree_pq.clear();
+    TreeBranches tb{n_branch, from, to, {}, 1};
+    const bool radial = n_branch == n_bus - 1;  // connected (checked) with n_bus - 1 branches
+    try {
+        if (radial) {
+            tb.zbr.resize(n_branch);
+            for (int k = 0; k < n_branch; ++k) tb.zbr[k] = cd(r[k], x[k]);
         }
+    } catch (const std::bad_alloc &) {
+        return fail(TPF_ERR_OOM, "host allocation failed");
     }
-    return rc;
+    return finish_network(Y, N, {slack_bus}, {cd(vs_re, vs_im)}, n_bus, slack_bus, radial ? &tb : nullptr, out);
 }
 
 extern "C" int tpf_build_network_3ph(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
@@ -562,19 +631,18 @@ extern "C" int tpf_build_network_3ph(int32_t n_bus, int32_t n_branch, const int3
     }
     const std::vector<int> sn = {3 * slack_bus, 3 * slack_bus + 1, 3 * slack_bus + 2};
     const std::vector<cd> vs = {cd(vs_abc[0], vs_abc[1]), cd(vs_abc[2], vs_abc[3]), cd(vs_abc[4], vs_abc[5])};
-    rc = finish_network(Y, Nn, sn, vs, n_bus, slack_bus, out);
-    if (rc == TPF_OK) {
-        (*out)->phases = 3;
-        if (n_branch == n_bus - 1) {
-            try {
-                std::vector<cd> zbr((size_t)9 * n_branch);
-                for (size_t e = 0; e < zbr.size(); ++e) zbr[e] = cd(zabc[2 * e], zabc[2 * e + 1]);
-                build_tree(**out, n_branch, from, to, zbr, 3);
-            } catch (const std::bad_alloc &) {
-                (*out)->tree_pq.clear();
-            }
+    TreeBranches tb{n_branch, from, to, {}, 3};
+    const bool radial = n_branch == n_bus - 1;
+    try {
+        if (radial) {
+            tb.zbr.resize((size_t)9 * n_branch);
+            for (size_t e = 0; e < tb.zbr.size(); ++e) tb.zbr[e] = cd(zabc[2 * e], zabc[2 * e + 1]);
         }
+    } catch (const std::bad_alloc &) {
+        return fail(TPF_ERR_OOM, "host allocation failed");
     }
+    rc = finish_network(Y, Nn, sn, vs, n_bus, slack_bus, radial ? &tb : nullptr, out);
+    if (rc == TPF_OK) (*out)->phases = 3;
     return rc;
 }
 
@@ -586,6 +654,7 @@ extern "C" void tpf_free_network(tpf_network net) {
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(dn->device);
         for (void *p : dn->owned) (void)hipFree(p);
+        if (dn->done_host) (void)hipHostFree(dn->done_host);
         (void)hipSetDevice(cur);
         delete dn;
     }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <complex>
 #include <cstdint>
 #include <mutex>
@@ -59,6 +60,11 @@ struct DeviceNet {
     float *AL32 = nullptr;
     uint16_t *ALbf = nullptr, *ALh = nullptr;
     double *wl = nullptr;
+    // Large path: a pinned host word, mapped for the device (done_dev), to which a sweep
+    // that finds no active column posts its solve's sequence number; the host loop that
+    // queues the sweeps reads it without waiting and stops queueing once it matches.
+    int *done_host = nullptr, *done_dev = nullptr;
+    mutable std::atomic<int> solve_seq{0};
     // Sparse Y_dd (CSR) and c = Y_ds v_s for the FP64 mismatch.
     int32_t *rowptr = nullptr;   // [n+1]
     int32_t *colidx = nullptr;   // [nnz]

@@ -198,3 +198,61 @@ def test_1000bus_200k_steps_sampled(gpu, feeder1000, mode, dtype):
         assert np.abs(Vg.cpu().numpy().astype(np.complex128) - ref.V).max() <= FAST_BOUND
     ymax = np.abs(onet.Ydd).sum(axis=1).max()
     assert float(mm.max()) < ymax * 1.2e-7 + 2e-7
+
+
+@pytest.mark.parametrize("mode", ["fp64", "mixed_fp16"])
+def test_solve_returns_before_device_finishes(gpu, feeder1000, mode):
+    """The large path queues every sweep without waiting on the device: the call returns
+    while its kernels still run (about 20,000 columns of 999 PQ buses take tens of ms on
+    the device, queueing takes about 1 ms), and the results read after a sync are right."""
+    f, net, onet = feeder1000
+    T = 20_000
+    S = W.profile_minute_year(f, steps=T)
+    Sd = _dev(S, gpu)
+    out = tpf.alloc_outputs(net, Sd, mode=mode)
+    tpf.solve_timeseries(net, Sd, tol=1e-6, max_iter=100, mode=mode, out=out)  # network and allocator warm
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    V, it, st = tpf.solve_timeseries(net, Sd, tol=1e-6, max_iter=100, mode=mode, out=out)
+    pending = not torch.cuda.current_stream().query()
+    ev1.record()
+    torch.cuda.synchronize()
+    assert pending, f"the solve waited for the device ({ev0.elapsed_time(ev1):.1f} ms of device time)"
+    assert int(st.max()) == tpf.ST_CONVERGED
+    idx = np.array([0, 1, 7777, T - 1])
+    if mode == "fp64":
+        _compare(onet, S[idx], V[idx], it[idx], st[idx], 1e-6, 100, TOL_FP64)
+    else:
+        ref = oracle.fpi(onet, S[idx], 1e-10, 200)
+        assert np.abs(V.cpu().numpy()[idx] - ref.V).max() <= FAST_BOUND
+
+
+@pytest.fixture(scope="module")
+def feeder2000():
+    f = W.make_feeder(2000)
+    return f, tpf.Network.from_feeder(f), oracle.build_feeder(f)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "mixed_fp16", "mixed_bf16"])
+def test_2000bus_sampled(gpu, feeder2000, mode):
+    """1,999 PQ buses (operator 3,998 x 3,998), 3,000 minute steps; 300 sampled columns
+    against the oracle (FP64: same tolerance, rounding-order bound; fast forms: the 1e-6
+    pu contract against a 1e-10 oracle), and their FP64 mismatch against the oracle's."""
+    f, net, onet = feeder2000
+    T = 3000
+    S = W.profile_minute_year(f, steps=T, t0=200_000)
+    V, it, st, mm = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode=mode, mismatch=True)
+    torch.cuda.synchronize()
+    assert int(st.max()) == tpf.ST_CONVERGED
+    rng = np.random.default_rng(13)
+    idx = np.unique(np.concatenate([rng.integers(0, T, 300), [0, T - 1]]))
+    ig = torch.from_numpy(idx).to(gpu)
+    Vs = V[ig]
+    if mode == "fp64":
+        _compare(onet, S[idx], Vs, it[ig], st[ig], 1e-6, 100, TOL_FP64)
+    else:
+        ref = oracle.fpi(onet, S[idx], 1e-10, 200)
+        assert np.abs(Vs.cpu().numpy() - ref.V).max() <= FAST_BOUND
+    mref = oracle.mismatch(onet, S[idx], Vs.cpu().numpy())
+    assert np.all(np.abs(mm[ig].cpu().numpy() - mref) <= _mm_rounding(onet) + 1e-9 * mref)
