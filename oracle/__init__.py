@@ -59,7 +59,10 @@ def _load():
         lib.oracle_fpi_zip.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double, P, P, ctypes.c_int64,
                                        P, ctypes.c_double, ctypes.c_int, P, P, P, P, P]
         lib.oracle_fpi_zip.restype = None
-        lib.oracle_mismatch_zip.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double, P, P,
+        lib.oracle_fpi_zipz.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double, P, P, P,
+                                        ctypes.c_int64, P, ctypes.c_double, ctypes.c_int, P, P, P, P, P]
+        lib.oracle_fpi_zipz.restype = None
+        lib.oracle_mismatch_zip.argtypes = [ctypes.c_int, P, P, ctypes.c_double, ctypes.c_double, P, P, P,
                                             ctypes.c_int64, P, P, P]
         lib.oracle_mismatch_zip.restype = None
         lib.oracle_num_threads.restype = ctypes.c_int
@@ -182,13 +185,18 @@ def _alphas(net: OracleNetwork, alpha_i, alpha_p):
 
 
 def fpi_zip(net: OracleNetwork, S: np.ndarray, alpha_i, alpha_p, tol: float, max_iter: int,
-            V0: np.ndarray | None = None) -> FpiResult:
-    """Eq. (2) with ZIP loads (alpha_Z = 0; alpha_I, alpha_P per PQ bus or scalars):
-    per column F = -B^-1 diag(alpha_P s*), w = -B^-1 (Y_ds v_s + alpha_I s*), B = Y_dd,
-    iterated as Algorithm 1."""
+            V0: np.ndarray | None = None, alpha_z=None) -> FpiResult:
+    """Eq. (2) with ZIP loads (alpha_Z, alpha_I, alpha_P per PQ bus or scalars): per
+    column F = -B^-1 diag(alpha_P s*), w = -B^-1 (Y_ds v_s + alpha_I s*) with
+    B = diag(alpha_Z s*) + Y_dd, iterated as Algorithm 1.  Without alpha_Z, B = Y_dd and
+    the network's Z = -Y_dd^-1 serves every column; with it, each column eliminates
+    its own B."""
     lib = _load()
     S = np.ascontiguousarray(np.asarray(S).reshape(-1, net.n), np.complex128)
     ai, ap = _alphas(net, alpha_i, alpha_p)
+    if alpha_z is not None:
+        az = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha_z, np.float64), (net.n,)))
+        return _fpi_zipz(lib, net, S, az, ai, ap, tol, max_iter, V0)
     tau = S.shape[0]
     V = np.empty_like(S)
     iters = np.empty(tau, np.int32)
@@ -205,16 +213,37 @@ def fpi_zip(net: OracleNetwork, S: np.ndarray, alpha_i, alpha_p, tol: float, max
     return FpiResult(V, iters, status, d)
 
 
-def mismatch_zip(net: OracleNetwork, S: np.ndarray, V: np.ndarray, alpha_i, alpha_p) -> np.ndarray:
-    """Per-column max |S .* (alpha_P + alpha_I .* V) + V .* conj(Y_ds v_s + Y_dd V)|."""
+def _fpi_zipz(lib, net, S, az, ai, ap, tol, max_iter, V0):
+    tau = S.shape[0]
+    V = np.empty_like(S)
+    iters = np.empty(tau, np.int32)
+    status = np.empty(tau, np.int8)
+    d = np.empty(tau, np.float64)
+    v0p = None
+    if V0 is not None:
+        V0 = np.ascontiguousarray(np.asarray(V0).reshape(-1, net.n), np.complex128)
+        assert V0.shape == S.shape
+        v0p = _ptr(V0)
+    lib.oracle_fpi_zipz(net.n, _ptr(np.ascontiguousarray(net.Ydd)), _ptr(np.ascontiguousarray(net.Yds)),
+                        float(np.real(net.vs)), float(np.imag(net.vs)), _ptr(az), _ptr(ai), _ptr(ap), tau, _ptr(S),
+                        float(tol), int(max_iter), v0p, _ptr(V), _ptr(iters), _ptr(status), _ptr(d))
+    return FpiResult(V, iters, status, d)
+
+
+def mismatch_zip(net: OracleNetwork, S: np.ndarray, V: np.ndarray, alpha_i, alpha_p, alpha_z=None) -> np.ndarray:
+    """Per-column max |S .* (alpha_P + alpha_I .* V + alpha_Z .* |V|^2) + V .* conj(Y_ds v_s + Y_dd V)|."""
     lib = _load()
     S = np.ascontiguousarray(np.asarray(S).reshape(-1, net.n), np.complex128)
     V = np.ascontiguousarray(np.asarray(V).reshape(-1, net.n), np.complex128)
     ai, ap = _alphas(net, alpha_i, alpha_p)
+    azp = None
+    if alpha_z is not None:
+        az = np.ascontiguousarray(np.broadcast_to(np.asarray(alpha_z, np.float64), (net.n,)))
+        azp = _ptr(az)
     out = np.empty(S.shape[0], np.float64)
     lib.oracle_mismatch_zip(net.n, _ptr(np.ascontiguousarray(net.Ydd)), _ptr(np.ascontiguousarray(net.Yds)),
-                            float(np.real(net.vs)), float(np.imag(net.vs)), _ptr(ai), _ptr(ap), S.shape[0], _ptr(S),
-                            _ptr(V), _ptr(out))
+                            float(np.real(net.vs)), float(np.imag(net.vs)), azp, _ptr(ai), _ptr(ap), S.shape[0],
+                            _ptr(S), _ptr(V), _ptr(out))
     return out
 
 

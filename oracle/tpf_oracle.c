@@ -28,10 +28,16 @@
  *                    zero: per column A = diag(alpha_P .* s*), B = Y_dd,
  *                    c = Y_ds v_s + alpha_I .* s*, F = -B^-1 A, w = -B^-1 c, then
  *                    Algorithm 1 with v <- F conj(v)^-1 + w.
+ *   oracle_fpi_zipz  Eq. (2) with the full ZIP model: per column B = diag(alpha_Z .* s*)
+ *                    + Y_dd now depends on s, so F = -B^-1 A and w = -B^-1 c are formed
+ *                    per column by Gauss-Jordan elimination with partial pivoting on
+ *                    [B | A | c], then Algorithm 1 with v <- F conj(v)^-1 + w.
  *   oracle_mismatch_zip  The power balance of the same loads: a load draws
  *                    v .* conj(i) with i = alpha_I .* s* + alpha_P .* s* ./ conj(v),
  *                    i.e. s .* (alpha_P + alpha_I .* v), so
- *                    m = S .* (alpha_P + alpha_I .* V) + V .* conj(Y_ds v_s + Y_dd V).
+ *                    m = S .* (alpha_P + alpha_I .* V) + V .* conj(Y_ds v_s + Y_dd V);
+ *                    a constant-impedance share adds the current alpha_Z .* s* .* v,
+ *                    drawing alpha_Z .* s .* |v|^2.
  *
  * Readings where the paper is silent or garbled (listed in the design notes):
  *   - the stopping measure is the complex modulus of the voltage step,
@@ -369,10 +375,103 @@ void oracle_fpi_zip(int n, const double complex *Z, const double complex *Yds, d
     }
 }
 
-/* Power balance of ZIP loads (alpha_Z = 0): m = S .* (alpha_P + alpha_I .* V)
- * + V .* conj(Y_ds v_s + Y_dd V); max_i |m_i| per column. */
+/* Eq. (2) with alpha_Z != 0.  Per column: A = diag(alpha_P .* s*),
+ * B = diag(alpha_Z .* s*) + Y_dd, c = Y_ds v_s + alpha_I .* s*, and
+ * [F | w] = -B^-1 [A | c] from Gauss-Jordan elimination with partial pivoting on the
+ * n x (n + 1 + n) array [B | c | A]; then the same iteration as oracle_fpi_zip.
+ * A column whose B is numerically singular ends NONFINITE after 0 sweeps. */
+void oracle_fpi_zipz(int n, const double complex *Ydd, const double complex *Yds, double vs_re,
+                     double vs_im, const double *alpha_z, const double *alpha_i,
+                     const double *alpha_p, int64_t tau, const double complex *S, double tol,
+                     int max_iter, const double complex *V0, double complex *V, int32_t *iters,
+                     int8_t *status, double *dlast)
+{
+    double complex vs = vs_re + I * vs_im;
+    const int W = 2 * n + 1; /* columns of the augmented array */
+#pragma omp parallel
+    {
+        double complex *M = malloc(sizeof(double complex) * (size_t)n * W);
+        double complex *cur = malloc(sizeof(double complex) * n);
+        double complex *nxt = malloc(sizeof(double complex) * n);
+        double complex *rec = malloc(sizeof(double complex) * n);
+#pragma omp for schedule(static)
+        for (int64_t col = 0; col < tau; ++col) {
+            const double complex *s = S + col * n;
+            /* [B | c | A] */
+            double scale = 0.0;
+            for (int i = 0; i < n; ++i) {
+                double complex *row = M + (size_t)i * W;
+                for (int j = 0; j < n; ++j) row[j] = Ydd[(size_t)i * n + j];
+                row[i] += alpha_z[i] * conj(s[i]);
+                row[n] = Yds[i] * vs + alpha_i[i] * conj(s[i]);
+                for (int j = 0; j < n; ++j) row[n + 1 + j] = (i == j) ? alpha_p[i] * conj(s[i]) : 0.0;
+                for (int j = 0; j < n; ++j) scale = fmax(scale, cabs(row[j]));
+            }
+            int singular = 0;
+            for (int c = 0; c < n && !singular; ++c) {
+                int p = c;
+                double best = cabs(M[(size_t)c * W + c]);
+                for (int i = c + 1; i < n; ++i) {
+                    double v = cabs(M[(size_t)i * W + c]);
+                    if (v > best) { best = v; p = i; }
+                }
+                if (!(best > 1e-13 * scale)) { singular = 1; break; }
+                if (p != c)
+                    for (int j = 0; j < W; ++j) {
+                        double complex tmp = M[(size_t)c * W + j];
+                        M[(size_t)c * W + j] = M[(size_t)p * W + j];
+                        M[(size_t)p * W + j] = tmp;
+                    }
+                double complex piv = M[(size_t)c * W + c];
+                for (int j = 0; j < W; ++j) M[(size_t)c * W + j] /= piv;
+                for (int i = 0; i < n; ++i) {
+                    if (i == c) continue;
+                    double complex f = M[(size_t)i * W + c];
+                    if (f == 0.0) continue;
+                    for (int j = 0; j < W; ++j) M[(size_t)i * W + j] -= f * M[(size_t)c * W + j];
+                }
+            }
+            if (singular) {
+                for (int i = 0; i < n; ++i) V[col * n + i] = NAN;
+                iters[col] = 0;
+                status[col] = ST_NONFINITE;
+                if (dlast) dlast[col] = NAN;
+                continue;
+            }
+            /* now M = [1 | B^-1 c | B^-1 A]: w_i = -M[i][n], F_ij = -M[i][n + 1 + j] */
+            for (int i = 0; i < n; ++i) cur[i] = V0 ? V0[col * n + i] : 1.0;
+            double d = INFINITY;
+            int k = 0, bad = 0;
+            while (d >= tol && k < max_iter) {
+                for (int i = 0; i < n; ++i) rec[i] = 1.0 / conj(cur[i]);
+                for (int i = 0; i < n; ++i) {
+                    double complex acc = 0.0;
+                    for (int j = 0; j < n; ++j) acc += -M[(size_t)i * W + n + 1 + j] * rec[j];
+                    nxt[i] = acc - M[(size_t)i * W + n];
+                }
+                d = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    if (!isfinite(creal(nxt[i])) || !isfinite(cimag(nxt[i]))) bad = 1;
+                    double e = cabs(nxt[i] - cur[i]);
+                    if (e > d) d = e;
+                }
+                memcpy(cur, nxt, sizeof(double complex) * n);
+                ++k;
+                if (bad) break;
+            }
+            memcpy(V + col * n, cur, sizeof(double complex) * n);
+            iters[col] = k;
+            status[col] = bad ? ST_NONFINITE : (d < tol ? ST_CONVERGED : ST_MAX_ITER);
+            if (dlast) dlast[col] = bad ? NAN : d;
+        }
+        free(M); free(cur); free(nxt); free(rec);
+    }
+}
+
+/* Power balance of ZIP loads: m = S .* (alpha_P + alpha_I .* V + alpha_Z .* |V|^2)
+ * + V .* conj(Y_ds v_s + Y_dd V); max_i |m_i| per column.  alpha_z may be NULL (zero). */
 void oracle_mismatch_zip(int n, const double complex *Ydd, const double complex *Yds,
-                         double vs_re, double vs_im, const double *alpha_i,
+                         double vs_re, double vs_im, const double *alpha_z, const double *alpha_i,
                          const double *alpha_p, int64_t tau, const double complex *S,
                          const double complex *V, double *mmax)
 {
@@ -384,7 +483,9 @@ void oracle_mismatch_zip(int n, const double complex *Ydd, const double complex 
         for (int i = 0; i < n; ++i) {
             double complex acc = Yds[i] * vs;
             for (int j = 0; j < n; ++j) acc += Ydd[(size_t)i * n + j] * v[j];
-            double complex load = S[col * n + i] * (alpha_p[i] + alpha_i[i] * v[i]);
+            double az = alpha_z ? alpha_z[i] : 0.0;
+            double v2 = creal(v[i]) * creal(v[i]) + cimag(v[i]) * cimag(v[i]);
+            double complex load = S[col * n + i] * (alpha_p[i] + alpha_i[i] * v[i] + az * v2);
             double complex m = load + v[i] * conj(acc);
             double a = cabs(m);
             if (!(a <= worst)) worst = a; /* NaN propagates */

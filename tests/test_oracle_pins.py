@@ -396,6 +396,80 @@ def test_zip_mixed_shares_satisfy_power_balance(seed):
     assert oracle.mismatch(net, S, res.V).max() > 1e-6
 
 
+def _zipz_numpy_balance(net, S, V, az, ai, ap):
+    """Power balance with a constant-impedance share too, written independently of the
+    oracle: the load current alpha_Z s* v draws alpha_Z s |v|^2."""
+    inj = net.Yds[None, :] * net.vs + V @ net.Ydd.T
+    return np.abs(S * (ap + ai * V + az * np.abs(V) ** 2) + V * np.conj(inj)).max(axis=1)
+
+
+def test_zipz_twobus_closed_form():
+    """One PQ bus behind z with all three shares: (y + alpha_Z s*) v = y v_s - alpha_I s*
+    - alpha_P s*/v*, i.e. v = v_s' - z' alpha_P s*/v* with v_s' = (v_s - z alpha_I s*) /
+    (1 + z alpha_Z s*) and z' = z / (1 + z alpha_Z s*): the constant-power two-bus problem
+    again, whose high root is closed-form."""
+    z, vs = 0.05 + 0.08j, 1.02 + 0.01j
+    net = _twobus_net(z, vs)
+    for s, az, ai, ap in [(0.9 + 0.4j, 0.3, 0.3, 0.4), (1.2 - 0.2j, 0.6, 0.1, 0.3), (0.7 + 0.7j, 0.2, 0.0, 0.8),
+                          (1.5 + 0.5j, 1.0, 0.0, 0.0)]:
+        res = oracle.fpi_zip(net, np.array([[s]]), ai, ap, 1e-14, 500, alpha_z=az)
+        assert res.status[0] == oracle.ST_CONVERGED
+        k = 1.0 + z * az * np.conj(s)
+        vs2, z2 = (vs - z * ai * np.conj(s)) / k, z / k
+        vh = twobus_roots(z2, vs2, ap * s)[0] if ap > 0 else vs2
+        assert abs(res.V[0, 0] - vh) < 1e-12, (s, az, ai, ap)
+        assert _zipz_numpy_balance(net, np.array([[s]]), res.V, az, ai, ap)[0] < 1e-12
+
+
+def test_zipz_impedance_only_is_one_linear_solve():
+    """alpha_P = 0: F = 0 and the first sweep lands on v = -(diag(alpha_Z s*) + Y_dd)^-1
+    (Y_ds v_s + alpha_I s*), a library solve per column; the second sweep does not move."""
+    f = W.make_feeder(25)
+    net = oracle.build_feeder(f)
+    S = W.profile_daily96(f, steps=6)
+    rng = np.random.default_rng(4)
+    az = rng.uniform(0.2, 1.0, net.n)
+    ai = 1.0 - az
+    res = oracle.fpi_zip(net, S, ai, 0.0, 1e-12, 10, alpha_z=az)
+    assert np.all(res.iters == 2) and np.all(res.status == oracle.ST_CONVERGED)
+    for c in range(S.shape[0]):
+        B = net.Ydd + np.diag(az * np.conj(S[c]))
+        v = np.linalg.solve(B, -(net.Yds * net.vs + ai * np.conj(S[c])))
+        assert np.abs(res.V[c] - v).max() < 1e-12
+    assert _zipz_numpy_balance(net, S, res.V, az, ai, 0.0).max() < 1e-11
+
+
+def test_zipz_zero_share_is_the_alpha_z_free_iteration():
+    f = W.make_feeder(30)
+    net = oracle.build_feeder(f)
+    S = W.profile_daily96(f, steps=10)
+    a = oracle.fpi_zip(net, S, 0.3, 0.7, 1e-12, 100)
+    b = oracle.fpi_zip(net, S, 0.3, 0.7, 1e-12, 100, alpha_z=0.0)
+    assert np.array_equal(a.iters, b.iters) and np.array_equal(a.status, b.status)
+    assert np.abs(a.V - b.V).max() < 1e-13
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_zipz_mixed_shares_satisfy_power_balance(seed):
+    f = W.make_feeder(60, load_scale=3.0)
+    net = oracle.build_feeder(f)
+    S = W.profile_daily96(f, steps=12)
+    rng = np.random.default_rng(seed)
+    sh = rng.dirichlet([1.0, 1.0, 1.0], net.n)
+    az, ai, ap = sh[:, 0], sh[:, 1], sh[:, 2]
+    res = oracle.fpi_zip(net, S, ai, ap, 1e-13, 200, alpha_z=az)
+    assert np.all(res.status == oracle.ST_CONVERGED)
+    assert _zipz_numpy_balance(net, S, res.V, az, ai, ap).max() < 1e-11
+    assert oracle.mismatch_zip(net, S, res.V, ai, ap, alpha_z=az).max() < 1e-11
+    Vp = res.V + 1e-3 * (rng.standard_normal(S.shape) + 1j * rng.standard_normal(S.shape))
+    assert np.allclose(oracle.mismatch_zip(net, S, Vp, ai, ap, alpha_z=az),
+                       _zipz_numpy_balance(net, S, Vp, az, ai, ap), rtol=1e-10, atol=1e-13)
+    # the constant-impedance share moves the solution, and the alpha_Z-free balance sees it
+    nz = oracle.fpi_zip(net, S, ai + az, ap, 1e-13, 200)
+    assert np.abs(nz.V - res.V).max() > 1e-5
+    assert oracle.mismatch_zip(net, S, res.V, ai + az, ap).max() > 1e-6
+
+
 # ----------------------------------------------------------------------------- three phases
 
 def _a2():
