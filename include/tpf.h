@@ -66,8 +66,9 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
  *   modes tol must be >= 5e-7 pu (the FP32 state floor).
  * Network size: these four modes run any n.  FP64 beyond 320 PQ buses, and FP32 and
  * the mixed modes beyond 128, use a per-sweep kernel sequence (dense Z no longer fits
- * one workgroup's registers) whose host loop waits for the device once per sweep;
- * smaller networks run one persistent kernel per solve. */
+ * one workgroup's registers), queued up to max_iter sweeps without waiting for the
+ * device (a sweep with no active column left exits at once); smaller networks run one
+ * persistent kernel per solve. */
 /* TREE_FP64   the FP64 iteration with Z I evaluated by two passes over the feeder's
  *             tree instead of the dense product: on a radial network without shunts,
  *             -Z is the path-impedance matrix, so Z I = -D with branch currents
@@ -77,7 +78,14 @@ enum { TPF_C64 = 0, TPF_C128 = 1 };
  *             n_bus - 1 branches (a tree): single-phase with n <= 1024 PQ buses, or
  *             three-phase (3x3 blocks per branch) with at most 408 PQ buses in TREE_FP64
  *             (the LDS holds 400 bytes of state per bus) and 512 in TREE_FP32; returns
- *             TPF_ERR_UNSUPPORTED otherwise. */
+ *             TPF_ERR_UNSUPPORTED otherwise.  With a constant-impedance ZIP share
+ *             (tpf_build_network_zip) each subtree is a Norton load G x + J seen from
+ *             its parent: per column G'_b = G_b / (1 + z_b G_b), G_b = alpha_Z,b s_b* +
+ *             sum of the children's G', formed once, then per sweep
+ *             J'_b = k_b (I_b + sum of the children's J') with k_b = 1 - z_b G'_b
+ *             and D_b = k_b D_parent + z_b (J'_b + G'_b v_s), V = v_s - D: the exact
+ *             B^-1 solve of Eq. (2) for that column.  Single-phase only; the extra
+ *             per-column state limits TREE_FP64 to about 800 PQ buses there. */
 /* TREE_FP32   the tree operator in FP32 arithmetic with the state kept as the FP32 drop
  *             V - w (as in FP32 mode; tol >= 5e-7 pu); the same networks as TREE_FP64. */
 enum {
@@ -127,20 +135,23 @@ int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, cons
                       double vs_im, tpf_network *out);
 
 /* Sec. II Eq. (2) with a ZIP load model: the same network whose loads draw, at bus q,
- * the current alpha_I[q] s* + alpha_P[q] s* / conj(v) (constant-current and constant-power
- * shares of the nominal power s), i.e. the power s (alpha_P + alpha_I v).  Eq. (2) then
- * has A = diag(alpha_P s*), B = Y_dd, c = Y_ds v_s + alpha_I s*, and the sweeps compute
- * V <- Z (alpha_P conj(S./V) + alpha_I conj(S)) + w.
- *   alpha_z          host float64 [n] or NULL: constant-impedance shares; must be 0
- *                    (a nonzero share makes B, hence F and w, differ per power flow:
- *                    TPF_ERR_UNSUPPORTED)
+ * the current alpha_Z[q] s* v + alpha_I[q] s* + alpha_P[q] s* / conj(v) (constant-impedance,
+ * constant-current and constant-power shares of the nominal power s), i.e. the power
+ * s (alpha_P + alpha_I v + alpha_Z |v|^2).  Eq. (2) then has A = diag(alpha_P s*),
+ * B = diag(alpha_Z s*) + Y_dd, c = Y_ds v_s + alpha_I s*.
+ *   alpha_z          host float64 [n] or NULL (all zero): constant-impedance shares
  *   alpha_i, alpha_p host float64 [n] per PQ bus (PQ order), finite; any values
  *                    (they need not sum to 1)
- * Other arguments and errors as tpf_build_network; TPF_ERR_INVALID_ARG for a NULL or
- * non-finite share.  A ZIP network solves in every mode; the FP16 form widens its
- * per-column scale by max_q |alpha_P[q]| + |alpha_I[q]| so that the larger injections stay
- * in range.  Its mismatch (options.mismatch_out, tpf_mismatch) is the balance of these
- * loads: S (alpha_P + alpha_I V) + V conj(Y_ds v_s + Y_dd V). */
+ * Without a constant-impedance share B = Y_dd for every column and the sweeps compute
+ * V <- Z (alpha_P conj(S./V) + alpha_I conj(S)) + w in every mode; the FP16 form widens
+ * its per-column scale by max_q |alpha_P[q]| + |alpha_I[q]| so that the larger injections
+ * stay in range.  With one (some alpha_z[q] != 0) B differs per column: only the tree
+ * modes solve it, on radial networks, by a per-column elimination along the tree (no
+ * B^-1 is formed); the dense modes return TPF_ERR_UNSUPPORTED from the solve calls
+ * (max_iter = 0 still returns the start).  Other arguments and errors as
+ * tpf_build_network; TPF_ERR_INVALID_ARG for a NULL or non-finite share.  The mismatch
+ * (options.mismatch_out, tpf_mismatch) is the balance of these loads:
+ * S (alpha_P + alpha_I V + alpha_Z |V|^2) + V conj(Y_ds v_s + Y_dd V). */
 int tpf_build_network_zip(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
                           const double *r, const double *x, int32_t slack_bus, double vs_re, double vs_im,
                           const double *alpha_z, const double *alpha_i, const double *alpha_p,

@@ -104,7 +104,9 @@ class Network:
     """A feeder prepared for the sweeps: Z = -Y_dd^-1 and w (Sec. II Eqs. (1)-(2)).
 
     With alpha_i / alpha_p (per PQ bus, or scalars) the loads follow Eq. (2)'s ZIP model
-    with constant-current and constant-power shares (alpha_z must be zero or None)."""
+    with constant-current and constant-power shares; a non-zero constant-impedance share
+    alpha_z makes B = diag(alpha_Z s*) + Y_dd differ per column, which the tree modes
+    solve (radial, single-phase networks) and the dense modes refuse."""
 
     def __init__(self, n_bus: int, frm, to, r, x, slack: int = 0, vs: complex = 1.0 + 0.0j,
                  alpha_i=None, alpha_p=None, alpha_z=None):

@@ -35,33 +35,39 @@ namespace {
 
 constexpr int kTreeWaves = 4;
 
-template <typename IO, int CPW, int B, bool ZIP>
+template <typename IO, int CPW, int B, int ZM>
 __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const int32_t *__restrict__ tree_i,
     const double *__restrict__ tree_z, int n, int levels, long long tau, double tol, int max_iter,
-    const double *__restrict__ aP, const double *__restrict__ aI) {
+    const double *__restrict__ aP, const double *__restrict__ aI, const double *__restrict__ aZ, double vs_re,
+    double vs_im) {
     constexpr int LPC = 64 / CPW;  // lanes per column
+    constexpr int NZ = ZM == 0 ? 0 : ZM + 1;  // ZIP shares per position
     extern __shared__ double lds[];
     const int np = n + 1;
     double *tz = lds;                                        // [np][4]: z, w per position
-    double *za = tz + 4 * np;                                // [np][2]: alpha_P, alpha_I (ZIP)
-    double *Jw = za + (ZIP ? 2 * np : 0);                    // [waves][CPW][np][2]
-    int32_t *ti = reinterpret_cast<int32_t *>(Jw + kTreeWaves * CPW * 2 * np);  // [np][4], level starts
+    double *za = tz + 4 * np;                                // [np][NZ]: alpha_P, alpha_I (, alpha_Z)
+    double *Jw = za + NZ * np;                               // [waves][CPW][np][2]
+    double *Gw = Jw + kTreeWaves * CPW * 2 * np;             // ZM == 2: G' per column, as Jw
+    int32_t *ti = reinterpret_cast<int32_t *>(Gw + (ZM == 2 ? kTreeWaves * CPW * 2 * np : 0));  // [np][4], levels
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int slot = lane / LPC, sl = lane % LPC;  // column slot of the wavefront, lane within it
     for (int e = threadIdx.x; e < 4 * np; e += kTreeWaves * 64) tz[e] = tree_z[e];
     for (int e = threadIdx.x; e < 4 * np + levels + 2; e += kTreeWaves * 64) ti[e] = tree_i[e];
-    if constexpr (ZIP) {
+    if constexpr (ZM >= 1) {
         for (int p = threadIdx.x; p < np; p += kTreeWaves * 64) {
             const int q = tree_i[4 * p];
-            za[2 * p] = q >= 0 ? aP[q] : 0.0;
-            za[2 * p + 1] = q >= 0 ? aI[q] : 0.0;
+            za[NZ * p] = q >= 0 ? aP[q] : 0.0;
+            za[NZ * p + 1] = q >= 0 ? aI[q] : 0.0;
+            if constexpr (ZM == 2) za[NZ * p + 2] = q >= 0 ? aZ[q] : 0.0;
         }
     }
     __syncthreads();
     double *J = Jw + (wave * CPW + slot) * 2 * np;
+    double *G = Gw + (wave * CPW + slot) * 2 * np;
+    bool fresh = true;  // the slot's column is new: its G' still to be formed (ZM == 2)
     const int32_t *ls = ti + 4 * np;  // level L = positions [ls[L], ls[L+1])
     if (sl == 0) J[0] = J[1] = 0.0;   // the slack's drop
 
@@ -99,10 +105,46 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
             }
         }
         it = 0;
+        fresh = true;
     };
     load();
     while (__ballot(c < tau)) {
         const bool live = c < tau;
+        if constexpr (ZM == 2) {
+            // a constant-impedance share (Eq. (2), B = diag(alpha_Z s*) + Y_dd) makes each
+            // subtree a Norton load G x + J seen from its parent: G_b = y_b + sum over the
+            // children of G'_c with y_b = alpha_Z s_b* and G'_b = G_b / (1 + z_b G_b), which
+            // depends on the column's s only.  Formed once per column, slot by slot.
+            if (__ballot(fresh)) {
+#pragma unroll
+                for (int r = 0; r < B; ++r) {
+                    const int p = 1 + sl + LPC * r;
+                    if (fresh && p <= n) {
+                        const double az = za[NZ * p + 2];
+                        G[2 * p] = az * sr[r];
+                        G[2 * p + 1] = -az * si[r];
+                    }
+                }
+                wave_sync();
+                for (int L = levels; L >= 1; --L) {
+                    for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                        if (!fresh) continue;
+                        double gr = G[2 * p], gi = G[2 * p + 1];
+                        for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
+                            gr += G[2 * ch];
+                            gi += G[2 * ch + 1];
+                        }
+                        const double dr = 1.0 + tz[4 * p] * gr - tz[4 * p + 1] * gi;
+                        const double di = tz[4 * p] * gi + tz[4 * p + 1] * gr;
+                        const double dd = 1.0 / (dr * dr + di * di);
+                        G[2 * p] = (gr * dr + gi * di) * dd;
+                        G[2 * p + 1] = (gi * dr - gr * di) * dd;
+                    }
+                    wave_sync();
+                }
+                fresh = false;
+            }
+        }
         // injections conj(S./V) (ZIP: alpha_P conj(S./V) + alpha_I conj(S)) into J
 #pragma unroll
         for (int r = 0; r < B; ++r) {
@@ -110,8 +152,8 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
             if (p <= n) {
                 const double inv = 1.0 / (vr[r] * vr[r] + vi[r] * vi[r]);
                 double ir = (sr[r] * vr[r] + si[r] * vi[r]) * inv, ii = (sr[r] * vi[r] - si[r] * vr[r]) * inv;
-                if constexpr (ZIP) {
-                    const double ap = za[2 * p], ai = za[2 * p + 1];
+                if constexpr (ZM >= 1) {
+                    const double ap = za[NZ * p], ai = za[NZ * p + 1];
                     ir = ap * ir + ai * sr[r];
                     ii = ap * ii - ai * si[r];
                 }
@@ -120,7 +162,9 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
             }
         }
         wave_sync();
-        // backward pass, deepest level first: J_b += J of b's children
+        // backward pass, deepest level first: J_b += J of b's children (ZM == 2: the
+        // branch current's source part J'_b = k_b (I_b + sum of the children's J'),
+        // k_b = 1 / (1 + z_b G_b) = 1 - z_b G'_b)
         for (int L = levels; L >= 1; --L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
                 double jr = J[2 * p], ji = J[2 * p + 1];
@@ -128,29 +172,49 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
                     jr += J[2 * ch];
                     ji += J[2 * ch + 1];
                 }
+                if constexpr (ZM == 2) {
+                    const double kr = 1.0 - (tz[4 * p] * G[2 * p] - tz[4 * p + 1] * G[2 * p + 1]);
+                    const double ki = -(tz[4 * p] * G[2 * p + 1] + tz[4 * p + 1] * G[2 * p]);
+                    const double tr = kr * jr - ki * ji;
+                    ji = kr * ji + ki * jr;
+                    jr = tr;
+                }
                 J[2 * p] = jr;
                 J[2 * p + 1] = ji;
             }
             wave_sync();
         }
-        // forward pass, level 1 first: D_b = D_parent + z_b J_b (in place of J_b)
+        // forward pass, level 1 first: D_b = D_parent + z_b J_b (in place of J_b); ZM == 2:
+        // x_b = k_b x_parent - z_b J'_b, so with D = v_s - x,
+        // D_b = k_b D_parent + z_b (J'_b + G'_b v_s)
         for (int L = 1; L <= levels; ++L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
                 const int par = ti[4 * p + 1];
-                const double zr = tz[4 * p], zi = tz[4 * p + 1], jr = J[2 * p], ji = J[2 * p + 1];
-                J[2 * p] = J[2 * par] + zr * jr - zi * ji;
-                J[2 * p + 1] = J[2 * par + 1] + zr * ji + zi * jr;
+                const double zr = tz[4 * p], zi = tz[4 * p + 1];
+                double jr = J[2 * p], ji = J[2 * p + 1], pr = J[2 * par], pi = J[2 * par + 1];
+                if constexpr (ZM == 2) {
+                    const double gr = G[2 * p], gi = G[2 * p + 1];
+                    const double kr = 1.0 - (zr * gr - zi * gi), ki = -(zr * gi + zi * gr);
+                    jr += gr * vs_re - gi * vs_im;
+                    ji += gr * vs_im + gi * vs_re;
+                    const double tr = kr * pr - ki * pi;
+                    pi = kr * pi + ki * pr;
+                    pr = tr;
+                }
+                J[2 * p] = pr + zr * jr - zi * ji;
+                J[2 * p + 1] = pi + zr * ji + zi * jr;
             }
             wave_sync();
         }
-        // V' = w + Z I = w - D; step max |V' - V| per column
+        // V' = w + Z I = w - D (ZM == 2: v_s - D); step max |V' - V| per column
         double dmax = 0.0;
         int bad = 0;
 #pragma unroll
         for (int r = 0; r < B; ++r) {
             const int p = 1 + sl + LPC * r;
             if (p <= n) {
-                const double nr = tz[4 * p + 2] - J[2 * p], ni = tz[4 * p + 3] - J[2 * p + 1];
+                const double wr = ZM == 2 ? vs_re : tz[4 * p + 2], wi = ZM == 2 ? vs_im : tz[4 * p + 3];
+                const double nr = wr - J[2 * p], ni = wi - J[2 * p + 1];
                 const double er = nr - vr[r], ei = ni - vi[r];
                 const double e = er * er + ei * ei;
                 bad |= !(e < HUGE_VAL);
@@ -191,38 +255,48 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
 // (as in the FP32 sweep kernels), and since V' = w - D the new state is simply U' = -D.
 // The injection uses V = w + U; w is added back in FP64 for the output.  The passes run
 // in FP32 (|D| ~ 1e-2 pu keeps their rounding near 1e-9 pu).
-template <typename IO, int CPW, int B, bool ZIP>
+template <typename IO, int CPW, int B, int ZM>
 __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const int32_t *__restrict__ tree_i,
     const double *__restrict__ tree_z, int n, int levels, long long tau, float tol, int max_iter,
-    const double *__restrict__ aP, const double *__restrict__ aI) {
+    const double *__restrict__ aP, const double *__restrict__ aI, const double *__restrict__ aZ, double vs_re,
+    double vs_im) {
     constexpr int LPC = 64 / CPW;
+    constexpr int NZ = ZM == 0 ? 0 : ZM + 1;
     extern __shared__ double lds[];
     const int np = n + 1;
-    double *wd = lds;                                        // [np][2] w in FP64 (outputs)
+    double *wd = lds;                                        // [np][2] w in FP64 (outputs); ZM == 2: v_s
     float *tz = reinterpret_cast<float *>(wd + 2 * np);      // [np][4]: z, w in FP32
-    float *za = tz + 4 * np;                                 // [np][2] (ZIP)
-    float *Jw = za + (ZIP ? 2 * np : 0);                     // [waves][CPW][np][2]
-    int32_t *ti = reinterpret_cast<int32_t *>(Jw + kTreeWaves * CPW * 2 * np);
+    float *za = tz + 4 * np;                                 // [np][NZ]: alpha_P, alpha_I (, alpha_Z)
+    float *Jw = za + NZ * np;                                // [waves][CPW][np][2]
+    float *Gw = Jw + kTreeWaves * CPW * 2 * np;              // ZM == 2: G' per column, as Jw
+    int32_t *ti = reinterpret_cast<int32_t *>(Gw + (ZM == 2 ? kTreeWaves * CPW * 2 * np : 0));
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int slot = lane / LPC, sl = lane % LPC;
+    // the state is the drop U = V - w; with a constant-impedance share w differs per column
+    // (w = -B^-1 c), so the drop is taken from the slack voltage instead
     for (int p = threadIdx.x; p < np; p += kTreeWaves * 64) {
-        wd[2 * p] = tree_z[4 * p + 2];
-        wd[2 * p + 1] = tree_z[4 * p + 3];
+        wd[2 * p] = ZM == 2 ? vs_re : tree_z[4 * p + 2];
+        wd[2 * p + 1] = ZM == 2 ? vs_im : tree_z[4 * p + 3];
     }
-    for (int e = threadIdx.x; e < 4 * np; e += kTreeWaves * 64) tz[e] = (float)tree_z[e];
+    for (int e = threadIdx.x; e < 4 * np; e += kTreeWaves * 64)
+        tz[e] = (ZM == 2 && (e & 3) >= 2) ? (float)((e & 1) ? vs_im : vs_re) : (float)tree_z[e];
     for (int e = threadIdx.x; e < 4 * np + levels + 2; e += kTreeWaves * 64) ti[e] = tree_i[e];
-    if constexpr (ZIP) {
+    if constexpr (ZM >= 1) {
         for (int p = threadIdx.x; p < np; p += kTreeWaves * 64) {
             const int q = tree_i[4 * p];
-            za[2 * p] = q >= 0 ? (float)aP[q] : 0.0f;
-            za[2 * p + 1] = q >= 0 ? (float)aI[q] : 0.0f;
+            za[NZ * p] = q >= 0 ? (float)aP[q] : 0.0f;
+            za[NZ * p + 1] = q >= 0 ? (float)aI[q] : 0.0f;
+            if constexpr (ZM == 2) za[NZ * p + 2] = q >= 0 ? (float)aZ[q] : 0.0f;
         }
     }
     __syncthreads();
     float *J = Jw + (wave * CPW + slot) * 2 * np;
+    float *G = Gw + (wave * CPW + slot) * 2 * np;
+    bool fresh = true;
+    const float vsr = (float)vs_re, vsi = (float)vs_im;
     const int32_t *ls = ti + 4 * np;
     if (sl == 0) J[0] = J[1] = 0.0f;
 
@@ -267,10 +341,42 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
             }
         }
         it = 0;
+        fresh = true;
     };
     load();
     while (__ballot(c < tau)) {
         const bool live = c < tau;
+        if constexpr (ZM == 2) {  // G' of new columns, as in fpi_tree_kernel
+            if (__ballot(fresh)) {
+#pragma unroll
+                for (int r = 0; r < B; ++r) {
+                    const int p = 1 + sl + LPC * r;
+                    if (fresh && p <= n) {
+                        const float az = za[NZ * p + 2];
+                        G[2 * p] = az * sr[r];
+                        G[2 * p + 1] = -az * si[r];
+                    }
+                }
+                wave_sync();
+                for (int L = levels; L >= 1; --L) {
+                    for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
+                        if (!fresh) continue;
+                        float gr = G[2 * p], gi = G[2 * p + 1];
+                        for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
+                            gr += G[2 * ch];
+                            gi += G[2 * ch + 1];
+                        }
+                        const float dr = 1.0f + tz[4 * p] * gr - tz[4 * p + 1] * gi;
+                        const float di = tz[4 * p] * gi + tz[4 * p + 1] * gr;
+                        const float dd = 1.0f / (dr * dr + di * di);
+                        G[2 * p] = (gr * dr + gi * di) * dd;
+                        G[2 * p + 1] = (gi * dr - gr * di) * dd;
+                    }
+                    wave_sync();
+                }
+                fresh = false;
+            }
+        }
 #pragma unroll
         for (int r = 0; r < B; ++r) {
             const int p = 1 + sl + LPC * r;
@@ -278,8 +384,8 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
                 const float vr = tz[4 * p + 2] + ur[r], vi = tz[4 * p + 3] + ui[r];
                 const float inv = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
                 float ir = (sr[r] * vr + si[r] * vi) * inv, ii = (sr[r] * vi - si[r] * vr) * inv;
-                if constexpr (ZIP) {
-                    const float ap = za[2 * p], ai = za[2 * p + 1];
+                if constexpr (ZM >= 1) {
+                    const float ap = za[NZ * p], ai = za[NZ * p + 1];
                     ir = ap * ir + ai * sr[r];
                     ii = ap * ii - ai * si[r];
                 }
@@ -295,6 +401,13 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
                     jr += J[2 * ch];
                     ji += J[2 * ch + 1];
                 }
+                if constexpr (ZM == 2) {
+                    const float kr = 1.0f - (tz[4 * p] * G[2 * p] - tz[4 * p + 1] * G[2 * p + 1]);
+                    const float ki = -(tz[4 * p] * G[2 * p + 1] + tz[4 * p + 1] * G[2 * p]);
+                    const float tr = kr * jr - ki * ji;
+                    ji = kr * ji + ki * jr;
+                    jr = tr;
+                }
                 J[2 * p] = jr;
                 J[2 * p + 1] = ji;
             }
@@ -303,9 +416,19 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
         for (int L = 1; L <= levels; ++L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
                 const int par = ti[4 * p + 1];
-                const float zr = tz[4 * p], zi = tz[4 * p + 1], jr = J[2 * p], ji = J[2 * p + 1];
-                J[2 * p] = J[2 * par] + zr * jr - zi * ji;
-                J[2 * p + 1] = J[2 * par + 1] + zr * ji + zi * jr;
+                const float zr = tz[4 * p], zi = tz[4 * p + 1];
+                float jr = J[2 * p], ji = J[2 * p + 1], pr = J[2 * par], pi = J[2 * par + 1];
+                if constexpr (ZM == 2) {
+                    const float gr = G[2 * p], gi = G[2 * p + 1];
+                    const float kr = 1.0f - (zr * gr - zi * gi), ki = -(zr * gi + zi * gr);
+                    jr += gr * vsr - gi * vsi;
+                    ji += gr * vsi + gi * vsr;
+                    const float tr = kr * pr - ki * pi;
+                    pi = kr * pi + ki * pr;
+                    pr = tr;
+                }
+                J[2 * p] = pr + zr * jr - zi * ji;
+                J[2 * p + 1] = pi + zr * ji + zi * jr;
             }
             wave_sync();
         }
@@ -352,14 +475,14 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
     }
 }
 
-template <typename IO, int CPW, int B, bool ZIP>
+template <typename IO, int CPW, int B, int ZM>
 int launch32_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
                 const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
     const int n = net.n, np = n + 1, levels = dn.tree_levels;
-    const size_t lds = (size_t)2 * np * 8 + (size_t)4 * np * 4 + (ZIP ? (size_t)2 * np * 4 : 0) +
-                       (size_t)kTreeWaves * CPW * 2 * np * 4 + (size_t)(4 * np + levels + 2) * 4;
+    const size_t lds = (size_t)2 * np * 8 + (size_t)4 * np * 4 + (size_t)(ZM ? ZM + 1 : 0) * np * 4 +
+                       (size_t)(ZM == 2 ? 2 : 1) * kTreeWaves * CPW * 2 * np * 4 + (size_t)(4 * np + levels + 2) * 4;
     if (lds > (size_t)160 * 1024) return fail(TPF_ERR_UNSUPPORTED, "tree operator: network too large for LDS");
-    auto k = fpi_tree32_kernel<IO, CPW, B, ZIP>;
+    auto k = fpi_tree32_kernel<IO, CPW, B, ZM>;
     if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
     int per_cu = 0;
@@ -373,15 +496,17 @@ int launch32_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, in
         std::max<long long>(1, std::min<long long>((long long)cus * per_cu, (tau + per_block - 1) / per_block));
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTreeWaves * 64), lds, st, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.tree_i, dn.tree_z, n, levels, (long long)tau, (float)tol, max_iter,
-                       (const double *)dn.aP, (const double *)dn.aI);
+                       (const double *)dn.aP, (const double *)dn.aI, (const double *)dn.aZ, net.vs.real(),
+                       net.vs.imag());
     return TPF_OK;
 }
 
 template <typename IO, int CPW, int B>
 int launch32_b(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
                const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
-    if (dn.aP) return launch32_as<IO, CPW, B, true>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    return launch32_as<IO, CPW, B, false>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (dn.aZ) return launch32_as<IO, CPW, B, 2>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (dn.aP) return launch32_as<IO, CPW, B, 1>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    return launch32_as<IO, CPW, B, 0>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
 }
 
 // The FP32 form takes 4 columns of 16 lanes up to 128 PQ buses: with half the FP64
@@ -814,14 +939,14 @@ int launch3_io(const tpf_network_s &net, const DeviceNet &dn, const void *S, int
     return fail(TPF_ERR_UNSUPPORTED, "tree operator: up to 512 three-phase buses");
 }
 
-template <typename IO, int CPW, int B, bool ZIP>
+template <typename IO, int CPW, int B, int ZM>
 int launch_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
               const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
     const int n = net.n, np = n + 1, levels = dn.tree_levels;
-    const size_t lds = (size_t)4 * np * 8 + (ZIP ? (size_t)2 * np * 8 : 0) + (size_t)kTreeWaves * CPW * 2 * np * 8 +
-                       (size_t)(4 * np + levels + 2) * 4;
+    const size_t lds = (size_t)4 * np * 8 + (size_t)(ZM ? ZM + 1 : 0) * np * 8 +
+                       (size_t)(ZM == 2 ? 2 : 1) * kTreeWaves * CPW * 2 * np * 8 + (size_t)(4 * np + levels + 2) * 4;
     if (lds > (size_t)160 * 1024) return fail(TPF_ERR_UNSUPPORTED, "tree operator: network too large for LDS");
-    auto k = fpi_tree_kernel<IO, CPW, B, ZIP>;
+    auto k = fpi_tree_kernel<IO, CPW, B, ZM>;
     if (hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
     int per_cu = 0;
@@ -835,15 +960,17 @@ int launch_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int6
         std::max<long long>(1, std::min<long long>((long long)cus * per_cu, (tau + per_block - 1) / per_block));
     hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(kTreeWaves * 64), lds, st, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.tree_i, dn.tree_z, n, levels, (long long)tau, tol, max_iter,
-                       (const double *)dn.aP, (const double *)dn.aI);
+                       (const double *)dn.aP, (const double *)dn.aI, (const double *)dn.aZ, net.vs.real(),
+                       net.vs.imag());
     return TPF_OK;
 }
 
 template <typename IO, int CPW, int B>
 int launch_b(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
              const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
-    if (dn.aP) return launch_as<IO, CPW, B, true>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
-    return launch_as<IO, CPW, B, false>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (dn.aZ) return launch_as<IO, CPW, B, 2>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    if (dn.aP) return launch_as<IO, CPW, B, 1>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    return launch_as<IO, CPW, B, 0>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
 }
 
 // Columns per wavefront: 8 (8 lanes each) up to 128 buses, 2 up to 256, then 1.  (At 99

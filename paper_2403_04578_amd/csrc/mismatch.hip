@@ -25,16 +25,20 @@ struct MismatchArgs {
     const double *yval;  // [nnz][2]
     const double *cval;  // [n][2]
     const double *aI, *aP;  // ZIP shares [n], or NULL for constant-power loads
+    const double *aZ;       // constant-impedance share [n], or NULL
     double *out;         // [tau]
 };
 
-// The power a load draws: S for constant power, S (alpha_P + alpha_I V) for ZIP loads.
+// The power a load draws: S for constant power, S (alpha_P + alpha_I V + alpha_Z |V|^2)
+// for ZIP loads (the constant-impedance current alpha_Z S* V draws alpha_Z S |V|^2).
 __device__ __forceinline__ void load_power(const MismatchArgs &mm, int b, double sr, double si, double vr, double vi,
                                            double &lr, double &li) {
     lr = sr;
     li = si;
     if (mm.aP) {
-        const double ap = mm.aP[b], ai = mm.aI[b];
+        double ap = mm.aP[b];
+        const double ai = mm.aI[b];
+        if (mm.aZ) ap += mm.aZ[b] * (vr * vr + vi * vi);
         lr = sr * ap + ai * (sr * vr - si * vi);
         li = si * ap + ai * (sr * vi + si * vr);
     }
@@ -216,7 +220,7 @@ int launch_io(const MismatchArgs &mm, int nnz, const void *S, const void *V, int
 
 int launch_mismatch_f64(const tpf_network_s &net, const DeviceNet &dn, const void *S, const void *V, int dtype,
                         int64_t tau, double *out, hipStream_t stream) {
-    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, dn.aI, dn.aP, out};
+    const MismatchArgs mm{dn.rowptr, dn.colidx, dn.yval, dn.cval, dn.aI, dn.aP, dn.aZ, out};
     const int nnz = (int)net.colidx.size();
     if (dtype == TPF_C128) return launch_io<double>(mm, nnz, S, V, net.n, tau, stream);
     return launch_io<float>(mm, nnz, S, V, net.n, tau, stream);

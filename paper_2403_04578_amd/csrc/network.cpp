@@ -302,6 +302,11 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
         double zs = 0.0;
         for (int q = 0; q < n; ++q) zs = std::max(zs, std::fabs(net.alpha_p[q]) + std::fabs(net.alpha_i[q]));
         dn.zscale = (float)zs;
+        if (!net.alpha_z.empty()) {
+            if (!dalloc((void **)&dn.aZ, n * 8)) return fail(TPF_ERR_OOM, "device allocation failed (ZIP shares)");
+            if (!h2d(dn.aZ, net.alpha_z.data(), n * 8))
+                return fail(TPF_ERR_DEVICE, "host-to-device copy failed (ZIP shares)");
+        }
     }
     return TPF_OK;
 }
@@ -683,13 +688,11 @@ extern "C" int tpf_build_network_zip(int32_t n_bus, int32_t n_branch, const int3
     if (n_bus < 2) return fail(TPF_ERR_INVALID_ARG, "n_bus must be >= 2");
     if (!alpha_i || !alpha_p) return fail(TPF_ERR_INVALID_ARG, "alpha_i and alpha_p must not be NULL");
     const int n = n_bus - 1;
+    bool any_z = false;
     for (int q = 0; q < n; ++q) {
         if (!std::isfinite(alpha_i[q]) || !std::isfinite(alpha_p[q]) || (alpha_z && !std::isfinite(alpha_z[q])))
             return fail(TPF_ERR_INVALID_ARG, "ZIP share of PQ bus " + std::to_string(q) + " not finite");
-        if (alpha_z && alpha_z[q] != 0.0)
-            return fail(TPF_ERR_UNSUPPORTED,
-                        "a constant-impedance share makes B = diag(alpha_Z s*) + Y_dd, hence F and w, differ per "
-                        "power flow; only alpha_z = 0 is supported");
+        any_z |= alpha_z && alpha_z[q] != 0.0;
     }
     tpf_network net = nullptr;
     const int rc = tpf_build_network(n_bus, n_branch, from, to, r, x, slack_bus, vs_re, vs_im, &net);
@@ -697,6 +700,7 @@ extern "C" int tpf_build_network_zip(int32_t n_bus, int32_t n_branch, const int3
     try {
         net->alpha_i.assign(alpha_i, alpha_i + n);
         net->alpha_p.assign(alpha_p, alpha_p + n);
+        if (any_z) net->alpha_z.assign(alpha_z, alpha_z + n);
     } catch (...) {
         tpf_free_network(net);
         return fail(TPF_ERR_OOM, "host allocation failed");

@@ -70,7 +70,7 @@ struct DeviceNet {
     int32_t *colidx = nullptr;   // [nnz]
     double *yval = nullptr;      // [nnz][2]
     double *cval = nullptr;      // [n][2]
-    // ZIP load shares per PQ bus (Eq. (2), alpha_Z = 0); NULL for constant-power loads.
+    // ZIP load shares per PQ bus (Eq. (2)); NULL for constant-power loads.
     // Radial networks, tree operator (fpi_tree.hip): breadth-first positions 0..n_bus-1
     // (0 = slack).  tree_i = [pq bus][parent][first child][end of children] per position
     // (4 n_bus int32) then the level starts (tree_levels + 2 int32); tree_z = per position
@@ -80,6 +80,7 @@ struct DeviceNet {
     int32_t *tree_i = nullptr;
     double *tree_z = nullptr;
     double *aI = nullptr, *aP = nullptr;  // [n] each
+    double *aZ = nullptr;                 // [n], only when some alpha_Z != 0 (tree operator)
     float zscale = 1.0f;                  // max_b |alpha_P| + |alpha_I| (bounds |I| / |S| with |V|)
     std::vector<void *> owned;   // every allocation above, freed with the network
 };
@@ -107,10 +108,12 @@ struct tpf_network_s {
     std::vector<int32_t> rowptr, colidx;
     std::vector<tpf::cd> yval;
     std::vector<tpf::cd> c;
-    // ZIP loads (Eq. (2)) with alpha_Z = 0: shares of constant current and constant power
-    // per PQ bus; empty for constant-power loads.
+    // ZIP loads (Eq. (2)): shares of constant current and constant power per PQ bus; empty
+    // for constant-power loads.  alpha_z (constant impedance) is empty unless some share
+    // is non-zero: then B = diag(alpha_Z s*) + Y_dd differs per column, which only the
+    // tree operator solves (per column, without forming B^-1).
     bool zip = false;
-    std::vector<double> alpha_i, alpha_p;
+    std::vector<double> alpha_i, alpha_p, alpha_z;
     // Breadth-first tree of a radial single-phase network (empty otherwise): per position
     // p = 0..n (0 = slack) the PQ index, parent position, children range and the impedance
     // of the branch from the parent; level starts.  Children of a position are

@@ -130,8 +130,8 @@ def test_workspace_sizes_by_path():
 
 
 def test_zip_network_build_and_errors():
-    """Eq. (2) ZIP loads: Z and w do not depend on the shares; a constant-impedance share
-    is refused (it makes F and w differ per power flow); shares must be finite."""
+    """Eq. (2) ZIP loads: Z and w do not depend on the shares (a constant-impedance share
+    included: it enters each column's B, not the network's Z); shares must be finite."""
     f = W.make_feeder(20, seed=3)
     n = f.n_bus - 1
     plain = tpf.Network.from_feeder(f)
@@ -141,7 +141,10 @@ def test_zip_network_build_and_errors():
     Z1, w1 = z.zw()
     assert np.array_equal(Z0, Z1) and np.array_equal(w0, w1)
     tpf.Network.from_feeder(f, alpha_i=0.2, alpha_p=0.8, alpha_z=0.0)  # an all-zero alpha_z is accepted
-    for kw, code in [(dict(alpha_i=0.2, alpha_p=0.7, alpha_z=0.1), tpf.TPF_ERR_UNSUPPORTED),
+    zz = tpf.Network.from_feeder(f, alpha_i=0.2, alpha_p=0.7, alpha_z=0.1)
+    Z2, w2 = zz.zw()
+    assert np.array_equal(Z0, Z2) and np.array_equal(w0, w2)
+    for kw, code in [(dict(alpha_i=0.2, alpha_p=0.7, alpha_z=np.nan), tpf.TPF_ERR_INVALID_ARG),
                      (dict(alpha_i=np.nan, alpha_p=1.0), tpf.TPF_ERR_INVALID_ARG),
                      (dict(alpha_i=0.0, alpha_p=np.inf), tpf.TPF_ERR_INVALID_ARG)]:
         with pytest.raises(tpf.TpfError) as e:

@@ -1,0 +1,142 @@
+"""GPU parity of Eq. (2) with a constant-impedance ZIP share (B = diag(alpha_Z s*) + Y_dd
+per column) against the oracle, which eliminates each column's [B | c | A]: the tree
+modes on radial single-phase feeders from 49 to 699 PQ buses (every launch shape of the
+tree kernels), complex128 and complex64 loads, start voltages, edge columns, the ZIP
+power-balance mismatch with its alpha_Z |V|^2 term, and the dense modes' refusal.
+
+Bounds: TREE_FP64 follows the oracle's iteration exactly, so columns with the oracle's
+sweep count agree to 1e-9 pu (a column whose last step sits on the tolerance may stop one
+sweep apart and is re-run on the oracle with that count); TREE_FP32 meets the 1e-6 pu
+fast-form contract against a 1e-10 oracle solution.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2403_04578_amd as tpf
+from paper_2403_04578_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP64 = 1e-9
+FAST_BOUND = 1e-6
+
+
+def _dev(S, gpu, dtype=torch.complex128):
+    return torch.from_numpy(np.ascontiguousarray(S)).to(gpu).to(dtype).contiguous()
+
+
+def _shares(n, seed):
+    """Seeded per-bus (alpha_Z, alpha_I, alpha_P) summing to one."""
+    sh = np.random.default_rng(seed).dirichlet([1.0, 1.0, 2.0], n)
+    return sh[:, 0].copy(), sh[:, 1].copy(), sh[:, 2].copy()
+
+
+def _setup(n_bus, seed=7):
+    f = W.make_feeder(n_bus)
+    az, ai, ap = _shares(n_bus - 1, seed)
+    net = tpf.Network.from_feeder(f, alpha_i=ai, alpha_p=ap, alpha_z=az)
+    return f, net, oracle.build_feeder(f), (az, ai, ap)
+
+
+def _compare(onet, S, sh, V, it, st, tol, max_iter, bound, V0=None):
+    az, ai, ap = sh
+    ref = oracle.fpi_zip(onet, S, ai, ap, tol, max_iter, V0=V0, alpha_z=az)
+    Vg = V.cpu().numpy().astype(np.complex128).reshape(ref.V.shape)
+    ig, sg = it.cpu().numpy(), st.cpu().numpy()
+    same = ig == ref.iters
+    assert np.sum(~same) <= max(2, 0.002 * len(same)), f"sweep counts differ on {np.sum(~same)} columns"
+    assert np.array_equal(sg[same], ref.status[same])
+    err = np.abs(Vg[same] - ref.V[same]).max(initial=0.0)
+    assert err <= bound, f"max |dV| = {err:.3e}"
+    for c in np.nonzero(~same)[0]:
+        assert abs(int(ig[c]) - int(ref.iters[c])) <= 1
+        r2 = oracle.fpi_zip(onet, S[c:c + 1], ai, ap, 0.0, int(ig[c]),
+                            V0=None if V0 is None else V0[c:c + 1], alpha_z=az)
+        assert np.abs(Vg[c] - r2.V[0]).max() <= bound
+    return Vg
+
+
+def _mm_rounding(onet):
+    return 16 * 2.0 ** -52 * float(np.abs(onet.Ydd).sum(axis=1).max())
+
+
+@pytest.mark.parametrize("n_bus,T", [(50, 300), (100, 200), (200, 60), (400, 24), (700, 6)])
+def test_zipz_tree_fp64_every_column(gpu, n_bus, T):
+    f, net, onet, sh = _setup(n_bus)
+    S = W.profile_minute_year(f, steps=T, t0=4321)
+    V, it, st, mm = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-9, max_iter=100, mode="tree_fp64", mismatch=True)
+    assert int(st.max()) == tpf.ST_CONVERGED
+    Vg = _compare(onet, S, sh, V, it, st, 1e-9, 100, TOL_FP64)
+    # the ZIP balance with the alpha_Z |V|^2 term, against the oracle's on the same voltages
+    ref_mm = oracle.mismatch_zip(onet, S, Vg, sh[1], sh[2], alpha_z=sh[0])
+    g = mm.cpu().numpy()
+    assert np.all(np.abs(g - ref_mm) <= _mm_rounding(onet) + 1e-9 * ref_mm)
+    assert g.max() < 1e-6
+
+
+@pytest.mark.parametrize("n_bus,T", [(50, 300), (100, 200), (400, 24), (700, 6)])
+def test_zipz_tree_fp32(gpu, n_bus, T):
+    f, net, onet, sh = _setup(n_bus, seed=8)
+    S = W.profile_minute_year(f, steps=T, t0=99)
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-6, max_iter=100, mode="tree_fp32")
+    assert int(st.max()) == tpf.ST_CONVERGED
+    ref = oracle.fpi_zip(onet, S, sh[1], sh[2], 1e-10, 200, alpha_z=sh[0])
+    assert np.abs(V.cpu().numpy() - ref.V).max() <= FAST_BOUND
+
+
+def test_zipz_shares_move_the_solution(gpu):
+    """The constant-impedance share is honoured: moving it into the constant-current share
+    changes the solution well beyond the tolerance, on both sides alike."""
+    f, net, onet, (az, ai, ap) = _setup(100)
+    S = W.profile_minute_year(f, steps=40, t0=600)
+    V1 = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-10, max_iter=100, mode="tree_fp64")[0].cpu().numpy()
+    net2 = tpf.Network.from_feeder(f, alpha_i=ai + az, alpha_p=ap)
+    V2 = tpf.solve_timeseries(net2, _dev(S, gpu), tol=1e-10, max_iter=100, mode="tree_fp64")[0].cpu().numpy()
+    assert np.abs(V1 - V2).max() > 1e-6
+    r2 = oracle.fpi_zip(onet, S, ai + az, ap, 1e-10, 100)
+    assert np.abs(V2 - r2.V).max() < 1e-9
+
+
+def test_zipz_complex64_start_and_edges(gpu):
+    f, net, onet, sh = _setup(100, seed=9)
+    az, ai, ap = sh
+    S = W.profile_minute_year(f, steps=64, t0=12345)
+    ref = oracle.fpi_zip(onet, S, ai, ap, 1e-12, 100, alpha_z=az)
+    # complex64 loads and outputs
+    S32 = S.astype(np.complex64)
+    V, it, st = tpf.solve_timeseries(net, _dev(S32, gpu, torch.complex64), tol=1e-9, max_iter=100, mode="tree_fp64")
+    assert V.dtype == torch.complex64
+    r32 = oracle.fpi_zip(onet, S32.astype(np.complex128), ai, ap, 1e-12, 100, alpha_z=az)
+    assert np.abs(V.cpu().numpy().astype(np.complex128) - r32.V).max() <= 1e-9 + 1.2e-7
+    # start voltages: the oracle from the same start
+    V0 = ref.V + 1e-3 * np.exp(1j * np.arange(S.size).reshape(S.shape))
+    V, it, st = tpf.solve_timeseries(net, _dev(S, gpu), tol=1e-9, max_iter=100, mode="tree_fp64",
+                                     V0=_dev(V0, gpu))
+    _compare(onet, S, sh, V, it, st, 1e-9, 100, TOL_FP64, V0=V0)
+    # a NaN load ends NONFINITE; a zero-load column stays at the flat start, the slack
+    # voltage, so its first sweep does not move
+    Se = S[:4].copy()
+    Se[1, 5] = np.nan
+    Se[2] = 0.0
+    V, it, st = tpf.solve_timeseries(net, _dev(Se, gpu), tol=1e-9, max_iter=100, mode="tree_fp64")
+    st, it = st.cpu().numpy(), it.cpu().numpy()
+    assert list(st) == [0, 2, 0, 0]
+    assert it[2] == 1 and np.abs(V[2].cpu().numpy() - onet.vs).max() < 1e-14
+    for mode in ("tree_fp64", "tree_fp32"):
+        V, it, st = tpf.solve_timeseries(net, _dev(Se, gpu), tol=1e-6, max_iter=1, mode=mode)
+        assert int(st[0]) == tpf.ST_MAX_ITER and int(it[0]) == 1
+        r1 = oracle.fpi_zip(onet, S[:1], ai, ap, 0.0, 1, alpha_z=az)
+        assert np.abs(V[0].cpu().numpy() - r1.V[0]).max() < (1e-12 if mode == "tree_fp64" else 1e-6)
+
+
+@pytest.mark.parametrize("mode", ["fp64", "fp32", "mixed_bf16", "mixed_fp16"])
+def test_zipz_dense_modes_refuse(gpu, mode):
+    f, net, onet, sh = _setup(60)
+    S = _dev(W.profile_minute_year(f, steps=4), gpu)
+    with pytest.raises(tpf.TpfError) as e:
+        tpf.solve_timeseries(net, S, tol=1e-6, max_iter=50, mode=mode)
+    assert e.value.code == tpf.TPF_ERR_UNSUPPORTED
+    V, it, st = tpf.solve_timeseries(net, S, tol=1e-6, max_iter=0, mode=mode)  # the start still returns
+    assert int(it.max()) == 0 and np.allclose(V.cpu().numpy(), 1.0)
