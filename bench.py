@@ -224,7 +224,8 @@ def bench_other(args):
         S = torch.from_numpy(S_host).to(dev)
         ai, ap = W.zip_shares(f.n_bus - 1)
         desc = ("100-bus radial feeder (99 PQ), ZIP loads (per bus constant-current share U(0, 0.6), the rest "
-                "constant power), 525,600 one-minute steps, complex128 S")
+                "constant power; the *_alpha_z forms: constant-impedance U(0, 0.4), constant-current U(0, 0.4), "
+                "the rest constant power), 525,600 one-minute steps, complex128 S")
         sample = lambda idx: S_host[idx]
     else:
         f = W.make_feeder(1000)
@@ -258,6 +259,11 @@ def bench_other(args):
     runs = [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16", "tree_fp64", "tree_fp32")]
     if zip_loads:
         runs.append(("fp64_constant_power", "fp64", tpf.Network.from_feeder(f)))
+        # a constant-impedance share as well (B differs per column): the tree forms
+        az, zi, zp = W.zipz_shares(f.n_bus - 1)
+        netz = tpf.Network.from_feeder(f, alpha_i=zi, alpha_p=zp, alpha_z=az)
+        runs += [("tree_fp64_alpha_z", "tree_fp64", netz), ("tree_fp32_alpha_z", "tree_fp32", netz)]
+        V_err_z = oracle.fpi_zip(onet, S_err, zi, zp, 1e-10, 200, alpha_z=az).V
     for key, mode, net in runs:
         out = tpf.alloc_outputs(net, S, mode, mismatch=True)
         kout = (out[0], out[1], out[2], None, out[4])  # same buffers, no mismatch pass
@@ -286,7 +292,8 @@ def bench_other(args):
                        "solve_hbm_gbs": 2.0 * esz * n * T / (k_ms * 1e-3) / 1e9}
         if key != "fp64_constant_power":  # the constant-power run solves other loads than the ZIP oracle
             forms[key]["max_err_vs_oracle_sample_pu"] = float(
-                np.abs(out[0][ti_err].cpu().numpy().astype(np.complex128) - V_err).max())
+                np.abs(out[0][ti_err].cpu().numpy().astype(np.complex128) -
+                       (V_err_z if key.endswith("_alpha_z") else V_err)).max())
         del out, kout
         torch.cuda.empty_cache()
     base = forms["fp64"]

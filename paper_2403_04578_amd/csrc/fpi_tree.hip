@@ -110,41 +110,6 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
     load();
     while (__ballot(c < tau)) {
         const bool live = c < tau;
-        if constexpr (ZM == 2) {
-            // a constant-impedance share (Eq. (2), B = diag(alpha_Z s*) + Y_dd) makes each
-            // subtree a Norton load G x + J seen from its parent: G_b = y_b + sum over the
-            // children of G'_c with y_b = alpha_Z s_b* and G'_b = G_b / (1 + z_b G_b), which
-            // depends on the column's s only.  Formed once per column, slot by slot.
-            if (__ballot(fresh)) {
-#pragma unroll
-                for (int r = 0; r < B; ++r) {
-                    const int p = 1 + sl + LPC * r;
-                    if (fresh && p <= n) {
-                        const double az = za[NZ * p + 2];
-                        G[2 * p] = az * sr[r];
-                        G[2 * p + 1] = -az * si[r];
-                    }
-                }
-                wave_sync();
-                for (int L = levels; L >= 1; --L) {
-                    for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
-                        if (!fresh) continue;
-                        double gr = G[2 * p], gi = G[2 * p + 1];
-                        for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
-                            gr += G[2 * ch];
-                            gi += G[2 * ch + 1];
-                        }
-                        const double dr = 1.0 + tz[4 * p] * gr - tz[4 * p + 1] * gi;
-                        const double di = tz[4 * p] * gi + tz[4 * p + 1] * gr;
-                        const double dd = 1.0 / (dr * dr + di * di);
-                        G[2 * p] = (gr * dr + gi * di) * dd;
-                        G[2 * p + 1] = (gi * dr - gr * di) * dd;
-                    }
-                    wave_sync();
-                }
-                fresh = false;
-            }
-        }
         // injections conj(S./V) (ZIP: alpha_P conj(S./V) + alpha_I conj(S)) into J
 #pragma unroll
         for (int r = 0; r < B; ++r) {
@@ -159,12 +124,21 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
                 }
                 J[2 * p] = ir;
                 J[2 * p + 1] = ii;
+                if (ZM == 2 && fresh) {  // y_b = alpha_Z s_b*, the start of G_b
+                    const double az = za[NZ * p + 2];
+                    G[2 * p] = az * sr[r];
+                    G[2 * p + 1] = -az * si[r];
+                }
             }
         }
         wave_sync();
-        // backward pass, deepest level first: J_b += J of b's children (ZM == 2: the
-        // branch current's source part J'_b = k_b (I_b + sum of the children's J'),
-        // k_b = 1 / (1 + z_b G_b) = 1 - z_b G'_b)
+        // backward pass, deepest level first: J_b += J of b's children.  ZM == 2: a
+        // constant-impedance share (Eq. (2), B = diag(alpha_Z s*) + Y_dd) makes each subtree
+        // a Norton load G x + J seen from its parent, with G_b = y_b + sum of the
+        // children's G'_c and G'_b = G_b / (1 + z_b G_b), which depend on the column's s
+        // only: formed in the first sweep of a column and kept.  The branch current's
+        // source part is J'_b = k_b (I_b + sum of the children's J'), k_b = 1 / (1 + z_b G_b)
+        // = 1 - z_b G'_b.
         for (int L = levels; L >= 1; --L) {
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
                 double jr = J[2 * p], ji = J[2 * p + 1];
@@ -173,6 +147,18 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
                     ji += J[2 * ch + 1];
                 }
                 if constexpr (ZM == 2) {
+                    if (fresh) {
+                        double gr = G[2 * p], gi = G[2 * p + 1];
+                        for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
+                            gr += G[2 * ch];
+                            gi += G[2 * ch + 1];
+                        }
+                        const double dr = 1.0 + tz[4 * p] * gr - tz[4 * p + 1] * gi;
+                        const double di = tz[4 * p] * gi + tz[4 * p + 1] * gr;
+                        const double dd = 1.0 / (dr * dr + di * di);
+                        G[2 * p] = (gr * dr + gi * di) * dd;
+                        G[2 * p + 1] = (gi * dr - gr * di) * dd;
+                    }
                     const double kr = 1.0 - (tz[4 * p] * G[2 * p] - tz[4 * p + 1] * G[2 * p + 1]);
                     const double ki = -(tz[4 * p] * G[2 * p + 1] + tz[4 * p + 1] * G[2 * p]);
                     const double tr = kr * jr - ki * ji;
@@ -206,6 +192,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree_kernel(
             }
             wave_sync();
         }
+        fresh = false;
         // V' = w + Z I = w - D (ZM == 2: v_s - D); step max |V' - V| per column
         double dmax = 0.0;
         int bad = 0;
@@ -346,37 +333,6 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
     load();
     while (__ballot(c < tau)) {
         const bool live = c < tau;
-        if constexpr (ZM == 2) {  // G' of new columns, as in fpi_tree_kernel
-            if (__ballot(fresh)) {
-#pragma unroll
-                for (int r = 0; r < B; ++r) {
-                    const int p = 1 + sl + LPC * r;
-                    if (fresh && p <= n) {
-                        const float az = za[NZ * p + 2];
-                        G[2 * p] = az * sr[r];
-                        G[2 * p + 1] = -az * si[r];
-                    }
-                }
-                wave_sync();
-                for (int L = levels; L >= 1; --L) {
-                    for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
-                        if (!fresh) continue;
-                        float gr = G[2 * p], gi = G[2 * p + 1];
-                        for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
-                            gr += G[2 * ch];
-                            gi += G[2 * ch + 1];
-                        }
-                        const float dr = 1.0f + tz[4 * p] * gr - tz[4 * p + 1] * gi;
-                        const float di = tz[4 * p] * gi + tz[4 * p + 1] * gr;
-                        const float dd = 1.0f / (dr * dr + di * di);
-                        G[2 * p] = (gr * dr + gi * di) * dd;
-                        G[2 * p + 1] = (gi * dr - gr * di) * dd;
-                    }
-                    wave_sync();
-                }
-                fresh = false;
-            }
-        }
 #pragma unroll
         for (int r = 0; r < B; ++r) {
             const int p = 1 + sl + LPC * r;
@@ -391,10 +347,15 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
                 }
                 J[2 * p] = ir;
                 J[2 * p + 1] = ii;
+                if (ZM == 2 && fresh) {
+                    const float az = za[NZ * p + 2];
+                    G[2 * p] = az * sr[r];
+                    G[2 * p + 1] = -az * si[r];
+                }
             }
         }
         wave_sync();
-        for (int L = levels; L >= 1; --L) {
+        for (int L = levels; L >= 1; --L) {  // as in fpi_tree_kernel
             for (int p = ls[L] + sl; p < ls[L + 1]; p += LPC) {
                 float jr = J[2 * p], ji = J[2 * p + 1];
                 for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
@@ -402,6 +363,18 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
                     ji += J[2 * ch + 1];
                 }
                 if constexpr (ZM == 2) {
+                    if (fresh) {
+                        float gr = G[2 * p], gi = G[2 * p + 1];
+                        for (int ch = ti[4 * p + 2]; ch < ti[4 * p + 3]; ++ch) {
+                            gr += G[2 * ch];
+                            gi += G[2 * ch + 1];
+                        }
+                        const float dr = 1.0f + tz[4 * p] * gr - tz[4 * p + 1] * gi;
+                        const float di = tz[4 * p] * gi + tz[4 * p + 1] * gr;
+                        const float dd = 1.0f / (dr * dr + di * di);
+                        G[2 * p] = (gr * dr + gi * di) * dd;
+                        G[2 * p + 1] = (gi * dr - gr * di) * dd;
+                    }
                     const float kr = 1.0f - (tz[4 * p] * G[2 * p] - tz[4 * p + 1] * G[2 * p + 1]);
                     const float ki = -(tz[4 * p] * G[2 * p + 1] + tz[4 * p + 1] * G[2 * p]);
                     const float tr = kr * jr - ki * ji;
@@ -432,6 +405,7 @@ __global__ __launch_bounds__(kTreeWaves * 64) void fpi_tree32_kernel(
             }
             wave_sync();
         }
+        fresh = false;
         float dmax = 0.0f;
         int bad = 0;
 #pragma unroll
@@ -504,6 +478,8 @@ int launch32_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, in
 template <typename IO, int CPW, int B>
 int launch32_b(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
                const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
+    // (the FP32 state is half the size: the shape of launch_b's halving measured slower here,
+    // 1.19 against 1.02 ms on the 100-bus year)
     if (dn.aZ) return launch32_as<IO, CPW, B, 2>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     if (dn.aP) return launch32_as<IO, CPW, B, 1>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     return launch32_as<IO, CPW, B, 0>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
@@ -968,7 +944,15 @@ int launch_as(const tpf_network_s &net, const DeviceNet &dn, const void *S, int6
 template <typename IO, int CPW, int B>
 int launch_b(const tpf_network_s &net, const DeviceNet &dn, const void *S, int64_t tau, double tol, int max_iter,
              const void *V0, void *V, int32_t *iters, int8_t *status, hipStream_t st) {
-    if (dn.aZ) return launch_as<IO, CPW, B, 2>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    // a constant-impedance share doubles the per-column LDS state (G' beside J): half the
+    // columns per wavefront, each over twice the lanes, keeps the workgroups per CU (100-bus
+    // year with alpha_Z: 2.00 ms against 2.74 ms with the constant-power shape)
+    if (dn.aZ) {
+        if constexpr (CPW >= 2)
+            return launch_as<IO, CPW / 2, B / 2, 2>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+        else
+            return launch_as<IO, CPW, B, 2>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
+    }
     if (dn.aP) return launch_as<IO, CPW, B, 1>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
     return launch_as<IO, CPW, B, 0>(net, dn, S, tau, tol, max_iter, V0, V, iters, status, st);
 }

@@ -269,6 +269,15 @@ def zip_shares(n_pq: int, seed: int = SEED_ZIP, max_current: float = 0.6):
     return ai, 1.0 - ai
 
 
+def zipz_shares(n_pq: int, seed: int = SEED_ZIP, max_impedance: float = 0.4, max_current: float = 0.4):
+    """Seeded ZIP shares with a constant-impedance part: alpha_Z ~ U(0, max_impedance),
+    alpha_I ~ U(0, max_current), alpha_P = 1 - alpha_Z - alpha_I per PQ bus."""
+    rng = np.random.default_rng(seed + 1)
+    az = rng.uniform(0.0, max_impedance, n_pq)
+    ai = rng.uniform(0.0, max_current, n_pq)
+    return az, ai, 1.0 - az - ai
+
+
 def mlp_sizes(n_pq: int, hidden: int = 256, layers: int = 3):
     """Layer widths of the warm-start network: 2 n + 4 inputs, `layers` hidden layers, 2 n outputs."""
     return [2 * n_pq + 4] + [hidden] * layers + [2 * n_pq]
