@@ -239,59 +239,89 @@ __device__ __forceinline__ void post_done(int *done_flag, int seq) {
     if (done_flag) __hip_atomic_store(done_flag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// One wave per active column: convergence test (Eq. (3)), retirement, and for a column
-// that stays active its place in the next list and its injection there (the next
-// sweep's B row).  `cnt_next` was cleared a sweep earlier; `cnt_clear` (the count two
-// sweeps back, read by no kernel still to run) is cleared for the sweep after next.
+// Places of the staying columns of a 256-column chunk in the next list: a rank from the
+// block's ballots and one atomic per chunk (a counter shared by every column of the sweep
+// would serialise a million atomics).  Returns the slot, or -1 when `stay` is false.
+__device__ __forceinline__ int chunk_slot(bool stay, int *counter, int *wsum, int *base) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned long long m = __ballot(stay);
+    const int rank = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wsum[wave] = __popcll(m);
+    __syncthreads();
+    if (tid == 0) {
+        const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        *base = tot ? atomicAdd(counter, tot) : 0;
+    }
+    __syncthreads();
+    int off = *base;
+    for (int w = 0; w < wave; ++w) off += wsum[w];
+    return stay ? off + rank : -1;
+}
+
+// Chunks of 256 active columns: one thread per column for the convergence test (Eq. (3))
+// and retirement, the staying columns' places in the next list, then one wave per column
+// for the outputs of a retired one or the next sweep's B row (injection) of a staying
+// one.  `cnt_next` was cleared a sweep earlier; `cnt_clear` (the count two sweeps back,
+// read by no kernel still to run) is cleared for the sweep after next.
 template <typename T, typename IO>
-__global__ void finish_kernel(const long long *__restrict__ act, const int *__restrict__ cnt, int *cnt_clear,
-                              const IO *__restrict__ S, const T *__restrict__ x, const double *__restrict__ w, int n,
-                              int KP, const double *__restrict__ aP, const double *__restrict__ aI, double tol,
-                              int max_iter, unsigned long long *__restrict__ dmax, const int *__restrict__ badf,
-                              int32_t *iters, int8_t *status, IO *__restrict__ V, long long *__restrict__ act_next,
-                              int *cnt_next, T *__restrict__ B, int *done_flag, int seq) {
-    const int lane = threadIdx.x & 63;
+__global__ __launch_bounds__(256) void finish_kernel(
+    const long long *__restrict__ act, const int *__restrict__ cnt, int *cnt_clear, const IO *__restrict__ S,
+    const T *__restrict__ x, const double *__restrict__ w, int n, int KP, const double *__restrict__ aP,
+    const double *__restrict__ aI, double tol, int max_iter, unsigned long long *__restrict__ dmax,
+    const int *__restrict__ badf, int32_t *iters, int8_t *status, IO *__restrict__ V,
+    long long *__restrict__ act_next, int *cnt_next, T *__restrict__ B, int *done_flag, int seq) {
+    __shared__ long long col_s[256];
+    __shared__ int slot_s[256];
+    __shared__ int wsum[4], base_s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nact = *cnt;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         *cnt_clear = 0;
         if (nact == 0) post_done(done_flag, seq);
     }
-    for (long long a = blockIdx.x * 4LL + (threadIdx.x >> 6); a < nact; a += gridDim.x * 4LL) {
-        const long long c = act[a];
-        const double e = __longlong_as_double((long long)dmax[c]);
-        const int bad = badf[c];
-        const int it = iters[c] + 1;
-        const bool conv = !bad && sqrt(e) < tol;
-        const bool done = bad || conv || it >= max_iter;
-        if (done) {
-            for (int b = lane; b < n; b += 64) {
-                double vr = (double)x[2 * (c * n + b)], vi = (double)x[2 * (c * n + b) + 1];
-                if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
-                V[2 * (c * n + b)] = (IO)vr;
-                V[2 * (c * n + b) + 1] = (IO)vi;
-            }
-        }
-        int slot = 0;
-        if (lane == 0) {
+    for (long long c0 = blockIdx.x * 256LL; c0 < nact; c0 += gridDim.x * 256LL) {  // block-uniform
+        const long long a = c0 + tid;
+        long long c = -1;
+        bool stay = false;
+        if (a < nact) {
+            c = act[a];
+            const double e = __longlong_as_double((long long)dmax[c]);
+            const int bad = badf[c];
+            const int it = iters[c] + 1;
+            const bool conv = !bad && sqrt(e) < tol;
+            const bool done = bad || conv || it >= max_iter;
             iters[c] = it;
             dmax[c] = 0ull;
-            if (done) {
-                status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            if (done) status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            stay = !done;
+        }
+        const int slot = chunk_slot(stay, cnt_next, wsum, &base_s);
+        if (stay) act_next[slot] = c;
+        col_s[tid] = c;
+        slot_s[tid] = slot;
+        __syncthreads();
+        for (int k = wave; k < 256; k += 4) {
+            const long long cc = col_s[k];
+            if (cc < 0) break;  // past the active columns (wave-uniform)
+            const int sl = slot_s[k];
+            if (sl < 0) {
+                for (int b = lane; b < n; b += 64) {
+                    double vr = (double)x[2 * (cc * n + b)], vi = (double)x[2 * (cc * n + b) + 1];
+                    if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
+                    V[2 * (cc * n + b)] = (IO)vr;
+                    V[2 * (cc * n + b) + 1] = (IO)vi;
+                }
             } else {
-                slot = atomicAdd(cnt_next, 1);
-                act_next[slot] = c;
+                T *Br = B + (long long)sl * KP;
+                for (int b = lane; b < KP / 2; b += 64) {
+                    T ir, ii;
+                    injection_at<T, IO>(S, x, w, n, cc, b, aP, aI, ir, ii);
+                    Br[2 * b] = ir;
+                    Br[2 * b + 1] = ii;
+                }
             }
         }
-        if (!done) {  // wave-uniform
-            slot = __shfl(slot, 0);
-            T *Br = B + (long long)slot * KP;
-            for (int b = lane; b < KP / 2; b += 64) {
-                T ir, ii;
-                injection_at<T, IO>(S, x, w, n, c, b, aP, aI, ir, ii);
-                Br[2 * b] = ir;
-                Br[2 * b + 1] = ii;
-            }
-        }
+        __syncthreads();  // the chunk's tables are reused
     }
 }
 
@@ -566,98 +596,118 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
     }
 }
 
-// One wave per column of the refine list (first) and the low list: schedule update,
-// retirement, and for a column that stays active its place in the next refine or low
-// list with its injection there (B32 row: I; B16 row: as low_entry), I_prev <- I.
-// cnt = {low, refine} counts of this sweep; cnt_next was cleared a sweep earlier;
-// cnt_clear (the pair two sweeps back) is cleared for the sweep after next.
+// Chunks of 256 columns of the refine list (first) and the low list: one thread per
+// column for the schedule update and retirement and the staying columns' places in the
+// next refine or low list (chunk_slot), then one wave per column for the outputs of a
+// retired one or its injection into the next sweep's B32 row (I) or B16 row (as
+// low_entry), I_prev <- I.  cnt = {low, refine} counts of this sweep; cnt_next was cleared
+// a sweep earlier; cnt_clear (the pair two sweeps back) is cleared for the sweep after next.
 template <int MODE, typename IO>
-__global__ void finish_mixed_kernel(const long long *__restrict__ actR, const long long *__restrict__ actL,
-                                    const int *__restrict__ cnt, int *cnt_clear, const IO *__restrict__ S,
-                                    const float *__restrict__ U, const double *__restrict__ w, int n, int KP,
-                                    int KP16, const double *__restrict__ aP, const double *__restrict__ aI,
-                                    float tol, int max_iter, unsigned long long *__restrict__ dmax,
-                                    unsigned *__restrict__ umax, const int *__restrict__ badf,
-                                    MixState *__restrict__ ms, int32_t *iters, int8_t *status, IO *__restrict__ V,
-                                    float *__restrict__ Ip, long long *__restrict__ nextR,
-                                    long long *__restrict__ nextL, int *cnt_next, float *__restrict__ B32,
-                                    uint32_t *__restrict__ B16, int *done_flag, int seq) {
-    const int lane = threadIdx.x & 63;
+__global__ __launch_bounds__(256) void finish_mixed_kernel(
+    const long long *__restrict__ actR, const long long *__restrict__ actL, const int *__restrict__ cnt,
+    int *cnt_clear, const IO *__restrict__ S, const float *__restrict__ U, const double *__restrict__ w, int n,
+    int KP, int KP16, const double *__restrict__ aP, const double *__restrict__ aI, float tol, int max_iter,
+    unsigned long long *__restrict__ dmax, unsigned *__restrict__ umax, const int *__restrict__ badf,
+    MixState *__restrict__ ms, int32_t *iters, int8_t *status, IO *__restrict__ V, float *__restrict__ Ip,
+    long long *__restrict__ nextR, long long *__restrict__ nextL, int *cnt_next, float *__restrict__ B32,
+    uint32_t *__restrict__ B16, int *done_flag, int seq) {
+    __shared__ long long col_s[256];
+    __shared__ int slot_s[256];  // -1: retired; else the slot in the list kind_s names
+    __shared__ int kind_s[256];  // 0: refine next, 1: low next
+    __shared__ int ph_s[256];
+    __shared__ float ks_s[256];
+    __shared__ int wsum[4], base_s;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int nl = cnt[0], nr = cnt[1];
-    if (blockIdx.x == 0 && threadIdx.x < 2) cnt_clear[threadIdx.x] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0 && nl + nr == 0) post_done(done_flag, seq);
+    const long long total = (long long)nr + nl;
+    if (blockIdx.x == 0 && tid < 2) cnt_clear[tid] = 0;
+    if (blockIdx.x == 0 && tid == 0 && total == 0) post_done(done_flag, seq);
     constexpr float u = Low16<MODE>::u;
     const float theta = 4.0f * u, refresh = 6.7e-8f / u, margin = 1.0f + 8.0f * u;
-    for (long long a = blockIdx.x * 4LL + (threadIdx.x >> 6); a < (long long)nr + nl; a += gridDim.x * 4LL) {
-        const bool refine = a < nr;
-        const long long c = refine ? actR[a] : actL[a - nr];
-        MixState m = ms[c];
-        const float d = (float)sqrt(__longlong_as_double((long long)dmax[c]));
-        const float um = __uint_as_float(umax[c]);
-        const int bad = badf[c];
-        m.it += 1;
-        bool conv = false;
-        if (refine) {
-            conv = d < tol;
-            m.ph = 1;
-            m.want = 0;
-            m.sumd = 0.f;
-        } else if (m.ph == 0) {
-            m.uref = fmaxf(m.uref, um);
-            if (!m.want && (d <= theta * m.uref || (m.it >= 2 && d > 0.5f * m.dprev))) m.want = 1;
-        } else {
-            conv = d * margin < tol;
-            m.sumd += d;
-            if (!m.want && m.sumd > refresh) m.want = 1;
-        }
-        m.dprev = d;
-        const bool done = bad || conv || m.it >= max_iter;
-        if (done)
-            for (int b = lane; b < n; b += 64) {
-                V[2 * (c * n + b)] = (IO)(w[2 * b] + (double)U[2 * (c * n + b)]);
-                V[2 * (c * n + b) + 1] = (IO)(w[2 * b + 1] + (double)U[2 * (c * n + b) + 1]);
+    for (long long c0 = blockIdx.x * 256LL; c0 < total; c0 += gridDim.x * 256LL) {  // block-uniform
+        const long long a = c0 + tid;
+        long long c = -1;
+        bool stay = false, want = false;
+        MixState m{};
+        if (a < total) {
+            const bool refine = a < nr;
+            c = refine ? actR[a] : actL[a - nr];
+            m = ms[c];
+            const float d = (float)sqrt(__longlong_as_double((long long)dmax[c]));
+            const float um = __uint_as_float(umax[c]);
+            const int bad = badf[c];
+            m.it += 1;
+            bool conv = false;
+            if (refine) {
+                conv = d < tol;
+                m.ph = 1;
+                m.want = 0;
+                m.sumd = 0.f;
+            } else if (m.ph == 0) {
+                m.uref = fmaxf(m.uref, um);
+                if (!m.want && (d <= theta * m.uref || (m.it >= 2 && d > 0.5f * m.dprev))) m.want = 1;
+            } else {
+                conv = d * margin < tol;
+                m.sumd += d;
+                if (!m.want && m.sumd > refresh) m.want = 1;
             }
-        int slot = 0;
-        if (lane == 0) {
+            m.dprev = d;
+            const bool done = bad || conv || m.it >= max_iter;
             iters[c] = m.it;
             dmax[c] = 0ull;
             umax[c] = 0u;
             ms[c] = m;
-            if (done) {
-                status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
-            } else if (m.want) {
-                slot = atomicAdd(cnt_next + 1, 1);
-                nextR[slot] = c;
+            if (done) status[c] = bad ? TPF_ST_NONFINITE : (conv ? TPF_ST_CONVERGED : TPF_ST_MAX_ITER);
+            stay = !done;
+            want = m.want != 0;
+        }
+        const int sr = chunk_slot(stay && want, cnt_next + 1, wsum, &base_s);
+        __syncthreads();  // wsum and base_s are reused
+        const int sl = chunk_slot(stay && !want, cnt_next, wsum, &base_s);
+        if (sr >= 0) nextR[sr] = c;
+        if (sl >= 0) nextL[sl] = c;
+        col_s[tid] = c;
+        slot_s[tid] = sr >= 0 ? sr : sl;
+        kind_s[tid] = sr >= 0 ? 0 : 1;
+        ph_s[tid] = m.ph;
+        ks_s[tid] = m.ks;
+        __syncthreads();
+        for (int k = wave; k < 256; k += 4) {
+            const long long cc = col_s[k];
+            if (cc < 0) break;  // past the active columns (wave-uniform)
+            const int slot = slot_s[k];
+            if (slot < 0) {
+                for (int b = lane; b < n; b += 64) {
+                    V[2 * (cc * n + b)] = (IO)(w[2 * b] + (double)U[2 * (cc * n + b)]);
+                    V[2 * (cc * n + b) + 1] = (IO)(w[2 * b + 1] + (double)U[2 * (cc * n + b) + 1]);
+                }
+            } else if (kind_s[k] == 0) {
+                float2 *Br = reinterpret_cast<float2 *>(B32 + (long long)slot * KP);
+                for (int b = lane; b < KP / 2; b += 64) {
+                    float2 iz = make_float2(0.f, 0.f);
+                    if (b < n) {
+                        const long long o = 2 * (cc * n + b);
+                        iz = injection32(S, U, w, o, b, aP, aI);
+                        *reinterpret_cast<float2 *>(Ip + o) = iz;
+                    }
+                    Br[b] = iz;
+                }
             } else {
-                slot = atomicAdd(cnt_next, 1);
-                nextL[slot] = c;
+                const int ph = ph_s[k];
+                const float kss = ks_s[k];
+                uint32_t *Br = B16 + (long long)slot * (KP16 / 2);
+                for (int b = lane; b < KP16 / 2; b += 64) {
+                    uint32_t out = 0u;
+                    if (b < n) {
+                        const long long o = 2 * (cc * n + b);
+                        out = low_entry<MODE>(injection32(S, U, w, o, b, aP, aI), reinterpret_cast<float2 *>(Ip + o),
+                                              ph, kss);
+                    }
+                    Br[b] = out;
+                }
             }
         }
-        if (done) continue;  // wave-uniform
-        slot = __shfl(slot, 0);
-        if (m.want) {
-            float2 *Br = reinterpret_cast<float2 *>(B32 + (long long)slot * KP);
-            for (int b = lane; b < KP / 2; b += 64) {
-                float2 iz = make_float2(0.f, 0.f);
-                if (b < n) {
-                    const long long o = 2 * (c * n + b);
-                    iz = injection32(S, U, w, o, b, aP, aI);
-                    *reinterpret_cast<float2 *>(Ip + o) = iz;
-                }
-                Br[b] = iz;
-            }
-        } else {
-            uint32_t *Br = B16 + (long long)slot * (KP16 / 2);
-            for (int b = lane; b < KP16 / 2; b += 64) {
-                uint32_t out = 0u;
-                if (b < n) {
-                    const long long o = 2 * (c * n + b);
-                    out = low_entry<MODE>(injection32(S, U, w, o, b, aP, aI), reinterpret_cast<float2 *>(Ip + o),
-                                          m.ph, m.ks);
-                }
-                Br[b] = out;
-            }
-        }
+        __syncthreads();  // the chunk's tables are reused
     }
 }
 
@@ -732,7 +782,7 @@ static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *
     // the device has already posted that none is left (all_retired).
     const int row_blocks = MP / 64;
     const unsigned g_mm = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)row_blocks * (rows / 64));
-    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + 3) / 4);
+    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + 255) / 256);
     const int seq = ++dn.solve_seq;
     for (int sweep = 0; sweep < max_iter; ++sweep) {
         if (all_retired(dn, seq)) break;
@@ -800,7 +850,7 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
     // Queued at once as in run_large; counts in pairs {low, refine}, three pairs in rotation.
     const unsigned g_r = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 64) * (rows / 64));
     const unsigned g_l = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 128) * (rows16 / 128));
-    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + 3) / 4);
+    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + 255) / 256);
     const int seq = ++dn.solve_seq;
     for (int sweep = 0; sweep < max_iter; ++sweep) {
         if (all_retired(dn, seq)) break;
