@@ -5,11 +5,11 @@
 //   gemm    V' = Z I + w on MFMA (64 x 64 output tiles, K staged through LDS), whose
 //           epilogue updates the state in place and reduces max |V' - V| per column
 //           with atomics;
-//   finish  one wave per active column: sweep count, stopping rule, retirement to the
-//           output and compaction of the active list for the next sweep.
-// FP64 mode keeps the state V in FP64; FP32 mode keeps the FP32 drop U = V - w.
-// The host reads the active count back once per sweep to size the next launches and
-// to stop once every column has retired.
+//   finish  chunks of 256 active columns: sweep count, stopping rule, retirement to the
+//           output, compaction of the active list for the next sweep and the next
+//           sweep's injection (the first sweep's comes from its own kernel).
+// FP64 mode keeps the state V in FP64; FP32 mode keeps the FP32 drop U = V - w.  Every
+// sweep is queued without waiting on the device: the active counts stay there.
 #include "tpf_internal.h"
 
 namespace tpf {
@@ -142,10 +142,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(const T *__restrict__ A, int 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
-    // a fixed grid walks the tiles of the active columns (none once every column is done);
-    // column tiles run fastest, so resident blocks share the A row block
+    // A fixed grid walks the tiles of the active columns (none once every column is done).
+    // With A small enough to stay in L2 the row blocks of a column tile run back to back
+    // (its B slab is fetched from HBM about once); otherwise column tiles run fastest and
+    // the resident blocks share A's row block.
+    const bool rows_fast = (size_t)row_blocks * 64 * KP * sizeof(T) <= ((size_t)2 << 20);
     for (int t = blockIdx.x; t < ct * row_blocks; t += gridDim.x) {
-        const int c0 = (t % ct) * 64, r0 = (t / ct) * 64;
+        const int c0 = (rows_fast ? t / row_blocks : t % ct) * 64;
+        const int r0 = (rows_fast ? t % row_blocks : t / ct) * 64;
         v4 acc[2][2];
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b) acc[a][b] = v4{0, 0, 0, 0};
@@ -239,7 +243,7 @@ __device__ __forceinline__ void post_done(int *done_flag, int seq) {
     if (done_flag) __hip_atomic_store(done_flag, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
-// Places of the staying columns of a 256-column chunk in the next list: a rank from the
+// Places of the staying columns of a chunk in the next list: a rank from the
 // block's ballots and one atomic per chunk (a counter shared by every column of the sweep
 // would serialise a million atomics).  Returns the slot, or -1 when `stay` is false.
 __device__ __forceinline__ int chunk_slot(bool stay, int *counter, int *wsum, int *base) {
@@ -258,7 +262,9 @@ __device__ __forceinline__ int chunk_slot(bool stay, int *counter, int *wsum, in
     return stay ? off + rank : -1;
 }
 
-// Chunks of 256 active columns: one thread per column for the convergence test (Eq. (3))
+// Chunks of cpb active columns (a power of two, 4 to 256: fewer for wider networks, so
+// that the per-column work of the second phase spreads over enough wavefronts): one
+// thread per column for the convergence test (Eq. (3))
 // and retirement, the staying columns' places in the next list, then one wave per column
 // for the outputs of a retired one or the next sweep's B row (injection) of a staying
 // one.  `cnt_next` was cleared a sweep earlier; `cnt_clear` (the count two sweeps back,
@@ -269,7 +275,7 @@ __global__ __launch_bounds__(256) void finish_kernel(
     const T *__restrict__ x, const double *__restrict__ w, int n, int KP, const double *__restrict__ aP,
     const double *__restrict__ aI, double tol, int max_iter, unsigned long long *__restrict__ dmax,
     const int *__restrict__ badf, int32_t *iters, int8_t *status, IO *__restrict__ V,
-    long long *__restrict__ act_next, int *cnt_next, T *__restrict__ B, int *done_flag, int seq) {
+    long long *__restrict__ act_next, int *cnt_next, T *__restrict__ B, int *done_flag, int seq, int cpb) {
     __shared__ long long col_s[256];
     __shared__ int slot_s[256];
     __shared__ int wsum[4], base_s;
@@ -279,11 +285,11 @@ __global__ __launch_bounds__(256) void finish_kernel(
         *cnt_clear = 0;
         if (nact == 0) post_done(done_flag, seq);
     }
-    for (long long c0 = blockIdx.x * 256LL; c0 < nact; c0 += gridDim.x * 256LL) {  // block-uniform
+    for (long long c0 = blockIdx.x * (long long)cpb; c0 < nact; c0 += (long long)gridDim.x * cpb) {  // block-uniform
         const long long a = c0 + tid;
         long long c = -1;
         bool stay = false;
-        if (a < nact) {
+        if (tid < cpb && a < nact) {
             c = act[a];
             const double e = __longlong_as_double((long long)dmax[c]);
             const int bad = badf[c];
@@ -300,7 +306,7 @@ __global__ __launch_bounds__(256) void finish_kernel(
         col_s[tid] = c;
         slot_s[tid] = slot;
         __syncthreads();
-        for (int k = wave; k < 256; k += 4) {
+        for (int k = wave; k < cpb; k += 4) {
             const long long cc = col_s[k];
             if (cc < 0) break;  // past the active columns (wave-uniform)
             const int sl = slot_s[k];
@@ -493,9 +499,11 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, j = lane & 15;
     const int wr = (wave >> 1) * 64, wc = (wave & 1) * 64;
-    // a fixed grid walks the tiles of the active columns, column tiles fastest
+    // a fixed grid walks the tiles of the active columns, ordered as in gemm_kernel
+    const bool rows_fast = (size_t)row_blocks * 128 * KP16 * 2 <= ((size_t)2 << 20);
     for (int t = blockIdx.x; t < ct * row_blocks; t += gridDim.x) {
-        const int c0 = (t % ct) * 128, r0 = (t / ct) * 128;
+        const int c0 = (rows_fast ? t / row_blocks : t % ct) * 128;
+        const int r0 = (rows_fast ? t % row_blocks : t / ct) * 128;
         f4x acc[4][4];
     #pragma unroll
         for (int a = 0; a < 4; ++a)
@@ -596,7 +604,7 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
     }
 }
 
-// Chunks of 256 columns of the refine list (first) and the low list: one thread per
+// Chunks of cpb columns (as finish_kernel) of the refine list (first) and the low list: one thread per
 // column for the schedule update and retirement and the staying columns' places in the
 // next refine or low list (chunk_slot), then one wave per column for the outputs of a
 // retired one or its injection into the next sweep's B32 row (I) or B16 row (as
@@ -610,7 +618,7 @@ __global__ __launch_bounds__(256) void finish_mixed_kernel(
     unsigned long long *__restrict__ dmax, unsigned *__restrict__ umax, const int *__restrict__ badf,
     MixState *__restrict__ ms, int32_t *iters, int8_t *status, IO *__restrict__ V, float *__restrict__ Ip,
     long long *__restrict__ nextR, long long *__restrict__ nextL, int *cnt_next, float *__restrict__ B32,
-    uint32_t *__restrict__ B16, int *done_flag, int seq) {
+    uint32_t *__restrict__ B16, int *done_flag, int seq, int cpb) {
     __shared__ long long col_s[256];
     __shared__ int slot_s[256];  // -1: retired; else the slot in the list kind_s names
     __shared__ int kind_s[256];  // 0: refine next, 1: low next
@@ -624,12 +632,12 @@ __global__ __launch_bounds__(256) void finish_mixed_kernel(
     if (blockIdx.x == 0 && tid == 0 && total == 0) post_done(done_flag, seq);
     constexpr float u = Low16<MODE>::u;
     const float theta = 4.0f * u, refresh = 6.7e-8f / u, margin = 1.0f + 8.0f * u;
-    for (long long c0 = blockIdx.x * 256LL; c0 < total; c0 += gridDim.x * 256LL) {  // block-uniform
+    for (long long c0 = blockIdx.x * (long long)cpb; c0 < total; c0 += (long long)gridDim.x * cpb) {  // block-uniform
         const long long a = c0 + tid;
         long long c = -1;
         bool stay = false, want = false;
         MixState m{};
-        if (a < total) {
+        if (tid < cpb && a < total) {
             const bool refine = a < nr;
             c = refine ? actR[a] : actL[a - nr];
             m = ms[c];
@@ -672,7 +680,7 @@ __global__ __launch_bounds__(256) void finish_mixed_kernel(
         ph_s[tid] = m.ph;
         ks_s[tid] = m.ks;
         __syncthreads();
-        for (int k = wave; k < 256; k += 4) {
+        for (int k = wave; k < cpb; k += 4) {
             const long long cc = col_s[k];
             if (cc < 0) break;  // past the active columns (wave-uniform)
             const int slot = slot_s[k];
@@ -718,6 +726,15 @@ __global__ __launch_bounds__(256) void finish_mixed_kernel(
 // memory; it never waits for the device.
 static bool all_retired(const DeviceNet &dn, int seq) {
     return dn.done_host && __atomic_load_n(dn.done_host, __ATOMIC_ACQUIRE) == seq;
+}
+
+// Columns per finish chunk: about 16,384 buses' worth, a power of two in [4, 256] (one
+// atomic per chunk keeps a million-column sweep from serialising on the list counter,
+// and small chunks keep a few wide columns spread over many wavefronts).
+static int finish_chunk(int n) {
+    int c = 4;
+    while (c < 256 && 2 * c * n <= 16384) c *= 2;
+    return c;
 }
 
 // Fixed grids of the queued sweeps: enough blocks to fill the chip, few enough that a
@@ -782,7 +799,8 @@ static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *
     // the device has already posted that none is left (all_retired).
     const int row_blocks = MP / 64;
     const unsigned g_mm = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)row_blocks * (rows / 64));
-    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + 255) / 256);
+    const int cpb = finish_chunk(n);
+    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + cpb - 1) / cpb);
     const int seq = ++dn.solve_seq;
     for (int sweep = 0; sweep < max_iter; ++sweep) {
         if (all_retired(dn, seq)) break;
@@ -792,7 +810,7 @@ static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *
                            dmax, badf);
         hipLaunchKernelGGL((finish_kernel<T, IO>), dim3(g_fin), dim3(256), 0, st, act[cur], cr, cz, (const IO *)S, x, w,
                            n, KP, dn.aP, dn.aI, tol, max_iter, dmax, badf, iters, status, (IO *)V, act[cur ^ 1], cn,
-                           B, dn.done_dev, seq);
+                           B, dn.done_dev, seq, cpb);
     }
     return TPF_OK;
 }
@@ -850,7 +868,8 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
     // Queued at once as in run_large; counts in pairs {low, refine}, three pairs in rotation.
     const unsigned g_r = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 64) * (rows / 64));
     const unsigned g_l = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 128) * (rows16 / 128));
-    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + 255) / 256);
+    const int cpb = finish_chunk(n);
+    const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + cpb - 1) / cpb);
     const int seq = ++dn.solve_seq;
     for (int sweep = 0; sweep < max_iter; ++sweep) {
         if (all_retired(dn, seq)) break;
@@ -864,7 +883,7 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
         hipLaunchKernelGGL((finish_mixed_kernel<MODE, IO>), dim3(g_fin), dim3(256), 0, st, actR[cur], actL[cur], cc, cz,
                            (const IO *)S, U, w, n, KP, K16, dn.aP, dn.aI, (float)tol, max_iter, dmax, umax, badf, ms,
                            iters, status, (IO *)V, Ip, actR[cur ^ 1], actL[cur ^ 1], cn, B32,
-                           reinterpret_cast<uint32_t *>(B16), dn.done_dev, seq);
+                           reinterpret_cast<uint32_t *>(B16), dn.done_dev, seq, cpb);
     }
     return TPF_OK;
 }
