@@ -127,6 +127,54 @@ def ingest_pmc(fetch_dir: str, write_dir: str):
     print(json.dumps(out, indent=1))
 
 
+def summarize_pmc(out_txt: str, command: str, dirs):
+    """Per-kernel SQ counters (median over dispatches) from rocprofv3 --pmc runs, with the
+    derived figures the design notes cite.  Normalisation: SQ_BUSY_CYCLES sums the busy
+    cycles of the 32 shader engines (8 XCDs x 4), each with 32 SIMDs, so a kernel's elapsed
+    cycles are SQ_BUSY_CYCLES / 32; SQ_VALU_MFMA_BUSY_CYCLES sums the matrix units' busy
+    cycles over all 1,024 SIMDs (a 16x16x32 16-bit product counts 16, its time at peak), so
+    MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (32 SQ_BUSY_CYCLES).  Wait = SQ_WAIT_INST_ANY /
+    SQ_WAVE_CYCLES (share of the waves' lifetime spent waiting on a dependency); VALU busy
+    is SQ_INSTS_VALU x 4 cycles (a 64-lane instruction on a 16-lane SIMD) over the same
+    SIMD-cycles."""
+    import csv
+    import glob
+    import statistics
+    keys = ("fpi_f64_kernel", "fpi_mixed_kernel", "predict_fused_kernel", "mismatch_tile_kernel", "fpi_tree_kernel",
+            "fpi_tree32_kernel", "gemm_low_kernel", "gemm_kernel", "finish_mixed_kernel", "finish_kernel")
+    vals = {}
+    for d in dirs:
+        for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            for r in csv.DictReader(open(path)):
+                name = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+                if not any(k + "<" in name for k in keys):
+                    continue
+                vals.setdefault(name, {}).setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    if not vals:
+        raise SystemExit("no counter rows of the sweep, inference or mismatch kernels in " + " ".join(dirs))
+    lines = ["# SQ counters per kernel (rocprofv3 --pmc, median over dispatches)", f"command: {command}", "",
+             "derived: MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (32 SQ_BUSY_CYCLES); VALU busy = 4 SQ_INSTS_VALU / "
+             "(32 SQ_BUSY_CYCLES); wait = SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES; elapsed = SQ_BUSY_CYCLES / 32 at "
+             "2.4 GHz", ""]
+    for name, cs in sorted(vals.items(), key=lambda kv: -statistics.median(kv[1].get("SQ_BUSY_CYCLES", [0]))):
+        med = {c: statistics.median(v) for c, v in cs.items()}
+        lines.append(name)
+        busy = med.get("SQ_BUSY_CYCLES")
+        if busy:
+            lines.append(f"   elapsed ~ {busy / 32 / 2.4e3:9.1f} us")
+            if "SQ_VALU_MFMA_BUSY_CYCLES" in med:
+                lines.append(f"   MFMA busy {100 * med['SQ_VALU_MFMA_BUSY_CYCLES'] / (32 * busy):6.1f} %")
+            if "SQ_INSTS_VALU" in med:
+                lines.append(f"   VALU busy {100 * 4 * med['SQ_INSTS_VALU'] / (32 * busy):6.1f} %")
+        if "SQ_WAIT_INST_ANY" in med and med.get("SQ_WAVE_CYCLES"):
+            lines.append(f"   wait      {100 * med['SQ_WAIT_INST_ANY'] / med['SQ_WAVE_CYCLES']:6.1f} %")
+        for c in sorted(med):
+            lines.append(f"   {c:28s} {med[c]:14.4g}   (n={len(cs[c])})")
+    with open(out_txt, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_trace(trace_dir: str, out_txt: str, command: str):
     """Per-kernel call counts and durations from rocprofv3 --kernel-trace --stats CSV output,
     with the sweep kernels' individual launches listed in order (the timed steps and the
@@ -403,6 +451,12 @@ def main():
                          "100-bus three-phase feeder over the year")
     ap.add_argument("--scaling", action="store_true",
                     help="time the FP64 and mixed FP16 solves over network sizes and batch sizes and exit")
+    ap.add_argument("--warm-mlp", default="",
+                    help="load the warm-start network from this file if it exists (no training; profiling "
+                         "runs), else train it and save it there")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="ARG",
+                    help="OUT_TXT COMMAND DIR [DIR ...]: write a per-kernel summary of rocprofv3 --pmc SQ "
+                         "counter runs and exit")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT_TXT", "COMMAND"),
                     help="write a short text summary of a rocprofv3 --kernel-trace --stats run and exit")
     args = ap.parse_args()
@@ -411,6 +465,11 @@ def main():
         return
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_pmc:
+        if len(args.summarize_pmc) < 3:
+            raise SystemExit("--summarize-pmc OUT_TXT COMMAND DIR [DIR ...]")
+        summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.summarize_pmc[2:])
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -458,8 +517,8 @@ def main():
     def time_form(mode, mlp=None):
         """K timed steps of one form (the solve, with the learned start evaluated by the solve
         itself for a warm form, and the FP64 mismatch), plus the dominant kernel alone: the
-        sweep kernel without the mismatch pass, or for the fused warm form (inference, sweeps
-        and mismatch in one kernel) the whole solve."""
+        sweep kernel without the mismatch pass (for a warm form, started from the network's
+        prediction computed beforehand, so that only the sweeps run)."""
         warm = dict(warm_start=mlp[0], t_index=mlp[1]) if mlp is not None else {}
         out = tpf.alloc_outputs(net, S, mode, mismatch=True, warm_start=mlp[0] if mlp else None)
 
@@ -473,21 +532,21 @@ def main():
             step()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
-        fused = mlp is not None and mode == "mixed_fp16"
-        kout = out if fused else tpf.alloc_outputs(net, S, mode, mismatch=False,
-                                                   warm_start=mlp[0] if mlp else None)
+        kout = tpf.alloc_outputs(net, S, mode, mismatch=False)
+        V0p = mlp[0].predict(S, mlp[1]) if mlp is not None else None
         ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
               for _ in range(args.steps)]
         for a, b in ev:
             a.record(stream)
-            tpf.solve_timeseries(net, S, tol, max_iter, mode, mismatch=fused, out=kout, **warm)
+            tpf.solve_timeseries(net, S, tol, max_iter, mode, V0=V0p, out=kout)
             b.record(stream)
         torch.cuda.synchronize()
         k_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+        del kout, V0p
         V, iters, status, mm, _ = out
         it = iters.cpu().numpy()
         return {"ms_per_step": 1e3 * wall / args.steps, "kernel_ms": k_ms, "V": V,
-                "kernel_timed": "inference + sweeps + mismatch (one kernel)" if fused else "sweeps",
+                "kernel_timed": "sweeps from the learned start" if mlp is not None else "sweeps",
                 "power_flows_per_s": T / (wall / args.steps),
                 "sweeps_mean": float(it.mean()), "sweeps_max": int(it.max()),
                 "sweep_hist": {int(k): int(v) for k, v in zip(*np.unique(it, return_counts=True))},
@@ -515,10 +574,16 @@ def main():
         V_tr, _, st_tr = tpf.solve_timeseries(net, S_tr, 1e-10, 100, "fp64")
         torch.cuda.synchronize()
         data_s = time.perf_counter() - t0
-        mlp = tpf.WarmStart(n, params=W.mlp_init_params(W.mlp_sizes(n)))
         t0 = time.perf_counter()
-        hist = mlp.fit(S_tr, t_tr, V_tr, epochs=args.train_epochs, batch=args.train_batch, lr=args.train_lr,
-                       lr_min=1e-5, seed=W.SEED_TRAIN)
+        if args.warm_mlp and os.path.exists(args.warm_mlp):  # trained by an earlier run of this script
+            mlp = tpf.WarmStart.load(args.warm_mlp)
+            hist = [float("nan")]
+        else:
+            mlp = tpf.WarmStart(n, params=W.mlp_init_params(W.mlp_sizes(n)))
+            hist = mlp.fit(S_tr, t_tr, V_tr, epochs=args.train_epochs, batch=args.train_batch, lr=args.train_lr,
+                           lr_min=1e-5, seed=W.SEED_TRAIN)
+            if args.warm_mlp:
+                mlp.save(args.warm_mlp)
         torch.cuda.synchronize()
         train_s = time.perf_counter() - t0
         del S_tr, V_tr
@@ -534,7 +599,8 @@ def main():
         pred_ms = float(np.mean([a.elapsed_time(b) for a, b in evp]))
         col_err = (V0buf - forms["fp64"]["V"]).abs().amax(dim=1).double().cpu().numpy()
         del V0buf
-        warm = {"train_steps": args.train_steps, "train_minutes": "drawn without replacement across the whole "
+        warm = {"loaded_from": args.warm_mlp if hist[-1] != hist[-1] else None,
+                "train_steps": args.train_steps, "train_minutes": "drawn without replacement across the whole "
                 "separately seeded year", "epochs": args.train_epochs, "batch": args.train_batch,
                 "lr": args.train_lr, "final_loss": hist[-1], "training_s": train_s, "training_data_s": data_s,
                 "predict_ms": pred_ms, "max_start_error_pu": float(col_err.max()),
@@ -613,7 +679,7 @@ def main():
         "warm_start": warm,
         "roofline": roofline(hf, PEAK_F16_TFLOPS,
                              f"fpi_mixed_kernel ({head.split('+')[0]}, 99 PQ buses"
-                             + (", inference + sweeps + mismatch)" if head == "mixed_fp16+warm" else ")"),
+                             + (", sweeps from the learned start)" if head.endswith("+warm") else ")"),
                              f"{head}/year100"),
         "fp64_form": {"value": base["power_flows_per_s"], "ms_per_step": base["ms_per_step"],
                       "roofline": roofline(base, PEAK_FP64_TFLOPS, "fpi_f64_kernel (99 PQ buses)",
