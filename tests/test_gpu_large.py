@@ -256,3 +256,32 @@ def test_2000bus_sampled(gpu, feeder2000, mode):
         assert np.abs(Vs.cpu().numpy() - ref.V).max() <= FAST_BOUND
     mref = oracle.mismatch(onet, S[idx], Vs.cpu().numpy())
     assert np.all(np.abs(mm[ig].cpu().numpy() - mref) <= _mm_rounding(onet) + 1e-9 * mref)
+
+
+@pytest.mark.parametrize("mode,n_bus", [("fp64", 400), ("mixed_fp16", 200)])
+def test_concurrent_solves_on_two_streams(gpu, mode, n_bus):
+    """Two solves of one network queued on two streams at once (the queued sweeps of each
+    read their own active counts; the pinned early-stop word carries each solve's own
+    sequence number, so one solve's post never stops the other's queue): each result equals
+    the same solve run alone, bit for bit."""
+    f = W.make_feeder(n_bus)
+    net = tpf.Network.from_feeder(f)
+    Sa = _dev(W.profile_minute_year(f, steps=700, t0=10), gpu)
+    Sb = _dev(W.profile_minute_year(f, steps=1100, t0=90_000), gpu)
+    ra = tpf.solve_timeseries(net, Sa, tol=1e-6, max_iter=100, mode=mode)
+    rb = tpf.solve_timeseries(net, Sb, tol=1e-6, max_iter=100, mode=mode)
+    torch.cuda.synchronize()
+    oa = tpf.alloc_outputs(net, Sa, mode)
+    ob = tpf.alloc_outputs(net, Sb, mode)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for _ in range(3):
+        with torch.cuda.stream(s1):
+            ca = tpf.solve_timeseries(net, Sa, tol=1e-6, max_iter=100, mode=mode, out=oa)
+        with torch.cuda.stream(s2):
+            cb = tpf.solve_timeseries(net, Sb, tol=1e-6, max_iter=100, mode=mode, out=ob)
+        torch.cuda.synchronize()
+        for x, y in zip(ra, ca):
+            assert torch.equal(x, y)
+        for x, y in zip(rb, cb):
+            assert torch.equal(x, y)
