@@ -4,7 +4,7 @@
 // load drawing S must satisfy S = v .* conj(i_d), i.e.
 //     m = S + V .* conj(Y_ds v_s + Y_dd V) = 0,
 // reported per column as max_i |m_i| (NaN if any term is NaN).  ZIP loads of Eq. (2)
-// (alpha_Z = 0) draw S (alpha_P + alpha_I V) in place of S.
+// draw S (alpha_P + alpha_I V + alpha_Z |V|^2) in place of S.
 //
 // Tiled kernel: a workgroup takes CB columns at a time (their V are contiguous),
 // copies their V into LDS with coalesced loads, and then TPC = 256 / CB consecutive
