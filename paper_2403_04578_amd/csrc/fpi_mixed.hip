@@ -185,7 +185,6 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     float ks[CG], inv[CG];  // B scale 2^sB and product unscale 2^-(sB + sZ) per group
     bool dif[CG];
     bool precise = !kMixed;
-    bool exhausted = false;
     int par = 0;
     const float theta_k = 4.0f * L::u;
     const float refresh = 6.7e-8f / L::u;
@@ -600,7 +599,7 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     constexpr int CG = (MODE == TPF_MODE_FP32 || TPW == 1) ? 4 : TPF_MIXED_CG;
     const int MT = dn.MT;
     constexpr bool mixed = MODE != TPF_MODE_FP32, split = MODE == TPF_MODE_MIXED_FP16;
-    const size_t NC = 16 * CG, NT = NW * 64;
+    const size_t NC = 16 * CG;
     const size_t KPL = 32 * KTL + 8, KP32 = 16 * MT + 4;
     const bool zip = dn.aP != nullptr;
     const size_t lds0 = (split ? 0 : NC * KP32 * 4) + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) +
