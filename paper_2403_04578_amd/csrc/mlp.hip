@@ -26,6 +26,7 @@ namespace tpf {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b4 __attribute__((ext_vector_type(4)));
 
 namespace {
 
@@ -245,13 +246,19 @@ __global__ void frag_kernel(const float *__restrict__ p, int64_t woff, int64_t b
 // in the accumulators until every wave has read its inputs), and the voltage write.  Wave
 // w owns output neurons 64 w .. 64 w + 63 of all rows (RT x 4 tiles of 16x16x32) and
 // streams its weight fragments (the fragment copy: 1 KB contiguous per fragment) from L2
-// two k-steps ahead; with RT = 8 each fragment feeds 32 products, halving the weight
-// traffic per row against 64-row tiles.  The first layer's inputs and the output layer's
-// neurons are ordered (Re, Im) per bus, so each complex load of S becomes one 4-byte LDS
-// write and each complex voltage two adjacent outputs.  The output layer goes through LDS
-// as FP32, 64 rows at a time, so that the voltages leave as contiguous complex stores.
-// Nothing but S and V0 touches HBM.
-constexpr int kFusedWidth = 256, kHStride = 264, kYStride = 257;
+// one k-step ahead.  The weights are the products' A operand, so a lane's four outputs of
+// a tile are consecutive neurons of one row: a hidden layer's leave as one 8-byte LDS
+// store.  RT = 6 (96 rows, 50.7 KB of LDS) lets three workgroups share a CU, at most 168
+// VGPRs each; 128-row tiles at two per CU measured 0.62 ms against 0.54 ms for the 100-bus
+// year, 64-row tiles at four per CU 0.61 ms.  The first layer's inputs and the output
+// layer's neurons are ordered (Re, Im) per bus, so each complex load of S becomes one
+// 4-byte LDS write and each complex voltage two adjacent outputs; the output layer goes
+// through LDS as FP32, half a tile at a time in the activations' bytes, so that the
+// voltages leave as contiguous complex stores (stored straight from the accumulators,
+// 128-byte pieces per row, the kernel ran twice as long).  Nothing but S and V0 touches HBM.
+// Row strides of the activations (BF16) and of the output staging (FP32): 16 RT rows of
+// one and 8 RT rows of the other take the same bytes.
+constexpr int kFusedWidth = 256, kHStride = 264, kYStride = 264;
 
 // Complex pairs as clang vectors, so that the streamed loads and stores can carry the
 // nontemporal hint (S and V0 pass once; the weights should stay in L2).
@@ -280,22 +287,40 @@ __device__ __forceinline__ float gelu_as(float z) {
     return 0.5f * z * (1.0f + copysignf(e, z));
 }
 
-template <int RT>
-constexpr size_t fused_lds() {
-    return (size_t)16 * RT * kHStride * 2 > (size_t)64 * kYStride * 4 ? (size_t)16 * RT * kHStride * 2
-                                                                       : (size_t)64 * kYStride * 4;
+// GELU as z P(z) without transcendental functions: P approximates the normal CDF as
+// 1/2 + y Q(y^2), y = z clamped to [-4.25, 4.25], Q a degree-8 minimax fit with P(4.25) = 1,
+// and P clamped to [0, 1] (so P = 0 below -4.25 and 1 above 4.25).  |error| < 5.5e-5 |z| /
+// 4.25 inside, 1.1e-5 |z| beyond: far below the BF16 rounding of the activation.
+__device__ __forceinline__ float gelu_poly(float z) {
+    const float y = __builtin_amdgcn_fmed3f(z, -4.25f, 4.25f);
+    const float u = y * y;
+    float q = 5.179778134190016e-11f;
+    q = __builtin_fmaf(q, u, -5.024720195478949e-09f);
+    q = __builtin_fmaf(q, u, 2.1581175246865314e-07f);
+    q = __builtin_fmaf(q, u, -5.462514309328981e-06f);
+    q = __builtin_fmaf(q, u, 9.186843817587942e-05f);
+    q = __builtin_fmaf(q, u, -0.0011003842810168862f);
+    q = __builtin_fmaf(q, u, 0.009793556295335293f);
+    q = __builtin_fmaf(q, u, -0.06631755083799362f);
+    q = __builtin_fmaf(q, u, 0.3988931477069855f);
+    return z * __builtin_amdgcn_fmed3f(__builtin_fmaf(y, q, 0.5f), 0.0f, 1.0f);
 }
 
+template <int RT>
+constexpr size_t fused_lds() {
+    return (size_t)16 * RT * kHStride * 2;
+}
+
+// three workgroups per CU: at most 168 VGPRs
 template <typename IO, int RT>
-__global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict__ S,
-                                                            const int64_t *__restrict__ t_index, int64_t rows,
-                                                            const MlpView mv, double vs_re, double vs_im,
-                                                            IO *__restrict__ V0) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void predict_fused_kernel(
+    const IO *__restrict__ S, const int64_t *__restrict__ t_index, int64_t rows, const MlpView mv, double vs_re,
+    double vs_im, IO *__restrict__ V0) {
     constexpr int R = 16 * RT;  // rows per workgroup
+    static_assert(RT % 2 == 0, "the output layer leaves in two halves of RT / 2 row tiles");
     typedef typename Pair<IO>::T P2;
     extern __shared__ __align__(16) unsigned char smem[];
     __bf16 *H = reinterpret_cast<__bf16 *>(smem);  // [R][264]
-    float *Yf = reinterpret_cast<float *>(smem);   // [64][257], once the last product has read H
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int g = lane >> 4, j = lane & 15;
@@ -358,17 +383,24 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
         const int n0 = 64 * wave;
         const bool mine = 4 * wave < T;
         const bool last = l == mv.L;
+        // The weights are the A operand and the activations the B operand, so that lane
+        // (g, j) of product tile (a, b) accumulates neurons n0 + 16 b + 4 g .. + 3 of row
+        // 16 a + j: four consecutive outputs of one row.  The accumulators start at the bias.
+        const float *bias = mv.b[l];
         f4 acc[RT][4];
 #pragma unroll
-        for (int a = 0; a < RT; ++a)
+        for (int b = 0; b < 4; ++b) {
+            const f4 bb = mine && 4 * wave + b < T ? *reinterpret_cast<const f4 *>(bias + n0 + 16 * b + 4 * g)
+                                                    : f4{0, 0, 0, 0};
 #pragma unroll
-            for (int b = 0; b < 4; ++b) acc[a][b] = f4{0, 0, 0, 0};
+            for (int a = 0; a < RT; ++a) acc[a][b] = bb;
+        }
         if (mine) {
-            // weight fragments stream from L2 through a ring of three register sets, two
-            // k-steps ahead of the products that use them (K <= 256: at most 8 k-steps)
+            // weight fragments stream from L2 through two register sets, one k-step ahead
+            // of the products that use them (K <= 256: at most 8 k-steps)
             const int ks = K / 32;
             // fragment (tile 4 wave + b, k-step k0 / 32): lane (g, j) holds neuron 16 t + j,
-            // inputs k0 + 8 g .. k0 + 8 g + 7 -- the B operand of these products
+            // inputs k0 + 8 g .. k0 + 8 g + 7
             const uint16_t *Wl = mv.W[l] + (size_t)lane * 8;
             auto ldw = [&](b8(&w)[4], int k0) {
 #pragma unroll
@@ -377,76 +409,75 @@ __global__ __launch_bounds__(256) void predict_fused_kernel(const IO *__restrict
                     w[b] = t < T ? *reinterpret_cast<const b8 *>(Wl + ((size_t)t * ks + k0 / 32) * 512) : b8{};
                 }
             };
-            b8 w[3][4];
-#pragma unroll
-            for (int st = 0; st < 2; ++st)
-                if (st < ks) ldw(w[st], 32 * st);
+            b8 w[2][4];
+            ldw(w[0], 0);
 #pragma unroll
             for (int st = 0; st < kFusedWidth / 32; ++st) {
                 if (st < ks) {
-                    if (st + 2 < ks) ldw(w[(st + 2) % 3], 32 * (st + 2));
+                    if (st + 1 < ks) ldw(w[(st + 1) % 2], 32 * (st + 1));
 #pragma unroll
                     for (int a = 0; a < RT; ++a) {
                         const b8 af = *reinterpret_cast<const b8 *>(H + (16 * a + j) * kHStride + 32 * st + 8 * g);
 #pragma unroll
                         for (int b = 0; b < 4; ++b)
-                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, w[st % 3][b], acc[a][b], 0, 0, 0);
+                            acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[st % 2][b], af, acc[a][b], 0, 0, 0);
                     }
                 }
             }
         }
-        __syncthreads();  // every wave has read this layer's inputs
-        const float *bias = mv.b[l];
         if (!last) {
+            __syncthreads();  // every wave has read this layer's inputs
             if (mine) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const int col = n0 + 16 * b + j;
-                    const float bc = 4 * wave + b < T ? bias[col] : 0.0f;
 #pragma unroll
-                    for (int a = 0; a < RT; ++a)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)  // padding: W, b = 0 -> gelu(0) = 0
-                            H[(16 * a + 4 * g + r) * kHStride + col] = (__bf16)gelu_as(acc[a][b][r] + bc);
+                    for (int a = 0; a < RT; ++a) {  // padding: W, b = 0 -> gelu(0) = 0
+                        const b4 h = b4{(__bf16)gelu_poly(acc[a][b][0]), (__bf16)gelu_poly(acc[a][b][1]),
+                                        (__bf16)gelu_poly(acc[a][b][2]), (__bf16)gelu_poly(acc[a][b][3])};
+                        *reinterpret_cast<b4 *>(H + (16 * a + j) * kHStride + n0 + 16 * b + 4 * g) = h;
+                    }
                 }
             }
             __syncthreads();
             continue;
         }
-        // output layer: 64 rows at a time through the FP32 staging, then contiguous stores
+        // output layer: half a tile (RT / 2 row tiles) at a time through the FP32 staging,
+        // which takes the activations' bytes once every wave has read them, then contiguous
+        // complex stores
+        constexpr int HT = RT / 2, HR = 16 * HT;
+        float *Yf = reinterpret_cast<float *>(smem);  // [HR][kYStride]
+        __syncthreads();
         P2 *dst = reinterpret_cast<P2 *>(V0) + r0 * n;
         const double inv_scale = 1.0 / kOutScale;
 #pragma unroll
-        for (int half = 0; half < RT / 4; ++half) {
+        for (int half = 0; half < 2; ++half) {
             if (mine) {
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const int col = n0 + 16 * b + j;
-                    const float bc = 4 * wave + b < T ? bias[col] : 0.0f;  // the bias has 16 T entries
+                    if (4 * wave + b >= T) continue;
 #pragma unroll
-                    for (int a = 0; a < 4; ++a)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            Yf[(16 * a + 4 * g + r) * kYStride + col] = acc[4 * half + a][b][r] + bc;
+                    for (int a = 0; a < HT; ++a)
+                        *reinterpret_cast<f4 *>(Yf + (16 * a + j) * kYStride + n0 + 16 * b + 4 * g) =
+                            acc[HT * half + a][b];
                 }
             }
             __syncthreads();
-            const int64_t rows_here = valid_rows - 64 * half;
-            const int64_t valid = (rows_here < 64 ? rows_here : 64) * (int64_t)n;
-            int r = tid / n, b = tid - (tid / n) * n;
+            const int64_t rows_here = valid_rows - HR * half;
+            const int64_t valid = (rows_here < HR ? rows_here : HR) * (int64_t)n;
+            int r = tid / n, bus = tid - (tid / n) * n;
             const int dr = 256 / n, db = 256 - dr * n;
-            for (int e = tid; e < 64 * n && e < valid; e += 256) {
-                const P2 o = P2{(IO)(vs_re + (double)Yf[r * kYStride + 2 * b] * inv_scale),
-                                (IO)(vs_im + (double)Yf[r * kYStride + 2 * b + 1] * inv_scale)};
-                __builtin_nontemporal_store(o, dst + (int64_t)64 * half * n + e);
+            for (int e = tid; e < HR * n && e < valid; e += 256) {
+                const P2 o = P2{(IO)(vs_re + (double)Yf[r * kYStride + 2 * bus] * inv_scale),
+                                (IO)(vs_im + (double)Yf[r * kYStride + 2 * bus + 1] * inv_scale)};
+                __builtin_nontemporal_store(o, dst + (int64_t)HR * half * n + e);
                 r += dr;
-                b += db;
-                if (b >= n) {
-                    b -= n;
+                bus += db;
+                if (bus >= n) {
+                    bus -= n;
                     r += 1;
                 }
             }
-            __syncthreads();  // the staging is reused by the next 64 rows
+            __syncthreads();  // the staging is reused by the second half
         }
     }
 }
@@ -949,7 +980,7 @@ int predict_impl(tpf_mlp_s &M, const void *S, int32_t dtype, const int64_t *t_in
         for (int l = 0; l < M.layers + 2; ++l) mv.dp[l] = M.dp[l];
         mv.L = M.layers;
         mv.n = M.n;
-        constexpr int RT = 8;
+        constexpr int RT = 6;
         constexpr size_t lds = fused_lds<RT>();
         const unsigned blocks = (unsigned)((rows + 16 * RT - 1) / (16 * RT));
         if (dtype == TPF_C128) {
