@@ -554,7 +554,7 @@ def main():
 
     stream = torch.cuda.current_stream(dev)
 
-    def time_form(mode, mlp=None):
+    def time_form(mode, mlp=None, S=S):
         """K timed steps of one form (the solve, with the learned start evaluated by the solve
         itself for a warm form, and the FP64 mismatch), plus the dominant kernel alone: the
         sweep kernel without the mismatch pass (for a warm form, started from the network's
@@ -649,6 +649,15 @@ def main():
         for mode in ("fp64", "mixed_fp16", "mixed_bf16"):
             if want(mode + "+warm"):
                 forms[mode + "+warm"] = time_form(mode, mlp=(mlp, t_year))
+    # the same year with S in complex64 (the workload names both input types): the FP64 form,
+    # the cold and the warm mixed FP16 forms, each against the oracle on the rounded loads
+    c64 = None
+    if not wanted:
+        S64 = S.to(torch.complex64)
+        f64 = {"fp64": time_form("fp64", S=S64), "mixed_fp16": time_form("mixed_fp16", S=S64)}
+        if warm is not None:
+            f64["mixed_fp16+warm"] = time_form("mixed_fp16", mlp=(mlp, t_year), S=S64)
+        c64 = {"S": "complex64 [525600, 99]", "forms": f64}
     Vref = forms["fp64"]["V"]
     for mode, r in forms.items():
         r["max_err_vs_fp64_pu"] = float((r["V"] - Vref).abs().max())
@@ -662,6 +671,15 @@ def main():
     for mode, r in forms.items():
         r["max_err_vs_oracle_sample_pu"] = float(np.abs(r["V"][ti].cpu().numpy() - ref).max())
         del r["V"]
+    if c64 is not None:
+        S64_host = S64[ti].cpu().numpy().astype(np.complex128)
+        ref64 = oracle.fpi(onet, S64_host, 1e-10, 200).V
+        b64 = c64["forms"]["fp64"]["ms_per_step"]
+        for mode, r in c64["forms"].items():
+            r["max_err_vs_oracle_sample_pu"] = float(np.abs(r["V"][ti].cpu().numpy().astype(np.complex128) - ref64).max())
+            r["speedup_vs_fp64"] = b64 / r["ms_per_step"]
+            del r["V"]
+        del S64
     # mismatch kernel alone
     ev2 = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(3)]
     for a, b in ev2:
@@ -726,6 +744,7 @@ def main():
                                            "fp64/year100")},
         "speedup_vs_fp64_form": base["ms_per_step"] / hf["ms_per_step"],
         "forms": forms,
+        "complex64_year": c64,
         "mismatch_kernel_ms": mm_ms,
         "host_to_device_s": h2d_s,
         "input_generation_s": gen_s,
