@@ -197,6 +197,19 @@ def test_train_resume_from_file_is_bitwise(data, tmp_path):
     assert not np.array_equal(d.get_params(), pa)
 
 
+def _predict_tol(y):
+    """Allowed start-voltage error of the inference kernel, in pu.
+
+    The reference takes the BF16-rounded weights and features, so what remains is the BF16
+    rounding of the three hidden layers' activations (2^-9 relative each, random in sign)
+    and the kernel's GELU polynomial (below 1.3e-5 |z|).  Together they leave about 2^-8 of
+    the output's scale max |y| (measured 4e-3 max |y| for two random initialisations at 130
+    and 2,000 rows); the bound 2^-6 max |y| keeps a factor 4 over that, while a wrong GELU
+    coefficient or a misplaced tile errs by a sizeable fraction of |y|.  y is in the
+    network's output units (OUT_SCALE x the voltage)."""
+    return 2.0 ** -6 * np.abs(y).max() / M.OUT_SCALE
+
+
 def test_prediction_matches_reference_forward(data):
     f, net, onet, S, t, Sd, td, V = data
     sizes = W.mlp_sizes(99)
@@ -207,7 +220,7 @@ def test_prediction_matches_reference_forward(data):
     y, _ = M.forward(_ref_params(p0, sizes), sizes, bf16_round(M.features(S[:rows], t[:rows])))
     ref = M.to_voltage(y)
     err = np.abs(V0.cpu().numpy() - ref).max()
-    assert err < 5e-3 * max(1.0, np.abs(y).max() / 20), err
+    assert err < _predict_tol(y), (err, _predict_tol(y))
 
 
 def test_training_reduces_sweeps_and_keeps_results(data, tmp_path):
@@ -268,4 +281,4 @@ def test_fused_prediction_ragged_rows_and_dtypes(data, rows, dtype):
     Sh = Sx.cpu().numpy().astype(np.complex128)
     y, _ = M.forward(_ref_params(p0, sizes), sizes, bf16_round(M.features(Sh, t[-rows:])))
     err = np.abs(V0.cpu().numpy().astype(np.complex128) - M.to_voltage(y)).max()
-    assert err < 5e-3 * max(1.0, np.abs(y).max() / 20) + (1e-7 if dtype == torch.complex64 else 0.0), err
+    assert err < _predict_tol(y) + (1e-7 if dtype == torch.complex64 else 0.0), err
