@@ -11,6 +11,10 @@
 // threads share a column's buses, walking the sparse row of Y_dd (a radial feeder has
 // about three nonzeros per row, kept in LDS) against the LDS copy of V; the column's
 // maximum is a shuffle reduction over those lanes.  Only S and V cross HBM, once.
+// Complex values move through LDS as one 16-byte access each (two 8-byte accesses at a
+// 16-byte stride doubled the bank conflicts, which took about half of the LDS time), and
+// the reduction runs over |m|^2 with one square root per column (a column whose
+// mismatch exceeds 1e154 pu would read inf).
 // Networks whose CSR or columns do not fit LDS use one wavefront per column with the
 // CSR in global memory.
 #include "tpf_internal.h"
@@ -82,6 +86,8 @@ inline size_t csr_lds_bytes(int n, int nnz) {
 // Columns per tile: 16 (16 threads per column) up to 256 buses, 8 up to 512, 4 up to 1024.
 inline int tile_columns(int n) { return n <= 256 ? 16 : n <= 512 ? 8 : n <= 1024 ? 4 : 0; }
 
+typedef double d2 __attribute__((ext_vector_type(2)));  // (Re, Im) in one LDS access
+
 template <typename IO, int CB>
 __global__ __launch_bounds__(256) void mismatch_tile_kernel(const IO *__restrict__ S, const IO *__restrict__ V, int n,
                                                             long long tau, int nnz, const MismatchArgs mm) {
@@ -114,10 +120,7 @@ __global__ __launch_bounds__(256) void mismatch_tile_kernel(const IO *__restrict
 #pragma unroll
             for (int u = 0; u < kBatch; ++u) {
                 const int e = e0 + 256 * u;
-                if (e < total) {
-                    Vs[2 * e] = (double)v[u].x;
-                    Vs[2 * e + 1] = (double)v[u].y;
-                }
+                if (e < total) reinterpret_cast<d2 *>(Vs)[e] = d2{(double)v[u].x, (double)v[u].y};
             }
         }
         __syncthreads();
@@ -137,26 +140,28 @@ __global__ __launch_bounds__(256) void mismatch_tile_kernel(const IO *__restrict
                 for (int u = 0; u < kBatch; ++u) {
                     const int b = b0 + TPC * u;
                     if (b < n) {
-                        double ar = cv[2 * b], ai = cv[2 * b + 1];
+                        const d2 c = reinterpret_cast<const d2 *>(cv)[b];
+                        double ar = c.x, ai = c.y;
                         for (int k = rp[b]; k < rp[b + 1]; ++k) {
                             const int q = ci[k];
-                            const double yr = yv[2 * k], yi = yv[2 * k + 1], xr = vc[2 * q], xi = vc[2 * q + 1];
-                            ar += yr * xr - yi * xi;
-                            ai += yr * xi + yi * xr;
+                            const d2 y = reinterpret_cast<const d2 *>(yv)[k], x = reinterpret_cast<const d2 *>(vc)[q];
+                            ar += y.x * x.x - y.y * x.y;
+                            ai += y.x * x.y + y.y * x.x;
                         }
-                        const double vr = vc[2 * b], vi = vc[2 * b + 1];
+                        const d2 v = reinterpret_cast<const d2 *>(vc)[b];
+                        const double vr = v.x, vi = v.y;
                         double lr, li;
                         load_power(mm, b, (double)s[u].x, (double)s[u].y, vr, vi, lr, li);
                         const double mr = lr + vr * ar + vi * ai;
                         const double mi = li + vi * ar - vr * ai;
-                        worst = nanmax(worst, sqrt(mr * mr + mi * mi));
+                        worst = nanmax(worst, mr * mr + mi * mi);
                     }
                 }
             }
         }
 #pragma unroll
         for (int off = TPC / 2; off > 0; off >>= 1) worst = nanmax(worst, __shfl_xor(worst, off));
-        if (part == 0 && cl < cols) mm.out[c0 + cl] = worst;
+        if (part == 0 && cl < cols) mm.out[c0 + cl] = sqrt(worst);
     }
 }
 
