@@ -347,10 +347,11 @@ def bench_other(args):
     runs = [(m, m, net) for m in ("fp64", "fp32", "mixed_bf16", "mixed_fp16", "tree_fp64", "tree_fp32")]
     if zip_loads:
         runs.append(("fp64_constant_power", "fp64", tpf.Network.from_feeder(f)))
-        # a constant-impedance share as well (B differs per column): the tree forms
+        # a constant-impedance share as well (B differs per column): the tree forms eliminate
+        # it along the tree, the dense forms carry its current in the injection
         az, zi, zp = W.zipz_shares(f.n_bus - 1)
         netz = tpf.Network.from_feeder(f, alpha_i=zi, alpha_p=zp, alpha_z=az)
-        runs += [("tree_fp64_alpha_z", "tree_fp64", netz), ("tree_fp32_alpha_z", "tree_fp32", netz)]
+        runs += [(m + "_alpha_z", m, netz) for m in ("fp64", "mixed_fp16", "tree_fp64", "tree_fp32")]
         V_err_z = oracle.fpi_zip(onet, S_err, zi, zp, 1e-10, 200, alpha_z=az).V
     for key, mode, net in runs:
         out = tpf.alloc_outputs(net, S, mode, mismatch=True)

@@ -143,12 +143,15 @@ int tpf_build_network(int32_t n_bus, int32_t n_branch, const int32_t *from, cons
  *   alpha_i, alpha_p host float64 [n] per PQ bus (PQ order), finite; any values
  *                    (they need not sum to 1)
  * Without a constant-impedance share B = Y_dd for every column and the sweeps compute
- * V <- Z (alpha_P conj(S./V) + alpha_I conj(S)) + w in every mode; the FP16 form widens
- * its per-column scale by max_q |alpha_P[q]| + |alpha_I[q]| so that the larger injections
- * stay in range.  With one (some alpha_z[q] != 0) B differs per column: only the tree
- * modes solve it, on radial networks, by a per-column elimination along the tree (no
- * B^-1 is formed); the dense modes return TPF_ERR_UNSUPPORTED from the solve calls
- * (max_iter = 0 still returns the start).  Other arguments and errors as
+ * V <- Z (alpha_P conj(S./V) + alpha_I conj(S)) + w in every mode.  With one (some
+ * alpha_z[q] != 0) B differs per column.  The tree modes eliminate it per column along
+ * the tree (no B^-1 is formed: the iterates of Eq. (2) with that B); the dense modes keep
+ * the shared Z and carry the constant-impedance current in the injection,
+ * V <- Z (alpha_P conj(S./V) + alpha_I conj(S) + alpha_Z conj(S) V) + w, which has the
+ * same fixed point (other iterates; it converges while the load impedances are large
+ * against the feeder's, as in any distribution feeder).  The FP16 form widens its
+ * per-column scale by max_q |alpha_P[q]| + |alpha_I[q]| + |alpha_Z[q]| so that the larger
+ * injections stay in range.  Other arguments and errors as
  * tpf_build_network; TPF_ERR_INVALID_ARG for a NULL or non-finite share.  The mismatch
  * (options.mismatch_out, tpf_mismatch) is the balance of these loads:
  * S (alpha_P + alpha_I V + alpha_Z |V|^2) + V conj(Y_ds v_s + Y_dd V). */

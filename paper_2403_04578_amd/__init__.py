@@ -106,7 +106,8 @@ class Network:
     With alpha_i / alpha_p (per PQ bus, or scalars) the loads follow Eq. (2)'s ZIP model
     with constant-current and constant-power shares; a non-zero constant-impedance share
     alpha_z makes B = diag(alpha_Z s*) + Y_dd differ per column, which the tree modes
-    solve (radial, single-phase networks) and the dense modes refuse."""
+    eliminate along the tree (radial, single-phase networks) and the dense modes carry as
+    the current alpha_Z conj(S) V in the injection (the same fixed point)."""
 
     def __init__(self, n_bus: int, frm, to, r, x, slack: int = 0, vs: complex = 1.0 + 0.0j,
                  alpha_i=None, alpha_p=None, alpha_z=None):

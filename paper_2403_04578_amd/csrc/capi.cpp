@@ -62,10 +62,6 @@ int solve_impl(tpf_network net, const void *S, int32_t dtype, int64_t T, double 
     if (mode < TPF_MODE_FP64 || mode > TPF_MODE_TREE_FP32) return fail(TPF_ERR_INVALID_ARG, "unknown mode");
     if (mode != TPF_MODE_FP64 && mode != TPF_MODE_TREE_FP64 && tol < 5e-7)
         return fail(TPF_ERR_INVALID_ARG, "tol below the FP32 state floor (5e-7 pu) in a reduced-precision mode");
-    if (!net->alpha_z.empty() && !is_tree(mode) && max_iter > 0)
-        return fail(TPF_ERR_UNSUPPORTED,
-                    "a constant-impedance share makes B = diag(alpha_Z s*) + Y_dd differ per column; only the tree "
-                    "modes (radial networks) solve it");
     const void *V0 = opts ? opts->V0 : nullptr;
     tpf_mlp mlp = opts ? opts->warm_start : nullptr;
     if (V0 && mlp) return fail(TPF_ERR_INVALID_ARG, "give either V0 or a warm-start network, not both");

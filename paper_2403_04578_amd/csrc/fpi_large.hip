@@ -84,13 +84,19 @@ __global__ void init_kernel(const IO *__restrict__ V0, const double *__restrict_
     }
 }
 
-// I = conj(S./V), or alpha_P conj(S./V) + alpha_I conj(S) for ZIP loads (aP, aI non-NULL),
-// at bus b of column c; zero on the K padding (b >= n).
+// ZIP shares of Eq. (2) per PQ bus: all NULL for constant-power loads; aZ NULL when no
+// bus has a constant-impedance share.
+struct ZipShares {
+    const double *aP, *aI, *aZ;
+};
+
+// I = conj(S./V), or for ZIP loads alpha_P conj(S./V) + alpha_I conj(S) + alpha_Z conj(S) V
+// (the constant-impedance current, carried in the injection: the same fixed point as
+// eliminating diag(alpha_Z s*) into Y_dd), at bus b of column c; zero on the K padding.
 template <typename T, typename IO>
 __device__ __forceinline__ void injection_at(const IO *__restrict__ S, const T *__restrict__ x,
                                              const double *__restrict__ w, int n, long long c, int b,
-                                             const double *__restrict__ aP, const double *__restrict__ aI, T &ir,
-                                             T &ii) {
+                                             const ZipShares zs, T &ir, T &ii) {
     ir = 0, ii = 0;
     if (b >= n) return;
     const double sr = (double)S[2 * (c * n + b)], si = (double)S[2 * (c * n + b) + 1];
@@ -98,10 +104,15 @@ __device__ __forceinline__ void injection_at(const IO *__restrict__ S, const T *
     if constexpr (sizeof(T) == 4) vr += w[2 * b], vi += w[2 * b + 1];
     const double inv = 1.0 / (vr * vr + vi * vi);
     double jr = (sr * vr + si * vi) * inv, ji = (sr * vi - si * vr) * inv;
-    if (aP) {
-        const double ap = aP[b], ai = aI[b];
+    if (zs.aP) {
+        const double ap = zs.aP[b], ai = zs.aI[b];
         jr = ap * jr + ai * sr;
         ji = ap * ji - ai * si;
+        if (zs.aZ) {
+            const double az = zs.aZ[b];
+            jr += az * (sr * vr + si * vi);
+            ji += az * (sr * vi - si * vr);
+        }
     }
     ir = (T)jr;
     ii = (T)ji;
@@ -111,7 +122,7 @@ __device__ __forceinline__ void injection_at(const IO *__restrict__ S, const T *
 template <typename T, typename IO>
 __global__ void inject_kernel(const IO *__restrict__ S, const T *__restrict__ x, const double *__restrict__ w, int n,
                               int KP, const long long *__restrict__ act, const int *__restrict__ na, int rows,
-                              const double *__restrict__ aP, const double *__restrict__ aI, T *__restrict__ B) {
+                              const ZipShares zs, T *__restrict__ B) {
     const long long total = (long long)rows * KP;
     const int nact = *na;
     for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total / 2;
@@ -119,7 +130,7 @@ __global__ void inject_kernel(const IO *__restrict__ S, const T *__restrict__ x,
         const long long a = e / (KP / 2);
         const int b = (int)(e - a * (KP / 2));
         T ir = 0, ii = 0;
-        if (a < nact) injection_at<T, IO>(S, x, w, n, act[a], b, aP, aI, ir, ii);
+        if (a < nact) injection_at<T, IO>(S, x, w, n, act[a], b, zs, ir, ii);
         B[a * KP + 2 * b] = ir;
         B[a * KP + 2 * b + 1] = ii;
     }
@@ -272,8 +283,8 @@ __device__ __forceinline__ int chunk_slot(bool stay, int *counter, int *wsum, in
 template <typename T, typename IO>
 __global__ __launch_bounds__(256) void finish_kernel(
     const long long *__restrict__ act, const int *__restrict__ cnt, int *cnt_clear, const IO *__restrict__ S,
-    const T *__restrict__ x, const double *__restrict__ w, int n, int KP, const double *__restrict__ aP,
-    const double *__restrict__ aI, double tol, int max_iter, unsigned long long *__restrict__ dmax,
+    const T *__restrict__ x, const double *__restrict__ w, int n, int KP, const ZipShares zs, double tol,
+    int max_iter, unsigned long long *__restrict__ dmax,
     const int *__restrict__ badf, int32_t *iters, int8_t *status, IO *__restrict__ V,
     long long *__restrict__ act_next, int *cnt_next, T *__restrict__ B, int *done_flag, int seq, int cpb) {
     __shared__ long long col_s[256];
@@ -321,7 +332,7 @@ __global__ __launch_bounds__(256) void finish_kernel(
                 T *Br = B + (long long)sl * KP;
                 for (int b = lane; b < KP / 2; b += 64) {
                     T ir, ii;
-                    injection_at<T, IO>(S, x, w, n, cc, b, aP, aI, ir, ii);
+                    injection_at<T, IO>(S, x, w, n, cc, b, zs, ir, ii);
                     Br[2 * b] = ir;
                     Br[2 * b + 1] = ii;
                 }
@@ -384,8 +395,8 @@ struct Low16<TPF_MODE_MIXED_FP16> {
     }
 };
 
-// One wave per column: FP16 scale from max |S| (times zscale = max |alpha_P| + |alpha_I|
-// for ZIP loads) and the initial schedule state.
+// One wave per column: FP16 scale from max |S| (times zscale = max |alpha_P| + |alpha_I| +
+// |alpha_Z| for ZIP loads) and the initial schedule state.
 template <int MODE, typename IO>
 __global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, int sZ, float zscale, MixState *ms,
                                 unsigned *umax) {
@@ -424,23 +435,30 @@ __global__ void init_mix_kernel(const IO *__restrict__ S, int n, long long tau, 
     }
 }
 
-// alpha_P conj(S./V) + alpha_I conj(S) for ZIP loads (aP, aI non-NULL), else conj(S./V).
-__device__ __forceinline__ float2 zip_injection(float ir, float ii, float sr, float si, const double *aP,
-                                                const double *aI, int b) {
-    if (!aP) return make_float2(ir, ii);
-    const float ap = (float)aP[b], ai = (float)aI[b];
-    return make_float2(ap * ir + ai * sr, ap * ii - ai * si);
+// alpha_P conj(S./V) + alpha_I conj(S) + alpha_Z conj(S) V for ZIP loads, else conj(S./V)
+// (given as ir, ii).
+__device__ __forceinline__ float2 zip_injection(float ir, float ii, float sr, float si, float vr, float vi,
+                                                const ZipShares &zs, int b) {
+    if (!zs.aP) return make_float2(ir, ii);
+    const float ap = (float)zs.aP[b], ai = (float)zs.aI[b];
+    float2 o = make_float2(ap * ir + ai * sr, ap * ii - ai * si);
+    if (zs.aZ) {
+        const float az = (float)zs.aZ[b];
+        o.x += az * (sr * vr + si * vi);
+        o.y += az * (sr * vi - si * vr);
+    }
+    return o;
 }
 
 // FP32 injection of column c at bus b (o = 2 (c n + b)) from U = V - w.
 template <typename IO>
 __device__ __forceinline__ float2 injection32(const IO *__restrict__ S, const float *__restrict__ U,
                                               const double *__restrict__ w, long long o, int b,
-                                              const double *__restrict__ aP, const double *__restrict__ aI) {
+                                              const ZipShares &zs) {
     const float sr = (float)S[o], si = (float)S[o + 1];
     const float vr = (float)w[2 * b] + U[o], vi = (float)w[2 * b + 1] + U[o + 1];
     const float r = 1.0f / fmaxf(vr * vr + vi * vi, kMinV2);
-    return zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, aP, aI, b);
+    return zip_injection((sr * vr + si * vi) * r, (sr * vi - si * vr) * r, sr, si, vr, vi, zs, b);
 }
 
 // 16-bit B entry of a low-list column: I 2^sB on a full sweep (ph = 0), (I - I_prev) 2^sB
@@ -463,7 +481,7 @@ __global__ void inject_low_kernel(const IO *__restrict__ S, const float *__restr
                                   const double *__restrict__ w, float *__restrict__ Ip,
                                   const MixState *__restrict__ ms, int n, int KP16,
                                   const long long *__restrict__ act, const int *__restrict__ na, int rows,
-                                  const double *__restrict__ aP, const double *__restrict__ aI,
+                                  const ZipShares zs,
                                   uint32_t *__restrict__ B) {
     const int nact = *na;
     const int half = KP16 / 2;
@@ -474,7 +492,7 @@ __global__ void inject_low_kernel(const IO *__restrict__ S, const float *__restr
         uint32_t out = 0u;
         if (a < nact && b < n) {
             const long long c = act[a], o = 2 * (c * n + b);
-            out = low_entry<MODE>(injection32(S, U, w, o, b, aP, aI), reinterpret_cast<float2 *>(Ip + o), ms[c].ph,
+            out = low_entry<MODE>(injection32(S, U, w, o, b, zs), reinterpret_cast<float2 *>(Ip + o), ms[c].ph,
                                   ms[c].ks);
         }
         B[a * half + b] = out;
@@ -614,7 +632,7 @@ template <int MODE, typename IO>
 __global__ __launch_bounds__(256) void finish_mixed_kernel(
     const long long *__restrict__ actR, const long long *__restrict__ actL, const int *__restrict__ cnt,
     int *cnt_clear, const IO *__restrict__ S, const float *__restrict__ U, const double *__restrict__ w, int n,
-    int KP, int KP16, const double *__restrict__ aP, const double *__restrict__ aI, float tol, int max_iter,
+    int KP, int KP16, const ZipShares zs, float tol, int max_iter,
     unsigned long long *__restrict__ dmax, unsigned *__restrict__ umax, const int *__restrict__ badf,
     MixState *__restrict__ ms, int32_t *iters, int8_t *status, IO *__restrict__ V, float *__restrict__ Ip,
     long long *__restrict__ nextR, long long *__restrict__ nextL, int *cnt_next, float *__restrict__ B32,
@@ -695,7 +713,7 @@ __global__ __launch_bounds__(256) void finish_mixed_kernel(
                     float2 iz = make_float2(0.f, 0.f);
                     if (b < n) {
                         const long long o = 2 * (cc * n + b);
-                        iz = injection32(S, U, w, o, b, aP, aI);
+                        iz = injection32(S, U, w, o, b, zs);
                         *reinterpret_cast<float2 *>(Ip + o) = iz;
                     }
                     Br[b] = iz;
@@ -708,7 +726,7 @@ __global__ __launch_bounds__(256) void finish_mixed_kernel(
                     uint32_t out = 0u;
                     if (b < n) {
                         const long long o = 2 * (cc * n + b);
-                        out = low_entry<MODE>(injection32(S, U, w, o, b, aP, aI), reinterpret_cast<float2 *>(Ip + o),
+                        out = low_entry<MODE>(injection32(S, U, w, o, b, zs), reinterpret_cast<float2 *>(Ip + o),
                                               ph, kss);
                     }
                     Br[b] = out;
@@ -792,7 +810,7 @@ static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *
     hipLaunchKernelGGL((init_kernel<T, IO>), dim3((unsigned)((tau + 3) / 4)), dim3(256), 0, st, (const IO *)V0, w, n,
                        (long long)tau, x, iters, act[0], cnt, dmax);
     hipLaunchKernelGGL((inject_kernel<T, IO>), dim3((unsigned)std::min<long long>(65536, (rows * KP / 2 + 255) / 256)),
-                       dim3(256), 0, st, (const IO *)S, x, w, n, KP, act[0], cnt, (int)rows, dn.aP, dn.aI, B);
+                       dim3(256), 0, st, (const IO *)S, x, w, n, KP, act[0], cnt, (int)rows, ZipShares{dn.aP, dn.aI, dn.aZ}, B);
     // Every sweep is queued without waiting, with grids fixed from tau: the active counts
     // stay on the device (three of them in rotation: read, appended, cleared) and the
     // kernels of a sweep with no active column exit at once.  Queueing stops early when
@@ -809,7 +827,7 @@ static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *
         hipLaunchKernelGGL((gemm_kernel<T>), dim3(g_mm), dim3(256), 0, st, A, KP, B, act[cur], cr, row_blocks, w, n, x,
                            dmax, badf);
         hipLaunchKernelGGL((finish_kernel<T, IO>), dim3(g_fin), dim3(256), 0, st, act[cur], cr, cz, (const IO *)S, x, w,
-                           n, KP, dn.aP, dn.aI, tol, max_iter, dmax, badf, iters, status, (IO *)V, act[cur ^ 1], cn,
+                           n, KP, ZipShares{dn.aP, dn.aI, dn.aZ}, tol, max_iter, dmax, badf, iters, status, (IO *)V, act[cur ^ 1], cn,
                            B, dn.done_dev, seq, cpb);
     }
     return TPF_OK;
@@ -863,7 +881,7 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
                        n, (long long)tau, dn.sZ, dn.aP ? dn.zscale : 1.0f, ms, umax);
     hipLaunchKernelGGL((inject_low_kernel<MODE, IO>),
                        dim3((unsigned)std::min<long long>(65536, (rows16 * K16 / 2 + 255) / 256)), dim3(256), 0, st,
-                       (const IO *)S, U, w, Ip, ms, n, K16, actL[0], cnt, (int)rows16, dn.aP, dn.aI,
+                       (const IO *)S, U, w, Ip, ms, n, K16, actL[0], cnt, (int)rows16, ZipShares{dn.aP, dn.aI, dn.aZ},
                        reinterpret_cast<uint32_t *>(B16));
     // Queued at once as in run_large; counts in pairs {low, refine}, three pairs in rotation.
     const unsigned g_r = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 64) * (rows / 64));
@@ -881,7 +899,7 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
         hipLaunchKernelGGL((gemm_low_kernel<MODE>), dim3(g_l), dim3(256), 0, st, A16, K16, B16, actL[cur], cc, ms, n,
                            U, dmax, umax, badf, MP / 128);
         hipLaunchKernelGGL((finish_mixed_kernel<MODE, IO>), dim3(g_fin), dim3(256), 0, st, actR[cur], actL[cur], cc, cz,
-                           (const IO *)S, U, w, n, KP, K16, dn.aP, dn.aI, (float)tol, max_iter, dmax, umax, badf, ms,
+                           (const IO *)S, U, w, n, KP, K16, ZipShares{dn.aP, dn.aI, dn.aZ}, (float)tol, max_iter, dmax, umax, badf, ms,
                            iters, status, (IO *)V, Ip, actR[cur ^ 1], actL[cur ^ 1], cn, B32,
                            reinterpret_cast<uint32_t *>(B16), dn.done_dev, seq, cpb);
     }

@@ -98,15 +98,16 @@ struct ColState {
 
 // PF (FP16 form only): 1 = the rows of S of each batch are staged in LDS, the next batch's
 // copied while the current one sweeps; 2 = the rows of V0 as well.  ZIP: loads of Eq. (2)
-// with constant-current and constant-power shares (aP, aI per bus; zscale = max_b
-// |alpha_P| + |alpha_I| bounds the injection for the FP16 column scale).
+// with constant-power, constant-current and constant-impedance shares (aP, aI, aZ per bus,
+// aZ possibly NULL; zscale = max_b |alpha_P| + |alpha_I| + |alpha_Z| bounds the injection
+// for the FP16 column scale while 1/4 < |V| < 4).
 template <int TPW, int NW, int KTL, int MODE, int CG, int PF, bool ZIP, typename IO>
 __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const float *__restrict__ A32,
     const uint16_t *__restrict__ Alow, const uint16_t *__restrict__ Alo, const double *__restrict__ wv, int n,
     int MT, int sZ, long long tau, float tol, int max_iter, unsigned long long *__restrict__ queue,
-    const double *__restrict__ aP, const double *__restrict__ aI, float zscale) {
+    const double *__restrict__ aP, const double *__restrict__ aI, const double *__restrict__ aZ, float zscale) {
     using L = LowOps<MODE>;
     typedef typename L::frag frag;
     typedef typename L::quad quad;
@@ -136,7 +137,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
     // batch sweeps
     IO *Spf = reinterpret_cast<IO *>(wl + 16 * MT);                                   // [NC][n][2]
     IO *Vpf = Spf + (size_t)NC * n * 2;                                               // [NC][n][2]
-    // ZIP shares [2][8 MT] (alpha_P, then alpha_I; padding buses 0), after the row copies
+    // ZIP shares [3][8 MT] (alpha_P, alpha_I, alpha_Z; padding buses 0), after the row copies
     float *zl = reinterpret_cast<float *>(Spf + (size_t)NC * n * 2 * (kSplit ? PF : 0));
 
     const int tid = threadIdx.x;
@@ -155,6 +156,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
         for (int e = tid; e < 8 * MT; e += NT) {
             zl[e] = e < n ? (float)aP[e] : 0.0f;
             zl[8 * MT + e] = e < n ? (float)aI[e] : 0.0f;
+            zl[16 * MT + e] = e < n && aZ ? (float)aZ[e] : 0.0f;
         }
     }
 
@@ -208,11 +210,17 @@ __global__ __launch_bounds__(NW * 64) void fpi_mixed_kernel(
             for (int q = 0; q < TPW; ++q) {
                 const f4 sv = q < nv ? Sx[(c * MT + tw + NW * q) * 64 + lane] : f4{0, 0, 0, 0};
                 f4 In = inject(sv, Wq[q], U[c][q], ks[c]);
-                if (ZIP && q < nv) {  // alpha_P conj(S./V) + alpha_I conj(S), both scaled
+                if (ZIP && q < nv) {
+                    // alpha_P conj(S./V) + alpha_I conj(S) + alpha_Z conj(S) V, all scaled
                     const int b0 = 8 * (tw + NW * q) + 2 * g;
-                    const float p0 = zl[b0], p1 = zl[b0 + 1], i0 = zl[8 * MT + b0] * ks[c], i1 = zl[8 * MT + b0 + 1] * ks[c];
-                    In = f4{p0 * In[0] + i0 * sv[0], p0 * In[1] - i0 * sv[1], p1 * In[2] + i1 * sv[2],
-                            p1 * In[3] - i1 * sv[3]};
+                    const float p0 = zl[b0], p1 = zl[b0 + 1];
+                    const float i0 = zl[8 * MT + b0] * ks[c], i1 = zl[8 * MT + b0 + 1] * ks[c];
+                    const float z0 = zl[16 * MT + b0] * ks[c], z1 = zl[16 * MT + b0 + 1] * ks[c];
+                    const f4 v = Wq[q] + U[c][q];
+                    In = f4{p0 * In[0] + i0 * sv[0] + z0 * (sv[0] * v[0] + sv[1] * v[1]),
+                            p0 * In[1] - i0 * sv[1] + z0 * (sv[0] * v[1] - sv[1] * v[0]),
+                            p1 * In[2] + i1 * sv[2] + z1 * (sv[2] * v[2] + sv[3] * v[3]),
+                            p1 * In[3] - i1 * sv[3] + z1 * (sv[2] * v[3] - sv[3] * v[2])};
                 }
                 if (q < nv) {
                     const f4 bv = dif[c] ? In - Ip[c][q] : In;
@@ -604,7 +612,7 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     const bool zip = dn.aP != nullptr;
     const size_t lds0 = (split ? 0 : NC * KP32 * 4) + (mixed ? NC * KPL * 2 * (split ? 2 : 1) : 0) +
                         (size_t)CG * MT * 64 * 16 + NC * (16 + 8 + 8) + 2 * NC * sizeof(ColState) + 32 +
-                        (size_t)16 * MT * 8 + (zip ? (size_t)16 * MT * 4 : 0);
+                        (size_t)16 * MT * 8 + (zip ? (size_t)24 * MT * 4 : 0);
     // The next batch's S is prefetched into LDS when it fits beside the rest, and its V0
     // too when that also fits (the copies write exactly the rows' bytes).
     // (measured: it pays in the FP16 form, not in the BF16 one, whose registers it raises)
@@ -635,7 +643,7 @@ static int launch_one(const tpf_network_s &net, const DeviceNet &dn, const void 
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.A32, MODE == TPF_MODE_MIXED_BF16 ? dn.Abf : dn.Ah, dn.Al,
                        dn.w64, net.n, MT, dn.sZ, (long long)tau, (float)tol, max_iter, queue, dn.aP, dn.aI,
-                       dn.zscale);
+                       dn.aZ, dn.zscale);
     return TPF_OK;
 }
 

@@ -51,8 +51,8 @@ struct SlotState {
 };
 
 // Writes the injection conj(S./V) of the lane's two buses 8t+g and 8t+g+4; for ZIP loads
-// (Eq. (2), alpha_Z = 0) alpha_P conj(S./V) + alpha_I conj(S), with the shares staged in
-// LDS as zl[2][8 MT] (alpha_P, then alpha_I).
+// (Eq. (2)) alpha_P conj(S./V) + alpha_I conj(S) + alpha_Z conj(S) V, with the shares
+// staged in LDS as zl[3][8 MT] (alpha_P, alpha_I, alpha_Z).
 template <bool ZIP>
 __device__ __forceinline__ void put_injection(double *Ib, int t, int lane, const d4 &vv, const d4 &ss,
                                               const double *zl, int MT) {
@@ -64,9 +64,9 @@ __device__ __forceinline__ void put_injection(double *Ib, int t, int lane, const
         double ir = (sr * vr + si * vi) * inv, ii = (sr * vi - si * vr) * inv;  // conj(S/V)
         if constexpr (ZIP) {
             const int b = 8 * t + g + 4 * h;
-            const double ap = zl[b], ai = zl[8 * MT + b];
-            ir = ap * ir + ai * sr;
-            ii = ap * ii - ai * si;
+            const double ap = zl[b], ai = zl[8 * MT + b], az = zl[16 * MT + b];
+            ir = ap * ir + ai * sr + az * (sr * vr + si * vi);
+            ii = ap * ii - ai * si + az * (sr * vi - si * vr);
         }
         Ib[256 * t + 64 * h + lane] = ir;        // Re, row 16t+g+4h
         Ib[256 * t + 64 * (h + 2) + lane] = ii;  // Im, row 16t+g+8+4h
@@ -131,14 +131,15 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
     const IO *__restrict__ S, IO *__restrict__ Vout, int32_t *__restrict__ iters_out,
     int8_t *__restrict__ status_out, const IO *__restrict__ V0, const double *__restrict__ A,
     const double *__restrict__ wv, int n, int MT, long long tau, double tol, int max_iter,
-    unsigned long long *__restrict__ queue, const double *__restrict__ aP, const double *__restrict__ aI) {
+    unsigned long long *__restrict__ queue, const double *__restrict__ aP, const double *__restrict__ aI,
+    const double *__restrict__ aZ) {
     extern __shared__ double lds[];
     double *Ib = lds;                                 // [16*MT][16]
     double *part = lds + 256 * MT;                    // [NW][16] partial max |dV|^2
     int *flag = reinterpret_cast<int *>(part + NW * 16);  // [NW][16] partial non-finite / guard flags
     unsigned long long *qb = reinterpret_cast<unsigned long long *>(flag + NW * 16);
     double *wl = reinterpret_cast<double *>(qb + 2);   // [2][8*MT] w staged once
-    double *zl = wl + 16 * MT;                         // [2][8*MT] ZIP shares (ZIP only)
+    double *zl = wl + 16 * MT;                         // [3][8*MT] ZIP shares (ZIP only)
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
@@ -207,6 +208,7 @@ __global__ __launch_bounds__(NW * 64) void fpi_f64_kernel(
         for (int e = threadIdx.x; e < 8 * MT; e += NW * 64) {
             zl[e] = e < n ? aP[e] : 0.0;
             zl[8 * MT + e] = e < n ? aI[e] : 0.0;
+            zl[16 * MT + e] = e < n && aZ ? aZ[e] : 0.0;
         }
     }
     // Initial fill: 16 consecutive queue entries per workgroup.
@@ -350,7 +352,7 @@ static int launch_rows_as(const tpf_network_s &net, const DeviceNet &dn, const v
                           unsigned long long *queue, hipStream_t stream) {
     const int MT = dn.MT;
     const size_t lds = (size_t)256 * MT * sizeof(double) + (size_t)NW * 16 * (sizeof(double) + sizeof(int)) + 16 +
-                       (size_t)(ZIP ? 32 : 16) * MT * sizeof(double);
+                       (size_t)(ZIP ? 40 : 16) * MT * sizeof(double);
     auto kern = fpi_f64_kernel<TPW, NW, ZIP, IO>;
     if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
         return fail(TPF_ERR_DEVICE, "hipFuncSetAttribute failed");
@@ -360,7 +362,7 @@ static int launch_rows_as(const tpf_network_s &net, const DeviceNet &dn, const v
     const long long blocks = std::min<long long>((long long)num_cus() * per_cu, (tau + 15) / 16);
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, (const IO *)S, (IO *)V, iters,
                        status, (const IO *)V0, dn.A64, dn.w64, net.n, MT, (long long)tau, tol, max_iter, queue,
-                       (const double *)dn.aP, (const double *)dn.aI);
+                       (const double *)dn.aP, (const double *)dn.aI, (const double *)dn.aZ);
     return TPF_OK;
 }
 

@@ -300,7 +300,9 @@ static int upload(tpf_network_s &net, DeviceNet &dn) {
         if (!h2d(dn.aI, net.alpha_i.data(), n * 8) || !h2d(dn.aP, net.alpha_p.data(), n * 8))
             return fail(TPF_ERR_DEVICE, "host-to-device copy failed (ZIP shares)");
         double zs = 0.0;
-        for (int q = 0; q < n; ++q) zs = std::max(zs, std::fabs(net.alpha_p[q]) + std::fabs(net.alpha_i[q]));
+        for (int q = 0; q < n; ++q)
+            zs = std::max(zs, std::fabs(net.alpha_p[q]) + std::fabs(net.alpha_i[q]) +
+                                  (net.alpha_z.empty() ? 0.0 : std::fabs(net.alpha_z[q])));
         dn.zscale = (float)zs;
         if (!net.alpha_z.empty()) {
             if (!dalloc((void **)&dn.aZ, n * 8)) return fail(TPF_ERR_OOM, "device allocation failed (ZIP shares)");

@@ -80,8 +80,8 @@ struct DeviceNet {
     int32_t *tree_i = nullptr;
     double *tree_z = nullptr;
     double *aI = nullptr, *aP = nullptr;  // [n] each
-    double *aZ = nullptr;                 // [n], only when some alpha_Z != 0 (tree operator)
-    float zscale = 1.0f;                  // max_b |alpha_P| + |alpha_I| (bounds |I| / |S| with |V|)
+    double *aZ = nullptr;                 // [n], only when some alpha_Z != 0
+    float zscale = 1.0f;                  // max_b |alpha_P| + |alpha_I| + |alpha_Z| (bounds |I| / |S| with |V|)
     std::vector<void *> owned;   // every allocation above, freed with the network
 };
 
@@ -110,8 +110,8 @@ struct tpf_network_s {
     std::vector<tpf::cd> c;
     // ZIP loads (Eq. (2)): shares of constant current and constant power per PQ bus; empty
     // for constant-power loads.  alpha_z (constant impedance) is empty unless some share
-    // is non-zero: then B = diag(alpha_Z s*) + Y_dd differs per column, which only the
-    // tree operator solves (per column, without forming B^-1).
+    // is non-zero: the tree operator then eliminates B = diag(alpha_Z s*) + Y_dd per column
+    // along the tree, the dense forms carry the current alpha_Z conj(S) V in the injection.
     bool zip = false;
     std::vector<double> alpha_i, alpha_p, alpha_z;
     // Breadth-first tree of a radial single-phase network (empty otherwise): per position
