@@ -537,3 +537,28 @@ def test_3ph_balanced_transposed_line_is_its_positive_sequence():
     # the coupling matters: the same loads on uncoupled phases with z_self land elsewhere
     loose = oracle.build_network(f1.n_bus, f1.frm, f1.to, zs.real, zs.imag)
     assert np.abs(oracle.fpi(loose, S1, 1e-13, 200).V - r1.V).max() > 1e-4
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_zipz_injection_splitting_has_the_same_fixed_point(seed):
+    """The dense forms keep the shared Z and w and carry the constant-impedance current in
+    the injection, V <- Z (alpha_P conj(S./V) + alpha_I conj(S) + alpha_Z conj(S) V) + w,
+    instead of eliminating diag(alpha_Z s*) into B per column.  Written out here with plain
+    numpy from a flat start, that iteration lands on the oracle's per-column-B solution
+    (other iterates, the same fixed point), at three times the base load."""
+    f = W.make_feeder(60, load_scale=3.0)
+    net = oracle.build_feeder(f)
+    S = W.profile_daily96(f, steps=12)
+    sh = np.random.default_rng(seed).dirichlet([1.0, 1.0, 1.0], net.n)
+    az, ai, ap = sh[:, 0], sh[:, 1], sh[:, 2]
+    ref = oracle.fpi_zip(net, S, ai, ap, 1e-13, 200, alpha_z=az)
+    assert np.all(ref.status == oracle.ST_CONVERGED)
+    V = np.ones_like(S)
+    for _ in range(200):
+        inj = ap * np.conj(S / V) + ai * np.conj(S) + az * np.conj(S) * V
+        Vn = inj @ net.Z.T + net.w
+        step, V = np.abs(Vn - V).max(), Vn
+        if step < 1e-14:
+            break
+    assert step < 1e-14
+    assert np.abs(V - ref.V).max() < 1e-11
