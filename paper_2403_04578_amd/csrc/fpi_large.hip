@@ -12,6 +12,8 @@
 // sweep is queued without waiting on the device: the active counts stay there.
 #include "tpf_internal.h"
 
+#include <algorithm>
+
 namespace tpf {
 
 typedef double d4x __attribute__((ext_vector_type(4)));
@@ -759,6 +761,22 @@ static int finish_chunk(int n) {
 // sweep with nothing left to do costs little.
 constexpr int64_t kGemmGrid = 1024, kFinishGrid = 1024;
 
+// Grid of a persistent GEMM: at most kGemmGrid blocks and no more than are resident at
+// once (CUs x blocks per CU).  Its blocks share the tiles evenly, so blocks beyond the
+// resident ones would start only after others had finished all of theirs and run the
+// kernel's second half at a fraction of the occupancy (the 16-bit GEMM, three blocks per
+// CU for its 43 KB of LDS, took twice as long with 1,024 blocks).
+template <typename Kernel>
+static int64_t gemm_grid(Kernel kernel, int64_t tiles) {
+    int dev = 0, cus = 256, per_cu = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)kernel, 256, 0) != hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    return std::max<int64_t>(1, std::min<int64_t>({kGemmGrid, (int64_t)cus * per_cu, tiles}));
+}
+
 // Workspace of the large path: state [tau][2n] (T), B operand [tau rounded to 64][KP] (T),
 // dmax [tau] (u64), bad flags [tau] (int), two active lists [tau] (i64), counters.
 // Mixed modes add I_prev [tau][2n] (FP32), the 16-bit B operand [tau rounded to 128][KP16],
@@ -816,7 +834,7 @@ static int run_large(const tpf_network_s &net, const DeviceNet &dn, const void *
     // kernels of a sweep with no active column exit at once.  Queueing stops early when
     // the device has already posted that none is left (all_retired).
     const int row_blocks = MP / 64;
-    const unsigned g_mm = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)row_blocks * (rows / 64));
+    const unsigned g_mm = (unsigned)gemm_grid(gemm_kernel<T>, (int64_t)row_blocks * (rows / 64));
     const int cpb = finish_chunk(n);
     const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + cpb - 1) / cpb);
     const int seq = ++dn.solve_seq;
@@ -884,8 +902,8 @@ static int run_large_mixed(const tpf_network_s &net, const DeviceNet &dn, const 
                        (const IO *)S, U, w, Ip, ms, n, K16, actL[0], cnt, (int)rows16, ZipShares{dn.aP, dn.aI, dn.aZ},
                        reinterpret_cast<uint32_t *>(B16));
     // Queued at once as in run_large; counts in pairs {low, refine}, three pairs in rotation.
-    const unsigned g_r = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 64) * (rows / 64));
-    const unsigned g_l = (unsigned)std::min<int64_t>(kGemmGrid, (int64_t)(MP / 128) * (rows16 / 128));
+    const unsigned g_r = (unsigned)gemm_grid(gemm_kernel<float>, (int64_t)(MP / 64) * (rows / 64));
+    const unsigned g_l = (unsigned)gemm_grid(gemm_low_kernel<MODE>, (int64_t)(MP / 128) * (rows16 / 128));
     const int cpb = finish_chunk(n);
     const unsigned g_fin = (unsigned)std::min<int64_t>(kFinishGrid, (tau + cpb - 1) / cpb);
     const int seq = ++dn.solve_seq;
