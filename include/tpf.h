@@ -232,7 +232,9 @@ int tpf_solve_timeseries_noalloc(tpf_network net, const void *S, int32_t dtype, 
 
 /* FP64 power-balance mismatch of given voltages (Eq. (1)):
  * out[c] = max_i |S_ci + V_ci conj((Y_ds v_s)_i + (Y_dd V_c)_i)|
- * (for a ZIP network the load term S_ci is S_ci (alpha_P,i + alpha_I,i V_ci)).
+ * (for a ZIP network the load term S_ci is S_ci (alpha_P,i + alpha_I,i V_ci +
+ * alpha_Z,i |V_ci|^2)).  NaN when a term is NaN; the maximum is taken over |.|^2, so a
+ * mismatch above about 1e154 pu reads inf.
  *   S, V   device [tau][n], dtype TPF_C64 or TPF_C128;  out  device float64 [tau]. */
 int tpf_mismatch(tpf_network net, const void *S, const void *V, int32_t dtype, int64_t tau,
                  double *out, void *stream);
