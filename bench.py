@@ -746,6 +746,13 @@ def main():
         "speedup_vs_fp64_form": base["ms_per_step"] / hf["ms_per_step"],
         "forms": forms,
         "complex64_year": c64,
+        # the paper's own figures for this workload (Table I): context on other hardware
+        "paper_context": {
+            "speedup_of_tensor_dense_vs_sparse_nr": 164,
+            "tensor_dense_cpu_min": 0.37, "tensor_gpu_min": 1.30, "nr_sparse_min": 61.85,
+            "hardware": "Intel Core i7-7700HQ (8 logical processors) and NVIDIA Quadro M1200 (4 GB)",
+            "workload": "100-bus k-ary feeder, 525,600 one-minute power flows, copula load profiles",
+            "note": "context, not the target: other hardware, other loads, precision not stated"},
         "mismatch_kernel_ms": mm_ms,
         "host_to_device_s": h2d_s,
         "input_generation_s": gen_s,
