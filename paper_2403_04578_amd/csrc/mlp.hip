@@ -249,8 +249,9 @@ __global__ void frag_kernel(const float *__restrict__ p, int64_t woff, int64_t b
 // one k-step ahead.  The weights are the products' A operand, so a lane's four outputs of
 // a tile are consecutive neurons of one row: a hidden layer's leave as one 8-byte LDS
 // store.  RT = 6 (96 rows, 50.7 KB of LDS) lets three workgroups share a CU, at most 168
-// VGPRs each; 128-row tiles at two per CU measured 0.62 ms against 0.54 ms for the 100-bus
-// year, 64-row tiles at four per CU 0.61 ms.  The first layer's inputs and the output
+// VGPRs each (three dwords per lane spill to scratch at that cap); 128-row tiles at two per
+// CU, spill-free, measured 0.62 ms against 0.54 ms for the 100-bus year, 64-row tiles at
+// four per CU 0.61 ms.  The first layer's inputs and the output
 // layer's neurons are ordered (Re, Im) per bus, so each complex load of S becomes one
 // 4-byte LDS write and each complex voltage two adjacent outputs; the output layer goes
 // through LDS as FP32, half a tile at a time in the activations' bytes, so that the
