@@ -569,18 +569,39 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
             __syncthreads();
             buf ^= 1;
         }
-        // lane group g holds rows 4g..4g+3 of each 16-row tile: Re/Im of two buses
+        // lane group g holds rows 4g..4g+3 of each 16-row tile: Re/Im of two buses.  All of
+        // the lane's state loads are issued before its first store: behind stores to
+        // addresses the compiler cannot tell apart they would go out one at a time.
+        long long cb[4];
+        int phb[4];
+        float invb[4];
+        float2 oldv[4][4][2];
     #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int ac = c0 + wc + 16 * b + j;
             const bool live = ac < nact;
-            const long long c = live ? act[ac] : 0;
-            int ph = 0;
-            float inv = 1.f;
+            cb[b] = live ? act[ac] : -1;
+            phb[b] = 0;
+            invb[b] = 1.f;
             if (live) {
-                ph = ms[c].ph;
-                inv = ms[c].inv;
+                phb[b] = ms[cb[b]].ph;
+                invb[b] = ms[cb[b]].inv;
             }
+    #pragma unroll
+            for (int a = 0; a < 4; ++a)
+    #pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int bus = (r0 + wr + 16 * a + 4 * g + 2 * h) >> 1;
+                    oldv[b][a][h] = make_float2(0.f, 0.f);
+                    if (live && bus < n) oldv[b][a][h] = *reinterpret_cast<const float2 *>(U + 2 * (cb[b] * n + bus));
+                }
+        }
+    #pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const bool live = cb[b] >= 0;
+            const long long c = live ? cb[b] : 0;
+            const int ph = phb[b];
+            const float inv = invb[b];
             float emax = 0.f, umx = 0.f;
             int bad = 0;
     #pragma unroll
@@ -589,8 +610,7 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
                 for (int h = 0; h < 2; ++h) {
                     const int bus = (r0 + wr + 16 * a + 4 * g + 2 * h) >> 1;
                     if (live && bus < n) {
-                        float2 *up = reinterpret_cast<float2 *>(U + 2 * (c * n + bus));
-                        const float2 old = *up;
+                        const float2 old = oldv[b][a][h];
                         const float pr = acc[a][b][2 * h] * inv, pi = acc[a][b][2 * h + 1] * inv;
                         const float nr = ph ? old.x + pr : pr, ni = ph ? old.y + pi : pi;
                         const float dr = nr - old.x, di = ni - old.y;
@@ -598,7 +618,7 @@ __global__ __launch_bounds__(256) void gemm_low_kernel(const uint16_t *__restric
                         bad |= !(e2 < HUGE_VALF);
                         emax = e2 > emax ? e2 : emax;
                         umx = fmaxf(umx, fmaxf(fabsf(nr), fabsf(ni)));
-                        *up = make_float2(nr, ni);
+                        *reinterpret_cast<float2 *>(U + 2 * (c * n + bus)) = make_float2(nr, ni);
                     }
                 }
             }
